@@ -1,0 +1,666 @@
+/*
+ * lbm_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU reference of the lattice update studied in
+ * Han, Ooka & Kikumoto, "A wall function approach in lattice Boltzmann
+ * method: algorithm and validation using turbulent channel flow"
+ * (arXiv 2009.04352).  It exists so that the GPU library can be checked
+ * against something written independently from the paper; it shares no
+ * code, header, table or helper with the GPU library and must never be
+ * called from the product path (only from tests, the smoke check and the
+ * CPU-baseline leg of the benchmark).
+ *
+ * What one time step computes, for every cell c = (x, y, z) of an
+ * nx * ny * nz channel (x, z periodic; walls below y = 0 and above
+ * y = ny - 1, halfway between the last cell and its missing neighbour):
+ *
+ *   1. gather   f_a(c) = fpost_a(c - e_a)                         (Eq. 1)
+ *               wall-crossing links: bounce-back (Eq. 3, 3-D form) or
+ *               mirror reflection (free-slip, Eq. 4, 3-D form).
+ *   2. WFB      at wall cells, Spalding's law (Eq. 16-17) solved by Newton
+ *               for u_tau, tau_w split along the wall velocity (Eq. 15),
+ *               and the four reflected diagonal populations shifted by
+ *               +-tau/2 (Eq. 13-14).
+ *   3. moments  rho, u (Eq. 2), with the half-force velocity shift.
+ *   4. SGS      Smagorinsky eddy viscosity (Cs, Sec. 3.1) from the local
+ *               non-equilibrium stress.
+ *   5. collide  BGK towards the second-order equilibrium, plus the body
+ *               force term F_a of Eq. 1.
+ *
+ * Readings of points the paper leaves open (all are listed with reasons in
+ * the project's design notes):
+ *   - walls are link-wise (halfway); WFB acts on the first fluid layer;
+ *   - y1 (distance used in y+) is a parameter, default one lattice spacing;
+ *   - the velocity fed to Spalding's law is the free-slip (gathered)
+ *     tangential velocity, including the half-force shift;
+ *   - Newton starts from the viscous-sublayer guess u_tau = sqrt(nu U / y1)
+ *     and stops on a relative step below newton_tol;
+ *   - U = 0 gives tau_w = 0;
+ *   - the top wall is the bottom wall mirrored in y;
+ *   - collision is single-relaxation-time (BGK); the Smagorinsky closure is
+ *     tau_e = (tau0 + sqrt(tau0^2 + 18 Cs^2 Q / rho)) / 2 with
+ *     Q = sqrt(2 Pi:Pi), Pi the non-equilibrium second moment;
+ *   - F_a is the Guo et al. (2002) force term with u = (sum e f + F/2)/rho.
+ *
+ * Arithmetic is IEEE FP64 throughout, summation order a = 0..18, built
+ * with -ffp-contract=off.  Populations are stored as full f (not f - w).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* Discrete velocities of D3Q19 in the paper's numbering (Table A-1). */
+static const int E[Q][3] = {
+    {0, 0, 0},                            /* 0 */
+    {1, 0, 0},   {-1, 0, 0},              /* 1, 2 */
+    {0, 1, 0},   {0, -1, 0},              /* 3, 4 */
+    {0, 0, 1},   {0, 0, -1},              /* 5, 6 */
+    {1, 1, 0},   {-1, -1, 0},             /* 7, 8 */
+    {1, 0, 1},   {-1, 0, -1},             /* 9, 10 */
+    {0, 1, 1},   {0, -1, -1},             /* 11, 12 */
+    {1, -1, 0},  {-1, 1, 0},              /* 13, 14 */
+    {1, 0, -1},  {-1, 0, 1},              /* 15, 16 */
+    {0, 1, -1},  {0, -1, 1},              /* 17, 18 */
+};
+
+static double W[Q];  /* weights, Qian et al. (1992): 1/3, 1/18, 1/36 by |e|^2 */
+static int OPP[Q];   /* e_opp(a) = -e_a */
+static int MIR[Q];   /* e_mir(a) = (e_ax, -e_ay, e_az): reflection in the wall */
+static int tables_ready = 0;
+
+static void tables_init(void)
+{
+    if (tables_ready) return;
+    for (int a = 0; a < Q; ++a) {
+        int n2 = E[a][0] * E[a][0] + E[a][1] * E[a][1] + E[a][2] * E[a][2];
+        W[a] = (n2 == 0) ? 1.0 / 3.0 : (n2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0;
+        OPP[a] = -1;
+        MIR[a] = -1;
+        for (int b = 0; b < Q; ++b) {
+            if (E[b][0] == -E[a][0] && E[b][1] == -E[a][1] && E[b][2] == -E[a][2]) OPP[a] = b;
+            if (E[b][0] == E[a][0] && E[b][1] == -E[a][1] && E[b][2] == E[a][2]) MIR[a] = b;
+        }
+    }
+    tables_ready = 1;
+}
+
+enum { ORC_BB = 0, ORC_WFB = 1, ORC_FREESLIP = 2 };
+enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_NONFINITE = -5, ORC_E_NEWTON = -6 };
+
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t bc;          /* ORC_BB, ORC_WFB or ORC_FREESLIP */
+    double tau0;         /* molecular relaxation time, nu0 = (tau0 - 1/2) / 3 */
+    double cs;           /* Smagorinsky constant */
+    double kappa, bconst;/* Spalding's law constants */
+    double fx;           /* body force density along x */
+    double y1;           /* wall distance of the first fluid layer in y+ */
+    double newton_tol;   /* relative step that ends Newton */
+    int32_t newton_maxit;
+    int32_t stats_every; /* sample statistics on steps t with t % every == 0; 0 = off */
+} orc_params;
+
+typedef struct {
+    orc_params p;
+    int64_t ncell;
+    double *fpost, *fnew;   /* [a][z][y][x], post-collision populations */
+    int64_t steps;
+    int status;
+    int64_t first_bad_step;
+    int32_t max_newton_iters;
+    double *stats;          /* [y][8]: sums of ux uy uz ux^2 uy^2 uz^2 ux*uy, count */
+    int64_t nsamples;
+} orc;
+
+/* ---------------------------------------------------------------- tables */
+
+void orc_tables(int32_t* e, double* w, int32_t* opp, int32_t* mir)
+{
+    tables_init();
+    for (int a = 0; a < Q; ++a) {
+        for (int d = 0; d < 3; ++d) e[3 * a + d] = E[a][d];
+        w[a] = W[a];
+        opp[a] = OPP[a];
+        mir[a] = MIR[a];
+    }
+}
+
+/* ------------------------------------------------------- Spalding's law */
+
+/* Eq. 16: y+ as an explicit function of u+. */
+double orc_spalding_yplus(double up, double kappa, double b)
+{
+    double k = kappa * up;
+    return up + exp(-kappa * b) * (exp(k) - 1.0 - k - k * k / 2.0 - k * k * k / 6.0);
+}
+
+/* Invert Eq. 16 for u+ at a given y+ by bisection on [0, y+] (Sp(p) >= p).
+ * Used for the initial profile and for workload parameters only. */
+double orc_spalding_uplus(double yplus, double kappa, double b)
+{
+    if (!(yplus > 0.0)) return 0.0;
+    double lo = 0.0, hi = yplus;
+    for (int i = 0; i < 200; ++i) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (orc_spalding_yplus(mid, kappa, b) < yplus) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Wall-function Newton solve (Sec. 2.3).  With y+ = y1 u_tau / nu and
+ * u+ = U / u_tau (Eq. 17), writing p = u+ and R = y1 U / nu turns Eq. 16
+ * into H(p) = p Sp(p) - R = 0.  Start: viscous sublayer u+ = y+, i.e.
+ * u_tau = sqrt(nu U / y1), p0 = sqrt(R).  Returns u_tau, or -1 on failure. */
+double orc_wall_utau(double U, double y1, double nu, double kappa, double b,
+                     double tol, int maxit, int32_t* iters_out)
+{
+    if (iters_out) *iters_out = 0;
+    if (U == 0.0) return 0.0;
+    double R = y1 * U / nu;
+    double p = sqrt(R);
+    double ekb = exp(-kappa * b);
+    for (int it = 1; it <= maxit; ++it) {
+        double k = kappa * p;
+        double ek = exp(k);
+        double sp = p + ekb * (ek - 1.0 - k - k * k / 2.0 - k * k * k / 6.0);
+        double dsp = 1.0 + kappa * ekb * (ek - 1.0 - k - k * k / 2.0);
+        double h = p * sp - R;
+        double dh = sp + p * dsp;
+        double pn = p - h / dh;
+        if (iters_out) *iters_out = it;
+        if (fabs(pn - p) <= tol * pn) return U / pn;
+        p = pn;
+    }
+    return -1.0;
+}
+
+/* ------------------------------------------------------ one-cell pieces */
+
+/* Second-order equilibrium (Qian et al. 1992), c_s^2 = 1/3. */
+static double feq(int a, double rho, const double u[3])
+{
+    double eu = E[a][0] * u[0] + E[a][1] * u[1] + E[a][2] * u[2];
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return W[a] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+void orc_feq(double rho, const double* u, double* out)
+{
+    tables_init();
+    for (int a = 0; a < Q; ++a) out[a] = feq(a, rho, u);
+}
+
+/* Eq. 2 with the half-force shift: rho = sum f, rho u = sum e f + F/2. */
+static void moments(const double f[Q], double fx, double* rho, double u[3])
+{
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < Q; ++a) {
+        r += f[a];
+        for (int d = 0; d < 3; ++d) j[d] += E[a][d] * f[a];
+    }
+    j[0] += 0.5 * fx;
+    *rho = r;
+    for (int d = 0; d < 3; ++d) u[d] = j[d] / r;
+}
+
+/* WFB correction of the gathered populations of one wall cell, Eqs. 13-17.
+ * wall = 0: bottom (wall below, +y into the flow, the paper's setting);
+ * wall = 1: top (the bottom case mirrored in y).
+ * rec (may be NULL) receives tau_x, tau_z, u_tau, U. */
+int orc_wfb_cell(const orc_params* p, int wall, double f[Q], double rec[4], int32_t* iters)
+{
+    tables_init();
+    double rho = 0.0, jx = 0.0, jz = 0.0;
+    for (int a = 0; a < Q; ++a) {
+        rho += f[a];
+        jx += E[a][0] * f[a];
+        jz += E[a][2] * f[a];
+    }
+    jx += 0.5 * p->fx;
+    double vx = jx / rho, vz = jz / rho;          /* free-slip velocity v, Eq. 7-10 */
+    double U = sqrt(vx * vx + vz * vz);
+    double taux = 0.0, tauz = 0.0, utau = 0.0;
+    int32_t it = 0;
+    if (U > 0.0) {
+        double nu0 = (p->tau0 - 0.5) / 3.0;
+        utau = orc_wall_utau(U, p->y1, nu0, p->kappa, p->bconst, p->newton_tol,
+                             p->newton_maxit, &it);
+        if (utau < 0.0) {
+            if (iters) *iters = it;
+            return ORC_E_NEWTON;
+        }
+        double tauw = rho * utau * utau;           /* Eq. 17 */
+        taux = -(vx / U) * tauw;                   /* Eq. 15 */
+        tauz = -(vz / U) * tauw;
+    }
+    /* Eq. 13 (dt = dy = 1): the in-pointing diagonals of the bottom wall are
+     * 7 and 14 (x) and 11 and 17 (z); the top wall uses their mirror images. */
+    int a7 = 7, a14 = 14, a11 = 11, a17 = 17;
+    if (wall == 1) { a7 = MIR[7]; a14 = MIR[14]; a11 = MIR[11]; a17 = MIR[17]; }
+    f[a7] += 0.5 * taux;
+    f[a14] -= 0.5 * taux;
+    f[a11] += 0.5 * tauz;
+    f[a17] -= 0.5 * tauz;
+    if (rec) { rec[0] = taux; rec[1] = tauz; rec[2] = utau; rec[3] = U; }
+    if (iters) *iters = it;
+    return ORC_OK;
+}
+
+/* BGK + Smagorinsky + body force on gathered (and WFB-corrected) f.
+ * out receives the post-collision populations; taue_out (may be NULL) the
+ * effective relaxation time. */
+void orc_collide_cell(const orc_params* p, const double f[Q], double out[Q], double* taue_out)
+{
+    tables_init();
+    double rho, u[3], fe[Q];
+    moments(f, p->fx, &rho, u);
+    for (int a = 0; a < Q; ++a) fe[a] = feq(a, rho, u);
+    double pi[3][3] = {{0}};
+    for (int a = 0; a < Q; ++a)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) pi[i][j] += E[a][i] * E[a][j] * (f[a] - fe[a]);
+    double pp = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) pp += pi[i][j] * pi[i][j];
+    double qn = sqrt(2.0 * pp);
+    double taue = 0.5 * (p->tau0 + sqrt(p->tau0 * p->tau0 + 18.0 * p->cs * p->cs * qn / rho));
+    double fvec[3] = {p->fx, 0.0, 0.0};
+    for (int a = 0; a < Q; ++a) {
+        double eu = E[a][0] * u[0] + E[a][1] * u[1] + E[a][2] * u[2];
+        double ef = E[a][0] * fvec[0] + E[a][1] * fvec[1] + E[a][2] * fvec[2];
+        double emuf = (E[a][0] - u[0]) * fvec[0] + (E[a][1] - u[1]) * fvec[1] + (E[a][2] - u[2]) * fvec[2];
+        double force = (1.0 - 1.0 / (2.0 * taue)) * W[a] * (3.0 * emuf + 9.0 * eu * ef);
+        out[a] = f[a] - (f[a] - fe[a]) / taue + force;
+    }
+    if (taue_out) *taue_out = taue;
+}
+
+/* ------------------------------------------------------------ gathering */
+
+/* A source of post-collision populations: either a stored array or the
+ * analytic initial state (used to check single cells of huge grids). */
+typedef struct {
+    const orc_params* p;
+    const double* fpost;  /* if non-NULL: [a][z][y][x] */
+    /* analytic initial state */
+    const double* profile;/* [y] streamwise velocity of the initial profile */
+    double noise;
+    uint64_t seed;
+} src_t;
+
+static int64_t cell_index(const orc_params* p, int x, int y, int z)
+{
+    return (int64_t)x + (int64_t)p->nx * ((int64_t)y + (int64_t)p->ny * (int64_t)z);
+}
+
+/* splitmix64 (Steele, Lea & Flood 2014): output k (k = 0, 1, ...) of the
+ * generator whose state starts at seed. */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double uniform01(uint64_t seed, uint64_t k)
+{
+    return (double)(splitmix64_at(seed, k) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+/* Initial velocity of a cell: profile value times (1 + d0, d1, d2) with
+ * d_i uniform in [-noise, noise), drawn from counter 3 * cell + i. */
+static void initial_velocity(const src_t* s, int x, int y, int z, double u[3])
+{
+    uint64_t c = (uint64_t)cell_index(s->p, x, y, z);
+    double up = s->profile[y];
+    double d[3];
+    for (int i = 0; i < 3; ++i) d[i] = s->noise * (2.0 * uniform01(s->seed, 3u * c + (uint64_t)i) - 1.0);
+    u[0] = up * (1.0 + d[0]);
+    u[1] = up * d[1];
+    u[2] = up * d[2];
+}
+
+static double src_get(const src_t* s, int a, int x, int y, int z)
+{
+    if (s->fpost) return s->fpost[(int64_t)a * ((int64_t)s->p->nx * s->p->ny * s->p->nz) + cell_index(s->p, x, y, z)];
+    double u[3];
+    initial_velocity(s, x, y, z, u);
+    return feq(a, 1.0, u);
+}
+
+static int wrap(int i, int n) { return ((i % n) + n) % n; }
+
+/* Streaming by pull (Eq. 1) with the wall rules for links that cross a wall:
+ * BB: the population returns on its own link (Eq. 3 in 3-D form);
+ * WFB / free-slip: the wall-normal population is bounced back, the
+ * diagonal ones are mirror images from the in-plane neighbour (Eq. 4 in
+ * 3-D form; pairs 7-13, 14-8, 11-18, 17-12 as listed with Eq. 14). */
+static void gather(const src_t* s, int x, int y, int z, double f[Q])
+{
+    const orc_params* p = s->p;
+    for (int a = 0; a < Q; ++a) {
+        int sx = wrap(x - E[a][0], p->nx);
+        int sy = y - E[a][1];
+        int sz = wrap(z - E[a][2], p->nz);
+        if (sy >= 0 && sy < p->ny) {
+            f[a] = src_get(s, a, sx, sy, sz);
+        } else if (p->bc == ORC_BB || (E[a][0] == 0 && E[a][2] == 0)) {
+            f[a] = src_get(s, OPP[a], x, y, z);
+        } else {
+            f[a] = src_get(s, MIR[a], sx, y, sz);
+        }
+    }
+}
+
+static int wall_of_row(const orc_params* p, int y)
+{
+    if (y == 0) return 0;
+    if (y == p->ny - 1) return 1;
+    return -1;
+}
+
+/* Gather + WFB (when active) at one cell: the "pre-collision state". */
+static int precollision(const src_t* s, int x, int y, int z, double f[Q], double rec[4], int32_t* iters)
+{
+    const orc_params* p = s->p;
+    gather(s, x, y, z, f);
+    if (rec) rec[0] = rec[1] = rec[2] = rec[3] = 0.0;
+    if (iters) *iters = 0;
+    int w = wall_of_row(p, y);
+    if (p->bc == ORC_WFB && w >= 0) {
+        if (p->ny == 1) return ORC_E_ARG;
+        return orc_wfb_cell(p, w, f, rec, iters);
+    }
+    return ORC_OK;
+}
+
+/* ----------------------------------------------------------- the object */
+
+static int params_ok(const orc_params* p)
+{
+    if (p->nx < 1 || p->ny < 2 || p->nz < 1) return 0;
+    if (!(p->tau0 > 0.5) || !(p->cs >= 0.0) || !(p->kappa > 0.0)) return 0;
+    if (!isfinite(p->tau0) || !isfinite(p->cs) || !isfinite(p->kappa) || !isfinite(p->bconst)) return 0;
+    if (!isfinite(p->fx) || !(p->y1 > 0.0) || !(p->newton_tol > 0.0) || p->newton_maxit < 1) return 0;
+    if (p->bc < 0 || p->bc > 2 || p->stats_every < 0) return 0;
+    return 1;
+}
+
+orc* orc_create(const orc_params* p)
+{
+    tables_init();
+    if (!params_ok(p)) return NULL;
+    orc* o = (orc*)calloc(1, sizeof(orc));
+    if (!o) return NULL;
+    o->p = *p;
+    o->ncell = (int64_t)p->nx * p->ny * p->nz;
+    o->fpost = (double*)calloc((size_t)(Q * o->ncell), sizeof(double));
+    o->fnew = (double*)calloc((size_t)(Q * o->ncell), sizeof(double));
+    o->stats = (double*)calloc((size_t)p->ny * 8, sizeof(double));
+    if (!o->fpost || !o->fnew || !o->stats) {
+        free(o->fpost); free(o->fnew); free(o->stats); free(o);
+        return NULL;
+    }
+    o->first_bad_step = -1;
+    return o;
+}
+
+void orc_destroy(orc* o)
+{
+    if (!o) return;
+    free(o->fpost);
+    free(o->fnew);
+    free(o->stats);
+    free(o);
+}
+
+int orc_set_param_bc(orc* o, int32_t bc)
+{
+    if (bc < 0 || bc > 2) return ORC_E_ARG;
+    o->p.bc = bc;
+    return ORC_OK;
+}
+
+void orc_set_state(orc* o, const double* fpost) { memcpy(o->fpost, fpost, sizeof(double) * Q * o->ncell); }
+void orc_get_state(const orc* o, double* fpost) { memcpy(fpost, o->fpost, sizeof(double) * Q * o->ncell); }
+int64_t orc_steps(const orc* o) { return o->steps; }
+int32_t orc_max_newton_iters(const orc* o) { return o->max_newton_iters; }
+int64_t orc_first_bad_step(const orc* o) { return o->first_bad_step; }
+
+/* Streamwise velocity of the initial profile per layer: Spalding's law at
+ * distance d_y = min(y, ny - 1 - y) + y1 from the nearer wall. */
+static void initial_profile(const orc_params* p, double u_tau, double* prof)
+{
+    double nu0 = (p->tau0 - 0.5) / 3.0;
+    for (int y = 0; y < p->ny; ++y) {
+        int dy = y < p->ny - 1 - y ? y : p->ny - 1 - y;
+        double d = (double)dy + p->y1;
+        prof[y] = u_tau * orc_spalding_uplus(d * u_tau / nu0, p->kappa, p->bconst);
+    }
+}
+
+void orc_initial_profile(const orc_params* p, double u_tau, double* prof) { initial_profile(p, u_tau, prof); }
+
+/* fpost(0) = f_eq(1, u0): Spalding profile plus seeded uniform noise. */
+int orc_init_spalding(orc* o, double u_tau, double noise, uint64_t seed)
+{
+    const orc_params* p = &o->p;
+    double* prof = (double*)malloc(sizeof(double) * p->ny);
+    if (!prof) return ORC_E_ARG;
+    initial_profile(p, u_tau, prof);
+    src_t s = {p, NULL, prof, noise, seed};
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t c = cell_index(p, x, y, z);
+                double u[3];
+                initial_velocity(&s, x, y, z, u);
+                for (int a = 0; a < Q; ++a) o->fpost[(int64_t)a * o->ncell + c] = feq(a, 1.0, u);
+            }
+    free(prof);
+    o->steps = 0;
+    o->status = ORC_OK;
+    o->first_bad_step = -1;
+    return ORC_OK;
+}
+
+/* Full update of one cell from a source of post-collision populations. */
+static int cell_update(const src_t* s, int x, int y, int z, double out[Q], double mom[4], int32_t* iters)
+{
+    double f[Q];
+    int st = precollision(s, x, y, z, f, NULL, iters);
+    if (st != ORC_OK) return st;
+    double rho, u[3];
+    moments(f, s->p->fx, &rho, u);
+    if (mom) { mom[0] = rho; mom[1] = u[0]; mom[2] = u[1]; mom[3] = u[2]; }
+    if (!(rho > 0.0) || !isfinite(rho)) return ORC_E_NONFINITE;
+    orc_collide_cell(s->p, f, out, NULL);
+    return ORC_OK;
+}
+
+int orc_step(orc* o, int64_t n)
+{
+    const orc_params* p = &o->p;
+    const int64_t nc = o->ncell;
+    for (int64_t t = 0; t < n; ++t) {
+        const int64_t step = o->steps + 1;
+        const int sample = p->stats_every > 0 && (step % p->stats_every) == 0;
+        src_t s = {p, o->fpost, NULL, 0.0, 0};
+        int bad = 0;
+        int32_t maxit = o->max_newton_iters;
+        double* srow = NULL;
+        if (sample) {
+            srow = (double*)calloc((size_t)p->nz * p->ny * 7, sizeof(double));
+            if (!srow) return ORC_E_ARG;
+        }
+#pragma omp parallel for schedule(static) reduction(| : bad) reduction(max : maxit)
+        for (int z = 0; z < p->nz; ++z) {
+            for (int y = 0; y < p->ny; ++y) {
+                for (int x = 0; x < p->nx; ++x) {
+                    double out[Q], mom[4];
+                    int32_t it = 0;
+                    int st = cell_update(&s, x, y, z, out, mom, &it);
+                    if (it > maxit) maxit = it;
+                    if (st != ORC_OK) {
+                        bad |= (st == ORC_E_NEWTON) ? 2 : 1;
+                        for (int a = 0; a < Q; ++a) out[a] = NAN;
+                    }
+                    int64_t c = cell_index(p, x, y, z);
+                    for (int a = 0; a < Q; ++a) o->fnew[(int64_t)a * nc + c] = out[a];
+                    if (sample) {
+                        double* r = srow + 7 * ((int64_t)z * p->ny + y);
+                        r[0] += mom[1]; r[1] += mom[2]; r[2] += mom[3];
+                        r[3] += mom[1] * mom[1]; r[4] += mom[2] * mom[2]; r[5] += mom[3] * mom[3];
+                        r[6] += mom[1] * mom[2];
+                    }
+                }
+            }
+        }
+        if (sample) {
+            for (int y = 0; y < p->ny; ++y) {
+                for (int z = 0; z < p->nz; ++z)
+                    for (int k = 0; k < 7; ++k) o->stats[8 * y + k] += srow[7 * ((int64_t)z * p->ny + y) + k];
+                o->stats[8 * y + 7] += (double)p->nx * p->nz;
+            }
+            o->nsamples += 1;
+            free(srow);
+        }
+        o->max_newton_iters = maxit;
+        double* tmp = o->fpost; o->fpost = o->fnew; o->fnew = tmp;
+        o->steps = step;
+        if (bad) {
+            if (o->first_bad_step < 0) o->first_bad_step = step;
+            o->status = (bad & 2) ? ORC_E_NEWTON : ORC_E_NONFINITE;
+            return o->status;
+        }
+    }
+    return ORC_OK;
+}
+
+/* Observables of the current state (steps 1-3 applied to fpost, no write):
+ * rho, ux, uy, uz per cell (any pointer may be NULL). */
+int orc_observe(const orc* o, double* rho, double* ux, double* uy, double* uz)
+{
+    const orc_params* p = &o->p;
+    src_t s = {p, o->fpost, NULL, 0.0, 0};
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int z = 0; z < p->nz; ++z)
+        for (int y = 0; y < p->ny; ++y)
+            for (int x = 0; x < p->nx; ++x) {
+                double f[Q], r, u[3];
+                if (precollision(&s, x, y, z, f, NULL, NULL) != ORC_OK) bad = 1;
+                moments(f, p->fx, &r, u);
+                int64_t c = cell_index(p, x, y, z);
+                if (rho) rho[c] = r;
+                if (ux) ux[c] = u[0];
+                if (uy) uy[c] = u[1];
+                if (uz) uz[c] = u[2];
+            }
+    return bad ? ORC_E_NEWTON : ORC_OK;
+}
+
+/* Wall records of the current state, layout [w][z][x] with w = 0 bottom,
+ * 1 top.  WFB: tau_x, tau_z, u_tau, U of the WFB correction the next step
+ * applies.  BB: force on the fluid by momentum exchange (the change of
+ * momentum of the reflected populations), u_tau = sqrt(|tau| / rho).
+ * Free-slip: zeros, U the tangential speed. */
+int orc_wall(const orc* o, double* taux, double* tauz, double* utau, double* uu)
+{
+    const orc_params* p = &o->p;
+    src_t s = {p, o->fpost, NULL, 0.0, 0};
+    for (int w = 0; w < 2; ++w) {
+        int y = (w == 0) ? 0 : p->ny - 1;
+        for (int z = 0; z < p->nz; ++z)
+            for (int x = 0; x < p->nx; ++x) {
+                double f[Q], rec[4];
+                int64_t k = (int64_t)w * p->nx * p->nz + (int64_t)z * p->nx + x;
+                if (precollision(&s, x, y, z, f, rec, NULL) != ORC_OK) return ORC_E_NEWTON;
+                double r, u[3];
+                moments(f, p->fx, &r, u);
+                if (p->bc == ORC_BB) {
+                    /* every population leaving the cell through the wall comes back
+                     * reversed: momentum change -2 e_b fpost_b */
+                    double tx = 0.0, tz = 0.0;
+                    int64_t c = cell_index(p, x, y, z);
+                    for (int b = 0; b < Q; ++b) {
+                        int dy = y + E[b][1];
+                        if (dy >= 0 && dy < p->ny) continue;
+                        double fb = o->fpost[(int64_t)b * o->ncell + c];
+                        tx += -2.0 * E[b][0] * fb;
+                        tz += -2.0 * E[b][2] * fb;
+                    }
+                    rec[0] = tx; rec[1] = tz;
+                    rec[2] = sqrt(sqrt(tx * tx + tz * tz) / r);
+                    rec[3] = sqrt(u[0] * u[0] + u[2] * u[2]);
+                } else if (p->bc == ORC_FREESLIP) {
+                    rec[0] = rec[1] = rec[2] = 0.0;
+                    rec[3] = sqrt(u[0] * u[0] + u[2] * u[2]);
+                }
+                if (taux) taux[k] = rec[0];
+                if (tauz) tauz[k] = rec[1];
+                if (utau) utau[k] = rec[2];
+                if (uu) uu[k] = rec[3];
+            }
+    }
+    return ORC_OK;
+}
+
+void orc_stats_sums(const orc* o, double* out, int64_t* nsamples)
+{
+    memcpy(out, o->stats, sizeof(double) * 8 * o->p.ny);
+    if (nsamples) *nsamples = o->nsamples;
+}
+
+void orc_stats_reset(orc* o)
+{
+    memset(o->stats, 0, sizeof(double) * 8 * o->p.ny);
+    o->nsamples = 0;
+}
+
+/* --------------------------------------- single cells of the initial state */
+
+/* Initial state, one step and observables at selected cells of a grid too
+ * large to hold twice, computed from the analytic initial state. */
+int orc_init_cells(const orc_params* p, double u_tau, double noise, uint64_t seed,
+                   int64_t n, const int64_t* cells, double* fpost_out /* [n][19] */)
+{
+    tables_init();
+    if (!params_ok(p)) return ORC_E_ARG;
+    double* prof = (double*)malloc(sizeof(double) * p->ny);
+    if (!prof) return ORC_E_ARG;
+    initial_profile(p, u_tau, prof);
+    src_t s = {p, NULL, prof, noise, seed};
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = cells[i];
+        int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((int64_t)p->nx * p->ny));
+        for (int a = 0; a < Q; ++a) fpost_out[Q * i + a] = src_get(&s, a, x, y, z);
+    }
+    free(prof);
+    return ORC_OK;
+}
+
+int orc_step1_cells(const orc_params* p, double u_tau, double noise, uint64_t seed,
+                    int64_t n, const int64_t* cells, double* fpost_out /* [n][19] */,
+                    double* mom_out /* [n][4]: observables of the initial state */)
+{
+    tables_init();
+    if (!params_ok(p)) return ORC_E_ARG;
+    double* prof = (double*)malloc(sizeof(double) * p->ny);
+    if (!prof) return ORC_E_ARG;
+    initial_profile(p, u_tau, prof);
+    src_t s = {p, NULL, prof, noise, seed};
+    int st = ORC_OK;
+    for (int64_t i = 0; i < n && st == ORC_OK; ++i) {
+        int64_t c = cells[i];
+        int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((int64_t)p->nx * p->ny));
+        st = cell_update(&s, x, y, z, fpost_out + Q * i, mom_out ? mom_out + 4 * i : NULL, NULL);
+    }
+    free(prof);
+    return st;
+}

@@ -1,0 +1,247 @@
+"""ctypes wrapper of the FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Only tests, the smoke check and the CPU-baseline leg of the benchmark may
+import this module.  It shares nothing with the GPU library; states are
+full populations f (not f - w) in the layout [a][z][y][x].
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+Q = 19
+BB, WFB, FREESLIP = 0, 1, 2
+OK, E_ARG, E_NONFINITE, E_NEWTON = 0, -1, -5, -6
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("bc", C.c_int32),
+        ("tau0", C.c_double), ("cs", C.c_double), ("kappa", C.c_double),
+        ("bconst", C.c_double), ("fx", C.c_double), ("y1", C.c_double),
+        ("newton_tol", C.c_double), ("newton_maxit", C.c_int32),
+        ("stats_every", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        PP = C.POINTER(Params)
+        L.orc_tables.argtypes = [i32p, dp, i32p, i32p]
+        L.orc_spalding_yplus.restype = C.c_double
+        L.orc_spalding_yplus.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_spalding_uplus.restype = C.c_double
+        L.orc_spalding_uplus.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_wall_utau.restype = C.c_double
+        L.orc_wall_utau.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int32)]
+        L.orc_feq.argtypes = [C.c_double, dp, dp]
+        L.orc_wfb_cell.restype = C.c_int
+        L.orc_wfb_cell.argtypes = [PP, C.c_int, dp, dp, C.POINTER(C.c_int32)]
+        L.orc_collide_cell.argtypes = [PP, dp, dp, C.POINTER(C.c_double)]
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [PP]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_param_bc.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_set_state.argtypes = [C.c_void_p, dp]
+        L.orc_get_state.argtypes = [C.c_void_p, dp]
+        L.orc_steps.restype = C.c_int64
+        L.orc_steps.argtypes = [C.c_void_p]
+        L.orc_max_newton_iters.restype = C.c_int32
+        L.orc_max_newton_iters.argtypes = [C.c_void_p]
+        L.orc_first_bad_step.restype = C.c_int64
+        L.orc_first_bad_step.argtypes = [C.c_void_p]
+        L.orc_initial_profile.argtypes = [PP, C.c_double, dp]
+        L.orc_init_spalding.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint64]
+        L.orc_step.restype = C.c_int
+        L.orc_step.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_observe.restype = C.c_int
+        L.orc_observe.argtypes = [C.c_void_p, dp, dp, dp, dp]
+        L.orc_wall.restype = C.c_int
+        L.orc_wall.argtypes = [C.c_void_p, dp, dp, dp, dp]
+        L.orc_stats_sums.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
+        L.orc_stats_reset.argtypes = [C.c_void_p]
+        L.orc_init_cells.restype = C.c_int
+        L.orc_init_cells.argtypes = [PP, C.c_double, C.c_double, C.c_uint64, C.c_int64, ip, dp]
+        L.orc_step1_cells.restype = C.c_int
+        L.orc_step1_cells.argtypes = [PP, C.c_double, C.c_double, C.c_uint64, C.c_int64, ip, dp, dp]
+        _lib = L
+    return _lib
+
+
+def tables():
+    """(e [19,3] int, w [19], opp [19], mirror_y [19]) as the oracle holds them."""
+    e = np.zeros(57, np.int32)
+    w = np.zeros(19)
+    opp = np.zeros(19, np.int32)
+    mir = np.zeros(19, np.int32)
+    lib().orc_tables(e, w, opp, mir)
+    return e.reshape(19, 3), w, opp, mir
+
+
+def make_params(nx, ny, nz, tau0, cs=0.1, kappa=0.41, bconst=5.5, fx=0.0, bc=WFB,
+                y1=1.0, newton_tol=1e-14, newton_maxit=100, stats_every=0):
+    return Params(nx, ny, nz, bc, tau0, cs, kappa, bconst, fx, y1, newton_tol,
+                  newton_maxit, stats_every)
+
+
+def spalding_yplus(uplus, kappa=0.41, b=5.5):
+    return lib().orc_spalding_yplus(float(uplus), kappa, b)
+
+
+def spalding_uplus(yplus, kappa=0.41, b=5.5):
+    return lib().orc_spalding_uplus(float(yplus), kappa, b)
+
+
+def wall_utau(U, y1, nu, kappa=0.41, b=5.5, tol=1e-14, maxit=100):
+    it = C.c_int32(0)
+    ut = lib().orc_wall_utau(float(U), float(y1), float(nu), kappa, b, tol, maxit, C.byref(it))
+    return ut, it.value
+
+
+def feq(rho, u):
+    out = np.zeros(19)
+    lib().orc_feq(float(rho), np.ascontiguousarray(u, dtype=np.float64), out)
+    return out
+
+
+def wfb_cell(params, wall, f):
+    """Apply the WFB correction to a copy of f; returns (f_new, record, status, iters)."""
+    f = np.array(f, dtype=np.float64)
+    rec = np.zeros(4)
+    it = C.c_int32(0)
+    st = lib().orc_wfb_cell(C.byref(params), int(wall), f, rec, C.byref(it))
+    return f, rec, st, it.value
+
+
+def collide_cell(params, f):
+    out = np.zeros(19)
+    taue = C.c_double(0.0)
+    lib().orc_collide_cell(C.byref(params), np.ascontiguousarray(f, dtype=np.float64), out, C.byref(taue))
+    return out, taue.value
+
+
+def rule_m(ny, re_tau, ma, kappa=0.41, b=5.5, y1=1.0):
+    """Workload parameters for a channel of ny layers (D = ny / 2) at Re_tau
+    with centreline Mach number ma: returns dict(u_tau, nu0, tau0, fx, yplus1)."""
+    D = ny / 2.0
+    uc = ma / np.sqrt(3.0)
+    u_tau = uc / spalding_uplus(re_tau, kappa, b)
+    nu0 = u_tau * D / re_tau
+    return dict(u_tau=u_tau, nu0=nu0, tau0=0.5 + 3.0 * nu0, fx=u_tau * u_tau / D,
+                yplus1=y1 * u_tau / nu0)
+
+
+class Oracle:
+    """A channel held by the oracle (two FP64 population arrays)."""
+
+    def __init__(self, params):
+        self.params = params
+        self.shape = (params.nz, params.ny, params.nx)
+        self.ncell = params.nx * params.ny * params.nz
+        self._h = lib().orc_create(C.byref(params))
+        if not self._h:
+            raise ValueError("oracle: invalid parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def set_bc(self, bc):
+        self.params.bc = bc
+        lib().orc_set_param_bc(self._h, bc)
+
+    def set_state(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(19 * self.ncell)
+        lib().orc_set_state(self._h, f)
+
+    def state(self):
+        out = np.zeros(19 * self.ncell)
+        lib().orc_get_state(self._h, out)
+        return out.reshape((19,) + self.shape)
+
+    def init_spalding(self, u_tau, noise=0.05, seed=0):
+        lib().orc_init_spalding(self._h, float(u_tau), float(noise), int(seed))
+
+    def step(self, n=1):
+        return lib().orc_step(self._h, int(n))
+
+    @property
+    def steps(self):
+        return lib().orc_steps(self._h)
+
+    @property
+    def max_newton_iters(self):
+        return lib().orc_max_newton_iters(self._h)
+
+    @property
+    def first_bad_step(self):
+        return lib().orc_first_bad_step(self._h)
+
+    def observe(self):
+        """(rho, ux, uy, uz), each [nz, ny, nx]."""
+        outs = [np.zeros(self.ncell) for _ in range(4)]
+        st = lib().orc_observe(self._h, *outs)
+        if st != OK:
+            raise RuntimeError("oracle observe failed: %d" % st)
+        return tuple(o.reshape(self.shape) for o in outs)
+
+    def wall(self):
+        """(tau_x, tau_z, u_tau, U), each [2, nz, nx]."""
+        n = 2 * self.params.nx * self.params.nz
+        outs = [np.zeros(n) for _ in range(4)]
+        st = lib().orc_wall(self._h, *outs)
+        if st != OK:
+            raise RuntimeError("oracle wall failed: %d" % st)
+        return tuple(o.reshape(2, self.params.nz, self.params.nx) for o in outs)
+
+    def stats_sums(self):
+        out = np.zeros(8 * self.params.ny)
+        ns = C.c_int64(0)
+        lib().orc_stats_sums(self._h, out, C.byref(ns))
+        return out.reshape(self.params.ny, 8), ns.value
+
+    def stats_reset(self):
+        lib().orc_stats_reset(self._h)
+
+
+def initial_profile(params, u_tau):
+    out = np.zeros(params.ny)
+    lib().orc_initial_profile(C.byref(params), float(u_tau), out)
+    return out
+
+
+def init_cells(params, u_tau, noise, seed, cells):
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cells), 19))
+    st = lib().orc_init_cells(C.byref(params), float(u_tau), float(noise), int(seed), len(cells), cells, out.reshape(-1))
+    if st != OK:
+        raise RuntimeError("oracle init_cells failed: %d" % st)
+    return out
+
+
+def step1_cells(params, u_tau, noise, seed, cells):
+    """Post-collision populations after one step, and observables (rho, u) of
+    the initial state, at the given cell indices (x + nx (y + ny z))."""
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cells), 19))
+    mom = np.zeros((len(cells), 4))
+    st = lib().orc_step1_cells(C.byref(params), float(u_tau), float(noise), int(seed), len(cells), cells,
+                               out.reshape(-1), mom.reshape(-1))
+    if st != OK:
+        raise RuntimeError("oracle step1_cells failed: %d" % st)
+    return out, mom
