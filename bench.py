@@ -1,0 +1,227 @@
+"""Benchmark: MLUPS and HBM-roofline fraction of the fused WFB LBM-LES step on
+one MI355X, FP16 / FP32 / BF16 stores against the plain FP64 store, with the
+accuracy of each reduced store stated against the FP64 GPU run.
+
+Workload (default): the 512 x 128 x 256 channel (16.8M cells) at Re_tau 2003,
+WFB walls, Smagorinsky Cs = 0.1, started from the Spalding profile with 5 %
+seeded noise; synthetic inputs generated on the device.  One step is one
+launch of the fused kernel over every cell (odd and even AA kernels
+alternate).  Timing: W untimed warm-up steps, then K steps bracketed by
+synchronisation, a HIP event recorded on the library's stream after every
+launch (per-kernel durations for the roofline).  Prints one JSON line.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+                [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % of HBM roofline at 1 GPU, FP16/FP32-store vs FP64, at stated ε_u+"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+HEADLINE = "f16"
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lattice.h", "store.h", "lbm_internal.h"):
+        with open(os.path.join(ROOT, "paper_2009_04352_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, store, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source") != kernel_source_hash():
+        return None
+    rec = t.get("stores", {}).get(store, {}).get(kernel)
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def run_store(P, W, name, store, steps, warmup):
+    import numpy as np
+    import torch
+    p = W.params(name)
+    nx, ny, nz = p["grid"]
+    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
+                   tiles=W.LAUNCH_TILES[store], graph_steps=0)
+    ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
+    ch.step(warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(ch.stream)
+    for i in range(steps):
+        ch.step(1)
+        ev[i + 1].record(ch.stream)
+    torch.cuda.synchronize()
+    total_ms = ev[0].elapsed_time(ev[steps])
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    t_index = warmup + 1 + np.arange(steps)          # 1-based step numbers; odd ones run the odd kernel
+    odd_ms = float(per[t_index % 2 == 1].mean()) if np.any(t_index % 2 == 1) else float("nan")
+    even_ms = float(per[t_index % 2 == 0].mean()) if np.any(t_index % 2 == 0) else float("nan")
+    status, first_bad = ch.sync()
+    n = nx * ny * nz
+    out = dict(ms_per_step=total_ms / steps, mlups=n * steps / (total_ms * 1e-3) / 1e6,
+               odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status), first_bad_step=int(first_bad))
+    fields = None
+    if status == 0:
+        rho, ux, uy, uz = ch.moments()
+        fields = (ux, uy, uz)
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+    return out, fields, p
+
+
+def copy_probe_gbs(P, nbytes=4 << 30, reps=10):
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    s = torch.cuda.current_stream()
+    P.copy_probe(dst, src, nbytes, s)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        P.copy_probe(dst, src, nbytes, s)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(W, name, budget_s=15.0):
+    """The FP64 CPU oracle on this host's cores: a bounded sample of the same
+    workload (the same grid from the same initial state, a few steps)."""
+    from oracle import oracle as O
+    p = W.params(name)
+    nx, ny, nz = p["grid"]
+    o = O.Oracle(O.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=O.WFB))
+    o.init_spalding(p["u_tau"], p["noise"], p["seed"])
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(50, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    del o
+    return dict(value=nx * ny * nz * k / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample="%dx%dx%d channel, WFB, FP64, %d steps after one untimed step (%.1f s)" % (nx, ny, nz, k, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--stores", default="f64,f32,f16,bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the channel step runs on a single MI355X here; "
+              "multi-GPU slab decomposition is not part of this build (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2009_04352_amd as P
+    from paper_2009_04352_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    stores = args.stores.split(",")
+    if "f64" not in stores:
+        stores = ["f64"] + stores
+    wl = W.WORKLOADS[args.workload]
+    nx, ny, nz = wl["grid"]
+    n = nx * ny * nz
+
+    copy_gbs = None if args.no_copy_probe else copy_probe_gbs(P)
+    res, fields = {}, {}
+    for s in stores:
+        r, f, p = run_store(P, W, args.workload, s, args.steps, args.warmup)
+        print("[bench] %s: %.1f MLUPS, odd %.4f ms, even %.4f ms, status %d"
+              % (s, r["mlups"], r["odd_kernel_ms"], r["even_kernel_ms"], r["status"]), file=sys.stderr, flush=True)
+        res[s], fields[s] = r, f
+    u_tau = p["u_tau"]
+    ref = fields.get("f64")
+    per_store = {}
+    for s in stores:
+        r = res[s]
+        bytes_cell = 38 * STORE_BYTES[s]
+        kern = "odd" if r["odd_kernel_ms"] >= r["even_kernel_ms"] else "even"
+        kms = r[kern + "_kernel_ms"]
+        gbs = bytes_cell * n / (kms * 1e-3) / 1e9
+        d = dict(mlups=r["mlups"], ms_per_step=r["ms_per_step"], bytes_per_cell=bytes_cell,
+                 odd_kernel_ms=r["odd_kernel_ms"], even_kernel_ms=r["even_kernel_ms"],
+                 dominant_kernel=kern, kernel_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+                 status=r["status"])
+        if copy_gbs:
+            d["copy_frac"] = gbs / copy_gbs
+        if ref is not None and fields[s] is not None:
+            du = max(float(np.abs(a - b).max()) for a, b in zip(fields[s], ref))
+            prof = fields[s][0].mean(axis=(0, 2)) / u_tau
+            prof_ref = ref[0].mean(axis=(0, 2)) / u_tau
+            d["max_du_over_utau_vs_f64"] = du / u_tau
+            d["eps_uplus_vs_f64"] = float(math.sqrt(((prof - prof_ref) ** 2).sum() / (prof_ref ** 2).sum()))
+        d["mlups_gain_vs_f64"] = r["mlups"] / res["f64"]["mlups"]
+        per_store[s] = d
+
+    head = HEADLINE if HEADLINE in per_store else stores[-1]
+    hd = per_store[head]
+    kern = hd["dominant_kernel"]
+    kms = hd[kern + "_kernel_ms"]
+    traffic = measured_traffic(args.workload, head, kern)
+    roof = dict(bound="hbm", achieved=hd["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=hd["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
+                kernel=("k_step odd (pull/push, wall reflections)" if kern == "odd" else "k_step even (local)"),
+                kernel_ms=kms, algorithmic_bytes_per_launch=hd["bytes_per_cell"] * n)
+    line = {
+        "metric": METRIC,
+        "value": hd["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hd["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %s" % (args.workload, wl["desc"]), "grid": [nx, ny, nz], "store": head,
+                   "boundary": "wfb", "re_tau": wl["re_tau"], "tau0": p["tau0"], "fx": p["fx"],
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "per_store": per_store,
+        "copy_probe_gbs": copy_gbs,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(W, args.workload)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

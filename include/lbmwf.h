@@ -1,0 +1,197 @@
+/*
+ * lbmwf.h -- C ABI of the wall-function-bounce LBM-LES channel library.
+ *
+ * Method: Han, Ooka & Kikumoto, "A wall function approach in lattice
+ * Boltzmann method: algorithm and validation using turbulent channel flow"
+ * (arXiv 2009.04352).  One time step of a D3Q19 channel (x streamwise and
+ * periodic, y wall-normal with a wall below the first and above the last
+ * layer, z spanwise and periodic) is one fused GPU update:
+ *   streaming of Eq. 1 with wall reflections (bounce-back, Eq. 3 in 3-D form;
+ *   mirror reflection, Eq. 4 in 3-D form), the wall-function bounce (WFB)
+ *   correction of Eq. 13-15 with tau_w from Spalding's law (Eq. 16-17) solved
+ *   by Newton's method (Sec. 2.3), the moments of Eq. 2, a Smagorinsky eddy
+ *   viscosity (Sec. 3.1) and BGK relaxation with the body force term F_a of
+ *   Eq. 1.
+ *
+ * Units are lattice units: dx = dt = 1, reference density 1.  A population
+ * array is [a][z][y][x] with x fastest; cell index c = x + nx (y + ny z).
+ * Directions a = 0..18 follow Table A-1.
+ *
+ * Conventions for every function returning int:
+ *   - LBM_OK (0) on success, a negative LBM_E_* code otherwise;
+ *   - no exception, abort or exit ever crosses this boundary;
+ *   - output arrays are written only on success;
+ *   - a context is not thread-safe; distinct contexts are independent;
+ *   - device work is enqueued on the context's stream (lbm_set_stream) and is
+ *     asynchronous unless the function says it synchronises.
+ */
+#ifndef LBMWF_H
+#define LBMWF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LBM_OK 0
+#define LBM_E_ARG (-1)        /* an argument is out of range or a pointer is NULL */
+#define LBM_E_STATE (-2)      /* call not valid in the context's state (e.g. no storage bound) */
+#define LBM_E_OOM (-3)        /* a library-side allocation failed */
+#define LBM_E_DEVICE (-4)     /* a HIP runtime call failed; lbm_last_error() has its text */
+#define LBM_E_NONFINITE (-5)  /* a cell's density became non-finite or non-positive */
+#define LBM_E_NEWTON (-6)     /* the wall-function Newton solve hit its iteration cap */
+
+/* wall boundaries (Sec. 2.1-2.2) */
+#define LBM_BB 0        /* bounce-back, the no-slip comparison path (Eq. 3, 3-D form) */
+#define LBM_WFB 1       /* wall-function bounce (Eq. 14 with tau_w from Eq. 15-17) */
+#define LBM_FREESLIP 2  /* mirror reflection (Eq. 4, 3-D form): WFB with tau_w = 0 */
+
+/* storage formats of h_a = f_a - w_a */
+#define LBM_STORE_F64 0   /* FP64 storage, FP64 arithmetic */
+#define LBM_STORE_F32 1   /* FP32 storage, FP32 arithmetic (Newton in FP64) */
+#define LBM_STORE_F16 2   /* IEEE binary16 storage, FP32 arithmetic */
+#define LBM_STORE_BF16 3  /* bfloat16 storage, FP32 arithmetic */
+
+/* parameter keys for lbm_set_param / lbm_get_param */
+#define LBM_P_Y1 0            /* wall distance of the first layer in y+ = y1 u_tau / nu (default 1) */
+#define LBM_P_NEWTON_TOL 1    /* Newton stops when |p_{k+1} - p_k| <= tol p_{k+1} (default 1e-14) */
+#define LBM_P_NEWTON_MAXIT 2  /* Newton iteration cap (default 100) */
+#define LBM_P_STATS_EVERY 3   /* sample plane statistics on steps t with t % k == 0; 0 = off (default) */
+#define LBM_P_STORE 4         /* LBM_STORE_*; settable only before lbm_bind_storage (default F64) */
+#define LBM_P_TILE_ODD 5      /* cells per block of the odd-step kernel: 64, 128, 256 or 512 */
+#define LBM_P_TILE_EVEN 6     /* cells per block of the even-step kernel */
+#define LBM_P_XCD_REMAP 7     /* 1: contiguous tile ranges per XCD (default), 0: identity */
+#define LBM_P_GRAPH_STEPS 8   /* steps per captured HIP graph chunk; 0 = launch eagerly (default 32) */
+#define LBM_P_BC 9            /* read-only here: the current boundary */
+#define LBM_P_TAU0 10         /* read-only: molecular relaxation time */
+#define LBM_P_FX 11           /* body force density along x; settable at any time */
+#define LBM_P_CS 12           /* Smagorinsky constant; settable at any time */
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz;
+} lbm_grid;
+
+/* Creates a channel context (no device memory yet).
+ * g: grid with nx >= 1, ny >= 2, nz >= 1 and nx * ny * nz < 2^31.
+ * tau: molecular relaxation time, > 1/2; nu0 = (tau - 1/2) / 3 (BGK, Eq. 1).
+ * Cs: Smagorinsky constant >= 0 (Sec. 3.1; the paper uses 0.1).
+ * kappa, B: Spalding's law constants (Eq. 16; the paper uses 0.41 and 5.5).
+ * Fx: body force density along x (the F_a of Eq. 1), any finite value.
+ * On error returns LBM_E_ARG and leaves *out untouched.  Defaults: store F64,
+ * boundary WFB, y1 = 1, Newton tol 1e-14 and cap 100, statistics off. */
+int lbm_create(const lbm_grid* g, double tau, double Cs, double kappa, double B, double Fx, lbm_ctx** out);
+
+/* Frees the context and its library-side device buffers (never the bound storage). */
+void lbm_destroy(lbm_ctx* ctx);
+
+int lbm_set_param(lbm_ctx* ctx, int key, double value);
+int lbm_get_param(const lbm_ctx* ctx, int key, double* value);
+
+/* Bytes of device storage the caller must bind: 19 * nx * ny * nz * sizeof(store). */
+int lbm_required_bytes(const lbm_ctx* ctx, size_t* bytes);
+
+/* Binds caller-owned device memory (e.g. a torch tensor) as the population
+ * array.  dev_ptr must be 256-byte aligned and hold at least the required
+ * bytes; the library never frees it.  The contents are undefined until an
+ * lbm_init_* or lbm_set_state call.  Allocates the library's small side
+ * buffers on the pointer's device. */
+int lbm_bind_storage(lbm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Sets the HIP stream (a hipStream_t, NULL = the default stream) on which all
+ * of the context's device work is enqueued. */
+int lbm_set_stream(lbm_ctx* ctx, void* hip_stream);
+
+/* LBM_BB, LBM_WFB or LBM_FREESLIP; applies from the next step (and to the
+ * observables of the current state). */
+int lbm_set_boundary(lbm_ctx* ctx, int bc);
+
+/* Initial state f = f_eq(1, u0) taken as post-collision populations:
+ * u0 = U(y) (1 + d0, d1, d2) with U(y) = u_tau u+(y+), u+ from Spalding's law
+ * (Eq. 16) at y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1, and d_i uniform
+ * in [-noise, noise) drawn by splitmix64 (Steele, Lea & Flood 2014) with
+ * counter 3 c + i from state `seed`.  Resets the step count to 0. */
+int lbm_init_spalding(lbm_ctx* ctx, double u_tau, double noise, uint64_t seed);
+
+/* Sets the state from host memory: h[a][c] = f*_a(c) - w_a, the post-collision
+ * populations minus the weights, 19 * ncells doubles (rounded to the store
+ * format).  Resets the step count to `steps`. Synchronises. */
+int lbm_set_state(lbm_ctx* ctx, const double* h_host, int64_t steps);
+
+/* Copies the state to host memory in the same canonical form as
+ * lbm_set_state, whatever the internal layout.  cells == NULL: all cells,
+ * out is [19][ncells]; otherwise out is [19][n] for the n listed cells.
+ * Synchronises. */
+int lbm_get_state(lbm_ctx* ctx, double* h_host);
+int lbm_get_state_cells(lbm_ctx* ctx, int64_t n, const int64_t* cells, double* out);
+
+/* Advances n >= 0 time steps.  Asynchronous; device-side failures surface at
+ * the next synchronising call. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Synchronises the stream and reports device-side failures: LBM_E_NONFINITE
+ * or LBM_E_NEWTON, with the first failing step (1-based) in *first_bad_step
+ * (may be NULL; -1 when none). */
+int lbm_sync(lbm_ctx* ctx, int64_t* first_bad_step);
+
+/* Steps done since the last initialisation. */
+int lbm_steps_done(const lbm_ctx* ctx, int64_t* steps);
+
+/* Observables of the current state: the gather and WFB correction the next
+ * step would do, then rho and u = (sum e f + F/2) / rho (Eq. 2).  Host arrays
+ * of ncells doubles each (any may be NULL), indexed by c.  Synchronises. */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz);
+/* Same for n listed cells: out is [n][4] = rho, ux, uy, uz. */
+int lbm_moments_cells(lbm_ctx* ctx, int64_t n, const int64_t* cells, double* out);
+
+/* Wall records of the current state, 2 * nx * nz doubles each (any may be
+ * NULL), layout [w][z][x], w = 0 bottom, 1 top.  WFB: tau_x, tau_z (Eq. 15),
+ * u_tau (Eq. 17) and the wall-parallel speed U fed to Spalding's law.  BB:
+ * the wall force on the fluid by momentum exchange and u_tau = sqrt(|tau|/rho).
+ * Free-slip: zeros and U.  Synchronises. */
+int lbm_wall_shear(lbm_ctx* ctx, double* tau_x, double* tau_z, double* u_tau, double* U);
+
+/* Plane statistics (Sec. 3.1 time and plane averages, Fig. 6 moments),
+ * accumulated in FP64 on sampled steps from the velocity each sampled step
+ * computes.  lbm_stats_sums: out[y][8] = sums of ux, uy, uz, ux^2, uy^2, uz^2,
+ * ux uy and the number of cell samples.  lbm_stats_get: out[y][8] = <ux>,
+ * <uy>, <uz>, <ux'^2>, <uy'^2>, <uz'^2>, <ux'uy'>, cell samples.  Both
+ * synchronise; nsamples (may be NULL) receives the number of sampled steps. */
+int lbm_stats_reset(lbm_ctx* ctx);
+int lbm_stats_sums(lbm_ctx* ctx, double* out, int64_t* nsamples);
+int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
+
+/* Picks the block size of the odd and even step kernels by timing each
+ * candidate for `steps` steps (>= 2) on the bound storage.  Valid only before
+ * the state is initialised (it writes a rest state); afterwards the state is
+ * undefined until lbm_init_* / lbm_set_state.  Synchronises.  tiles (may be
+ * NULL) receives the chosen odd and even tile sizes. */
+int lbm_autotune(lbm_ctx* ctx, int steps, int32_t* tiles);
+
+/* Spalding's law inverted on the host (Eq. 16): u+ for a given y+ >= 0. */
+int lbm_spalding_uplus(double yplus, double kappa, double B, double* uplus);
+
+/* The device wall-function solve on n host values of the wall-parallel speed
+ * U: u_tau[i] (-1 on an iteration-cap failure) and iterations[i].  Uses the
+ * same device code as the step.  Synchronises the default stream. */
+int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, double kappa, double B, double tol,
+                         int32_t maxit, double* u_tau, int32_t* iterations);
+
+/* Streams `bytes` (a multiple of 16) from src to dst on the device with a
+ * plain copy kernel; a probe of the achievable HBM bandwidth. */
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+const char* lbm_status_str(int status);
+/* Text of the last error of ctx (valid until the next call on ctx), or of the
+ * last error of a call without a context when ctx is NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMWF_H */

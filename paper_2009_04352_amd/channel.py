@@ -1,0 +1,183 @@
+"""Python face of the C ABI: one channel context on one GPU.
+
+PyTorch provides the device memory (a uint8 tensor the library binds) and
+the stream; every step of the computation runs in the library's HIP kernels.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+
+STORES = {"f64": L.LBM_STORE_F64, "f32": L.LBM_STORE_F32, "f16": L.LBM_STORE_F16, "bf16": L.LBM_STORE_BF16}
+BOUNDARIES = {"bb": L.LBM_BB, "wfb": L.LBM_WFB, "freeslip": L.LBM_FREESLIP}
+
+
+def spalding_uplus(yplus, kappa=0.41, B=5.5):
+    """u+ of Spalding's law at y+ (host inversion in the library)."""
+    out = C.c_double(0.0)
+    L.check(L.lib().lbm_spalding_uplus(float(yplus), float(kappa), float(B), C.byref(out)))
+    return out.value
+
+
+def device_wall_utau(U, y1, nu, kappa=0.41, B=5.5, tol=1e-14, maxit=100):
+    """The step kernel's FP64 wall-function solve on the GPU for each speed in U:
+    returns (u_tau, iterations); u_tau = -1 marks an iteration-cap failure."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    ut = np.zeros_like(U)
+    it = np.zeros(U.shape, dtype=np.int32)
+    L.check(L.lib().lbm_device_wall_utau(U.size, L.dptr(U), y1, nu, kappa, B, tol, maxit, L.dptr(ut),
+                                         it.ctypes.data_as(C.POINTER(C.c_int32))))
+    return ut, it
+
+
+def copy_probe(dst, src, nbytes, stream=None):
+    """Plain device copy of nbytes (multiple of 16) between two torch tensors."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    L.check(L.lib().lbm_copy_probe(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), int(nbytes),
+                                   C.c_void_p(s.cuda_stream)))
+
+
+class Channel:
+    """A D3Q19 channel (x, z periodic, walls in y) advanced on the GPU."""
+
+    def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
+                 device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False):
+        import torch
+        self.lib = L.lib()
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.ncell = nx * ny * nz
+        self.store = store
+        h = C.c_void_p()
+        L.check(self.lib.lbm_create(C.byref(L.Grid(nx, ny, nz)), tau, cs, kappa, B, fx, C.byref(h)))
+        self._h = h
+        self._set(L.LBM_P_STORE, STORES[store])
+        self._set(L.LBM_P_Y1, y1)
+        if stats_every:
+            self._set(L.LBM_P_STATS_EVERY, stats_every)
+        if graph_steps is not None:
+            self._set(L.LBM_P_GRAPH_STEPS, graph_steps)
+        if tiles is not None:
+            self._set(L.LBM_P_TILE_ODD, tiles[0])
+            self._set(L.LBM_P_TILE_EVEN, tiles[1])
+        nbytes = C.c_size_t(0)
+        L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
+        self.nbytes = nbytes.value
+        self.device = torch.device(device)
+        self.storage = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        L.check(self.lib.lbm_bind_storage(self._h, C.c_void_p(self.storage.data_ptr()), self.nbytes), self._h)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.check(self.lib.lbm_set_stream(self._h, C.c_void_p(self.stream.cuda_stream)), self._h)
+        self.set_boundary(bc)
+        self.tiles = None
+        if autotune:
+            self.autotune()
+
+    # -- plumbing
+    def _chk(self, code):
+        return L.check(code, self._h)
+
+    def _set(self, key, value):
+        self._chk(self.lib.lbm_set_param(self._h, key, float(value)))
+
+    def get_param(self, key):
+        v = C.c_double(0.0)
+        self._chk(self.lib.lbm_get_param(self._h, key, C.byref(v)))
+        return v.value
+
+    def set_param(self, key, value):
+        self._set(key, value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lbm_destroy(self._h)
+            self._h = C.c_void_p()
+        self.storage = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up
+    def set_boundary(self, bc):
+        self._chk(self.lib.lbm_set_boundary(self._h, BOUNDARIES[bc] if isinstance(bc, str) else int(bc)))
+
+    def autotune(self, steps=6):
+        t = (C.c_int32 * 2)()
+        self._chk(self.lib.lbm_autotune(self._h, int(steps), t))
+        self.tiles = (t[0], t[1])
+        return self.tiles
+
+    def init_spalding(self, u_tau, noise=0.05, seed=0):
+        self._chk(self.lib.lbm_init_spalding(self._h, float(u_tau), float(noise), int(seed)))
+
+    def set_state(self, h, steps=0):
+        """h: [19, nz, ny, nx] (or flat) float64, post-collision f - w."""
+        h = np.ascontiguousarray(h, dtype=np.float64).reshape(-1)
+        if h.size != 19 * self.ncell:
+            raise ValueError("state must hold 19 * ncell values")
+        self._chk(self.lib.lbm_set_state(self._h, L.dptr(h), int(steps)))
+
+    def get_state(self):
+        out = np.empty(19 * self.ncell)
+        self._chk(self.lib.lbm_get_state(self._h, L.dptr(out)))
+        return out.reshape((19,) + self.shape)
+
+    def get_state_cells(self, cells):
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty(19 * len(cells))
+        self._chk(self.lib.lbm_get_state_cells(self._h, len(cells), L.i64ptr(cells), L.dptr(out)))
+        return out.reshape(19, len(cells)).T.copy()
+
+    # -- time stepping
+    def step(self, n=1):
+        self._chk(self.lib.lbm_step(self._h, int(n)))
+
+    def sync(self):
+        """Returns (status, first bad step); raises nothing."""
+        fb = C.c_int64(-1)
+        st = self.lib.lbm_sync(self._h, C.byref(fb))
+        return st, fb.value
+
+    @property
+    def steps(self):
+        s = C.c_int64(0)
+        self._chk(self.lib.lbm_steps_done(self._h, C.byref(s)))
+        return s.value
+
+    # -- observation
+    def moments(self):
+        outs = [np.empty(self.ncell) for _ in range(4)]
+        self._chk(self.lib.lbm_moments(self._h, *[L.dptr(o) for o in outs]))
+        return tuple(o.reshape(self.shape) for o in outs)
+
+    def moments_cells(self, cells):
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.empty(4 * len(cells))
+        self._chk(self.lib.lbm_moments_cells(self._h, len(cells), L.i64ptr(cells), L.dptr(out)))
+        return out.reshape(len(cells), 4)
+
+    def wall_shear(self):
+        m = 2 * self.nx * self.nz
+        outs = [np.empty(m) for _ in range(4)]
+        self._chk(self.lib.lbm_wall_shear(self._h, *[L.dptr(o) for o in outs]))
+        return tuple(o.reshape(2, self.nz, self.nx) for o in outs)
+
+    def stats_reset(self):
+        self._chk(self.lib.lbm_stats_reset(self._h))
+
+    def stats_sums(self):
+        out = np.empty(8 * self.ny)
+        ns = C.c_int64(0)
+        self._chk(self.lib.lbm_stats_sums(self._h, L.dptr(out), C.byref(ns)))
+        return out.reshape(self.ny, 8), ns.value
+
+    def stats(self):
+        out = np.empty(8 * self.ny)
+        ns = C.c_int64(0)
+        self._chk(self.lib.lbm_stats_get(self._h, L.dptr(out), C.byref(ns)))
+        return out.reshape(self.ny, 8), ns.value

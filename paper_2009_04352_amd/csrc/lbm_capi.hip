@@ -1,0 +1,913 @@
+// C ABI of the WFB LBM-LES channel library: contexts, argument checking,
+// storage binding, launch sequencing (AA parity, HIP graph chunks),
+// observation, statistics and the block-size autotuner.  Declared in
+// include/lbmwf.h; the device code lives in lbm_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lbm_internal.h"
+#include "lbmwf.h"
+#include "store.h"
+
+using namespace lbmwf;
+
+namespace {
+
+thread_local std::string g_err;  // errors of calls without a context
+
+struct GraphKey {
+    int layout_s, len, stats_every;
+    long long phase;
+    bool operator<(const GraphKey& o) const
+    {
+        return std::tie(layout_s, len, stats_every, phase) < std::tie(o.layout_s, o.len, o.stats_every, o.phase);
+    }
+};
+
+}  // namespace
+
+struct lbm_ctx {
+    int nx = 0, ny = 0, nz = 0;
+    long long n = 0;
+    double tau0 = 0, cs = 0, kappa = 0, bconst = 0, fx = 0;
+    double y1 = 1.0, newton_tol = 1e-14;
+    int newton_maxit = 100;
+    int store = kStoreF64;
+    int bc = kWFB;
+    int stats_every = 0;
+    int tile_odd = 256, tile_even = 256, xcd_remap = 1, graph_steps = 32;
+
+    void* h = nullptr;
+    size_t bytes = 0;
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+
+    DevFlags* dflags = nullptr;
+    double* dacc = nullptr;      // [ny][8]
+    double* dprof = nullptr;     // [ny]
+    double* dpart = nullptr;     // [max tiles][7]
+    size_t part_cap = 0;         // tiles
+    double* dtmp = nullptr;      // relayout scratch, [2 nx nz][5]
+
+    bool initialized = false;
+    long long steps = 0;
+    int layout_s = 0;            // 1 after an odd number of steps
+    int layout_spec = 0;         // reflections stored in layout S were mirror images
+    long long nsamples = 0;
+
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::string err;
+};
+
+namespace {
+
+int fail(lbm_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+#define LBM_HIP(ctx, call)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (dev >= 0 && hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+        else prev = -1;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int tiles_per_row(int nx, int tile) { return (nx + tile - 1) / tile; }
+
+long long ntiles_for(const lbm_ctx* c, int tile)
+{
+    return (long long)tiles_per_row(c->nx, tile) * c->ny * c->nz;
+}
+
+bool tile_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
+
+void drop_graphs(lbm_ctx* c)
+{
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+StepArgs step_args(const lbm_ctx* c, bool odd)
+{
+    StepArgs a{};
+    a.h = c->h;
+    a.n = c->n;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.tile_x = odd ? c->tile_odd : c->tile_even;
+    a.ntx = tiles_per_row(c->nx, a.tile_x);
+    a.ntiles = (int)ntiles_for(c, a.tile_x);
+    a.xcd_remap = c->xcd_remap;
+    a.newton_maxit = c->newton_maxit;
+    a.tau0 = c->tau0;
+    a.cs2_18 = 18.0 * c->cs * c->cs;
+    a.fx = c->fx;
+    a.y1 = c->y1;
+    a.nu0 = (c->tau0 - 0.5) / 3.0;
+    a.kappa = c->kappa;
+    a.bconst = c->bconst;
+    a.ekb = std::exp(-c->kappa * c->bconst);
+    a.newton_tol = c->newton_tol;
+    a.flags = c->dflags;
+    a.partials = c->dpart;
+    return a;
+}
+
+ObsArgs obs_args(const lbm_ctx* c)
+{
+    ObsArgs a{};
+    a.h = c->h;
+    a.n = c->n;
+    a.nx = c->nx;
+    a.ny = c->ny;
+    a.nz = c->nz;
+    a.layout_s = c->layout_s;
+    a.bc = c->bc;
+    a.layout_spec = c->layout_spec;
+    a.newton_maxit = c->newton_maxit;
+    a.fx = c->fx;
+    a.y1 = c->y1;
+    a.nu0 = (c->tau0 - 0.5) / 3.0;
+    a.kappa = c->kappa;
+    a.bconst = c->bconst;
+    a.ekb = std::exp(-c->kappa * c->bconst);
+    a.newton_tol = c->newton_tol;
+    return a;
+}
+
+bool sampled(const lbm_ctx* c, long long t) { return c->stats_every > 0 && t % c->stats_every == 0; }
+
+// Enqueues `len` steps starting after step t0 from layout `layout_s` on stream s.
+// Pure with respect to the context's bookkeeping (used for eager launches and
+// for graph capture).
+hipError_t enqueue_steps(const lbm_ctx* c, hipStream_t s, int layout_s, long long t0, long long len)
+{
+    const StepArgs ao = step_args(c, true), ae = step_args(c, false);
+    for (long long i = 0; i < len; ++i) {
+        const long long t = t0 + 1 + i;
+        const bool odd = (layout_s == 0);
+        const bool st = sampled(c, t);
+        hipError_t e = launch_step(c->store, odd, c->bc, st, odd ? ao : ae, s);
+        if (e != hipSuccess) return e;
+        if (st) {
+            const StepArgs& a = odd ? ao : ae;
+            e = launch_stats_reduce(c->dpart, a.ntx, c->ny, c->nz, c->nx, c->dacc, s);
+            if (e != hipSuccess) return e;
+        }
+        layout_s ^= 1;
+    }
+    return hipSuccess;
+}
+
+void advance_bookkeeping(lbm_ctx* c, long long len)
+{
+    for (long long i = 0; i < len; ++i) {
+        const long long t = c->steps + 1;
+        if (c->layout_s == 0) c->layout_spec = (c->bc != kBB);
+        if (sampled(c, t)) c->nsamples += 1;
+        c->layout_s ^= 1;
+        c->steps = t;
+    }
+}
+
+int ensure_partials(lbm_ctx* c)
+{
+    if (c->stats_every <= 0) return LBM_OK;
+    const size_t need = (size_t)std::max(ntiles_for(c, c->tile_odd), ntiles_for(c, c->tile_even));
+    if (need <= c->part_cap) return LBM_OK;
+    drop_graphs(c);
+    if (c->dpart) (void)hipFree(c->dpart);
+    c->dpart = nullptr;
+    c->part_cap = 0;
+    LBM_HIP(c, hipMalloc((void**)&c->dpart, need * 7 * sizeof(double)));
+    c->part_cap = need;
+    return LBM_OK;
+}
+
+int reset_flags(lbm_ctx* c)
+{
+    DevFlags f{};
+    f.status = 0;
+    f.max_newton_iters = 0;
+    f.first_bad = ~0ull;
+    f.cnt[0] = f.cnt[1] = c->steps + 1;
+    LBM_HIP(c, hipMemcpyAsync(c->dflags, &f, sizeof(f), hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(c, hipStreamSynchronize(c->stream));  // f lives on the host stack
+    return LBM_OK;
+}
+
+int read_flags(lbm_ctx* c, DevFlags* f)
+{
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+    LBM_HIP(c, hipMemcpy(f, c->dflags, sizeof(DevFlags), hipMemcpyDeviceToHost));
+    return LBM_OK;
+}
+
+int status_of(const DevFlags& f)
+{
+    if (f.status & 1) return LBM_E_NONFINITE;
+    if (f.status & 2) return LBM_E_NEWTON;
+    return LBM_OK;
+}
+
+// Synchronise and report any device-side failure.
+int sync_check(lbm_ctx* c)
+{
+    DevFlags f;
+    int st = read_flags(c, &f);
+    if (st != LBM_OK) return st;
+    st = status_of(f);
+    if (st != LBM_OK)
+        return fail(c, st, std::string(lbm_status_str(st)) + " at step " + std::to_string((long long)f.first_bad));
+    return LBM_OK;
+}
+
+int check_ready(lbm_ctx* c)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+    if (!c->initialized) return fail(c, LBM_E_STATE, "state not initialised");
+    return LBM_OK;
+}
+
+// Moves the wall-crossing populations of a streamed layout when the boundary
+// switched between bounce-back and mirror reflection.
+int fix_layout(lbm_ctx* c)
+{
+    if (!c->initialized || !c->layout_s) return LBM_OK;
+    const int want = (c->bc != kBB);
+    if (want == c->layout_spec) return LBM_OK;
+    if (!c->dtmp) LBM_HIP(c, hipMalloc((void**)&c->dtmp, (size_t)2 * c->nx * c->nz * 5 * sizeof(double)));
+    LBM_HIP(c, launch_relayout(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->layout_spec, want, c->dtmp, c->stream));
+    c->layout_spec = want;
+    return LBM_OK;
+}
+
+// u+ of Spalding's law (Eq. 16) at y+: Newton on Sp(p) - y+ = 0 from a start
+// to the right of the root (Sp(p) >= p, and the log-law estimate plus a margin
+// when it is also to the right), where Newton on the increasing convex
+// function converges monotonically.
+double spalding_uplus_host(double yp, double kappa, double b)
+{
+    if (!(yp > 0.0)) return 0.0;
+    const double ekb = std::exp(-kappa * b);
+    auto sp = [&](double p) {
+        const double k = kappa * p;
+        return p + ekb * (std::expm1(k) - k - 0.5 * k * k - k * k * k / 6.0);
+    };
+    double p = yp;
+    const double alt = b + std::log1p(yp) / kappa + 2.0;
+    if (alt < p && sp(alt) >= yp) p = alt;
+    for (int it = 0; it < 400; ++it) {
+        const double k = kappa * p;
+        const double g = sp(p) - yp;
+        const double dg = 1.0 + kappa * ekb * (std::expm1(k) - k - 0.5 * k * k);
+        const double pn = p - g / dg;
+        if (!(pn < p)) break;  // monotone decrease has stopped: converged to round-off
+        p = pn;
+    }
+    return p;
+}
+
+}  // namespace
+
+// ===================================================================== API
+
+extern "C" {
+
+const char* lbm_status_str(int s)
+{
+    switch (s) {
+        case LBM_OK: return "ok";
+        case LBM_E_ARG: return "invalid argument";
+        case LBM_E_STATE: return "invalid state";
+        case LBM_E_OOM: return "out of memory";
+        case LBM_E_DEVICE: return "device error";
+        case LBM_E_NONFINITE: return "non-finite density";
+        case LBM_E_NEWTON: return "wall-function Newton solve did not converge";
+    }
+    return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+int lbm_create(const lbm_grid* g, double tau, double Cs, double kappa, double B, double Fx, lbm_ctx** out)
+{
+    if (!g || !out) return fail(nullptr, LBM_E_ARG, "null argument");
+    if (g->nx < 1 || g->ny < 2 || g->nz < 1) return fail(nullptr, LBM_E_ARG, "grid needs nx >= 1, ny >= 2, nz >= 1");
+    const long long n = (long long)g->nx * g->ny * g->nz;
+    if (n >= (1ll << 31)) return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny * nz must be below 2^31");
+    if (!std::isfinite(tau) || !(tau > 0.5)) return fail(nullptr, LBM_E_ARG, "tau must be finite and > 1/2");
+    if (!std::isfinite(Cs) || !(Cs >= 0.0)) return fail(nullptr, LBM_E_ARG, "Cs must be finite and >= 0");
+    if (!std::isfinite(kappa) || !(kappa > 0.0)) return fail(nullptr, LBM_E_ARG, "kappa must be finite and > 0");
+    if (!std::isfinite(B) || !std::isfinite(Fx)) return fail(nullptr, LBM_E_ARG, "B and Fx must be finite");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_E_OOM, "context allocation failed");
+    c->nx = g->nx;
+    c->ny = g->ny;
+    c->nz = g->nz;
+    c->n = n;
+    c->tau0 = tau;
+    c->cs = Cs;
+    c->kappa = kappa;
+    c->bconst = B;
+    c->fx = Fx;
+    *out = c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    DeviceGuard dg(c->dev);
+    if (c->stream || c->dflags) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->dflags) (void)hipFree(c->dflags);
+    if (c->dacc) (void)hipFree(c->dacc);
+    if (c->dprof) (void)hipFree(c->dprof);
+    if (c->dpart) (void)hipFree(c->dpart);
+    if (c->dtmp) (void)hipFree(c->dtmp);
+    delete c;
+}
+
+int lbm_set_param(lbm_ctx* c, int key, double v)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!std::isfinite(v)) return fail(c, LBM_E_ARG, "parameter value must be finite");
+    const bool integral = (v == std::floor(v));
+    switch (key) {
+        case LBM_P_Y1:
+            if (!(v > 0.0)) return fail(c, LBM_E_ARG, "y1 must be > 0");
+            c->y1 = v;
+            break;
+        case LBM_P_NEWTON_TOL:
+            if (!(v > 0.0)) return fail(c, LBM_E_ARG, "Newton tolerance must be > 0");
+            c->newton_tol = v;
+            break;
+        case LBM_P_NEWTON_MAXIT:
+            if (!integral || v < 1 || v > 10000) return fail(c, LBM_E_ARG, "Newton cap must be an integer in [1, 10000]");
+            c->newton_maxit = (int)v;
+            break;
+        case LBM_P_STATS_EVERY:
+            if (!integral || v < 0 || v > 1e9) return fail(c, LBM_E_ARG, "statistics interval must be an integer >= 0");
+            c->stats_every = (int)v;
+            break;
+        case LBM_P_STORE:
+            if (c->h) return fail(c, LBM_E_STATE, "the store format is fixed once storage is bound");
+            if (!integral || v < 0 || v > 3) return fail(c, LBM_E_ARG, "store must be 0..3");
+            c->store = (int)v;
+            return LBM_OK;
+        case LBM_P_TILE_ODD:
+        case LBM_P_TILE_EVEN:
+            if (!integral || !tile_ok((int)v)) return fail(c, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
+            (key == LBM_P_TILE_ODD ? c->tile_odd : c->tile_even) = (int)v;
+            break;
+        case LBM_P_XCD_REMAP:
+            if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
+            c->xcd_remap = (int)v;
+            break;
+        case LBM_P_GRAPH_STEPS:
+            if (!integral || v < 0 || v > 4096) return fail(c, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
+            c->graph_steps = (int)v;
+            break;
+        case LBM_P_FX:
+            c->fx = v;
+            break;
+        case LBM_P_CS:
+            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "Cs must be >= 0");
+            c->cs = v;
+            break;
+        default:
+            return fail(c, LBM_E_ARG, "unknown or read-only parameter key");
+    }
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_get_param(const lbm_ctx* c, int key, double* v)
+{
+    if (!c || !v) return fail(nullptr, LBM_E_ARG, "null argument");
+    switch (key) {
+        case LBM_P_Y1: *v = c->y1; break;
+        case LBM_P_NEWTON_TOL: *v = c->newton_tol; break;
+        case LBM_P_NEWTON_MAXIT: *v = c->newton_maxit; break;
+        case LBM_P_STATS_EVERY: *v = c->stats_every; break;
+        case LBM_P_STORE: *v = c->store; break;
+        case LBM_P_TILE_ODD: *v = c->tile_odd; break;
+        case LBM_P_TILE_EVEN: *v = c->tile_even; break;
+        case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
+        case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
+        case LBM_P_BC: *v = c->bc; break;
+        case LBM_P_TAU0: *v = c->tau0; break;
+        case LBM_P_FX: *v = c->fx; break;
+        case LBM_P_CS: *v = c->cs; break;
+        default: return fail(const_cast<lbm_ctx*>(c), LBM_E_ARG, "unknown parameter key");
+    }
+    return LBM_OK;
+}
+
+int lbm_required_bytes(const lbm_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return fail(nullptr, LBM_E_ARG, "null argument");
+    *bytes = (size_t)19 * (size_t)c->n * (size_t)store_bytes(c->store);
+    return LBM_OK;
+}
+
+int lbm_bind_storage(lbm_ctx* c, void* ptr, size_t bytes)
+{
+    if (!c || !ptr) return fail(c, LBM_E_ARG, "null argument");
+    size_t need = 0;
+    lbm_required_bytes(c, &need);
+    if (bytes < need) return fail(c, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ptr) % 256 != 0) return fail(c, LBM_E_ARG, "storage must be 256-byte aligned");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, ptr);
+    if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
+        return fail(c, LBM_E_ARG, "storage is not device memory");
+    if (c->h && attr.device != c->dev) return fail(c, LBM_E_STATE, "storage must stay on the same device");
+    c->dev = attr.device;
+    DeviceGuard dg(c->dev);
+    if (!c->dflags) {
+        LBM_HIP(c, hipMalloc((void**)&c->dflags, sizeof(DevFlags)));
+        LBM_HIP(c, hipMalloc((void**)&c->dacc, (size_t)c->ny * 8 * sizeof(double)));
+        LBM_HIP(c, hipMalloc((void**)&c->dprof, (size_t)c->ny * sizeof(double)));
+        LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
+    }
+    drop_graphs(c);
+    c->h = ptr;
+    c->bytes = bytes;
+    c->initialized = false;
+    return LBM_OK;
+}
+
+int lbm_set_stream(lbm_ctx* c, void* s)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    c->stream = (hipStream_t)s;
+    return LBM_OK;
+}
+
+int lbm_set_boundary(lbm_ctx* c, int bc)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (bc != LBM_BB && bc != LBM_WFB && bc != LBM_FREESLIP) return fail(c, LBM_E_ARG, "unknown boundary");
+    DeviceGuard dg(c->dev);
+    c->bc = bc;
+    drop_graphs(c);
+    return fix_layout(c);
+}
+
+int lbm_init_spalding(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+    if (!std::isfinite(u_tau) || u_tau < 0.0 || !std::isfinite(noise) || noise < 0.0 || noise >= 1.0)
+        return fail(c, LBM_E_ARG, "need 0 <= u_tau, 0 <= noise < 1");
+    DeviceGuard dg(c->dev);
+    std::vector<double> prof(c->ny);
+    const double nu0 = (c->tau0 - 0.5) / 3.0;
+    for (int y = 0; y < c->ny; ++y) {
+        const int d = std::min(y, c->ny - 1 - y);
+        const double dist = d + c->y1;
+        prof[y] = u_tau * spalding_uplus_host(dist * u_tau / nu0, c->kappa, c->bconst);
+    }
+    LBM_HIP(c, hipMemcpyAsync(c->dprof, prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    LBM_HIP(c, launch_init_spalding(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->dprof, noise,
+                                    (unsigned long long)seed, c->stream));
+    c->steps = 0;
+    c->layout_s = 0;
+    c->layout_spec = (c->bc != kBB);
+    c->initialized = true;
+    int st = reset_flags(c);
+    if (st != LBM_OK) return st;
+    LBM_HIP(c, hipStreamSynchronize(c->stream));  // the profile lives on the host stack
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
+{
+    if (!c || !in) return fail(c, LBM_E_ARG, "null argument");
+    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+    if (steps < 0) return fail(c, LBM_E_ARG, "steps must be >= 0");
+    DeviceGuard dg(c->dev);
+    const long long chunk = std::min<long long>(c->n, 1ll << 24);
+    double* tmp = nullptr;
+    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
+    std::vector<double> stage((size_t)chunk * 19);
+    int st = LBM_OK;
+    for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
+        const long long cnt = std::min(chunk, c->n - first);
+        for (int a = 0; a < 19; ++a)
+            std::memcpy(stage.data() + (size_t)a * cnt, in + (size_t)a * c->n + first, (size_t)cnt * sizeof(double));
+        hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 19 * sizeof(double), hipMemcpyHostToDevice,
+                                      c->stream);
+        if (e == hipSuccess) e = launch_set_state(c->store, c->h, c->n, first, cnt, tmp, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("set_state: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(tmp);
+    if (st != LBM_OK) return st;
+    c->steps = steps;
+    c->layout_s = 0;
+    c->layout_spec = (c->bc != kBB);
+    c->initialized = true;
+    st = reset_flags(c);
+    if (st != LBM_OK) return st;
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, double* out)
+{
+    int st = check_ready(c);
+    if (st != LBM_OK) return st;
+    DeviceGuard dg(c->dev);
+    if ((st = fix_layout(c)) != LBM_OK) return st;
+    if ((st = sync_check(c)) != LBM_OK) return st;
+    if (cells)
+        for (long long i = 0; i < count; ++i)
+            if (cells[i] < 0 || cells[i] >= c->n) return fail(c, LBM_E_ARG, "cell index out of range");
+    const long long chunk = std::min<long long>(std::max<long long>(count, 1), 1ll << 24);
+    double* tmp = nullptr;
+    long long* dcells = nullptr;
+    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
+    if (cells && hipMalloc((void**)&dcells, (size_t)chunk * sizeof(long long)) != hipSuccess) {
+        (void)hipFree(tmp);
+        return fail(c, LBM_E_DEVICE, "get_state: allocation failed");
+    }
+    std::vector<double> stage((size_t)chunk * 19);
+    std::vector<double> result((size_t)count * 19);
+    for (long long first = 0; first < count && st == LBM_OK; first += chunk) {
+        const long long cnt = std::min(chunk, count - first);
+        hipError_t e = hipSuccess;
+        if (cells)
+            e = hipMemcpyAsync(dcells, cells + first, (size_t)cnt * sizeof(long long), hipMemcpyHostToDevice,
+                               c->stream);
+        if (e == hipSuccess)
+            e = launch_get_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->layout_s, c->layout_spec,
+                                 cells ? dcells : nullptr, cells ? 0 : first, cnt, tmp, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(stage.data(), tmp, (size_t)cnt * 19 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            st = fail(c, LBM_E_DEVICE, std::string("get_state: ") + hipGetErrorString(e));
+            break;
+        }
+        for (int a = 0; a < 19; ++a)
+            std::memcpy(result.data() + (size_t)a * count + first, stage.data() + (size_t)a * cnt,
+                        (size_t)cnt * sizeof(double));
+    }
+    (void)hipFree(tmp);
+    if (dcells) (void)hipFree(dcells);
+    if (st == LBM_OK) std::memcpy(out, result.data(), result.size() * sizeof(double));
+    return st;
+}
+
+int lbm_get_state(lbm_ctx* c, double* out)
+{
+    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+    return get_state_impl(c, c->n, nullptr, out);
+}
+
+int lbm_get_state_cells(lbm_ctx* c, int64_t n, const int64_t* cells, double* out)
+{
+    if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
+    if (n == 0) return LBM_OK;
+    return get_state_impl(c, n, cells, out);
+}
+
+int lbm_step(lbm_ctx* c, int64_t n)
+{
+    int st = check_ready(c);
+    if (st != LBM_OK) return st;
+    if (n < 0) return fail(c, LBM_E_ARG, "n must be >= 0");
+    if (n == 0) return LBM_OK;
+    DeviceGuard dg(c->dev);
+    if ((st = fix_layout(c)) != LBM_OK) return st;
+    if ((st = ensure_partials(c)) != LBM_OK) return st;
+    long long left = n;
+    while (left > 0) {
+        if (c->graph_steps > 0 && left >= c->graph_steps) {
+            const long long L = c->graph_steps;
+            GraphKey key{c->layout_s, (int)L, c->stats_every, c->stats_every > 0 ? c->steps % c->stats_every : 0};
+            auto it = c->graphs.find(key);
+            if (it == c->graphs.end()) {
+                if (!c->cap_stream) LBM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                LBM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = enqueue_steps(c, c->cap_stream, c->layout_s, c->steps, L);
+                hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return fail(c, LBM_E_DEVICE, std::string("graph capture: ") +
+                                                     hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                hipGraphExec_t ex = nullptr;
+                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                it = c->graphs.emplace(key, ex).first;
+            }
+            LBM_HIP(c, hipGraphLaunch(it->second, c->stream));
+            advance_bookkeeping(c, L);
+            left -= L;
+        } else {
+            LBM_HIP(c, enqueue_steps(c, c->stream, c->layout_s, c->steps, 1));
+            advance_bookkeeping(c, 1);
+            left -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_sync(lbm_ctx* c, int64_t* first_bad)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (first_bad) *first_bad = -1;
+    if (!c->dflags) return LBM_OK;
+    DeviceGuard dg(c->dev);
+    DevFlags f;
+    int st = read_flags(c, &f);
+    if (st != LBM_OK) return st;
+    st = status_of(f);
+    if (st != LBM_OK) {
+        if (first_bad) *first_bad = (int64_t)f.first_bad;
+        return fail(c, st, std::string(lbm_status_str(st)) + " at step " + std::to_string((long long)f.first_bad));
+    }
+    return LBM_OK;
+}
+
+int lbm_steps_done(const lbm_ctx* c, int64_t* s)
+{
+    if (!c || !s) return fail(nullptr, LBM_E_ARG, "null argument");
+    *s = c->steps;
+    return LBM_OK;
+}
+
+static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* cells, double* out, int* iters)
+{
+    int st = check_ready(c);
+    if (st != LBM_OK) return st;
+    DeviceGuard dg(c->dev);
+    if ((st = fix_layout(c)) != LBM_OK) return st;
+    if ((st = sync_check(c)) != LBM_OK) return st;
+    if (cells)
+        for (long long i = 0; i < count; ++i)
+            if (cells[i] < 0 || cells[i] >= c->n) return fail(c, LBM_E_ARG, "cell index out of range");
+    const long long chunk = std::min<long long>(std::max<long long>(count, 1), 1ll << 24);
+    double* tmp = nullptr;
+    long long* dcells = nullptr;
+    int* dit = nullptr;
+    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 4 * sizeof(double)));
+    hipError_t e = hipSuccess;
+    if (cells) e = hipMalloc((void**)&dcells, (size_t)chunk * sizeof(long long));
+    if (e == hipSuccess && iters) e = hipMalloc((void**)&dit, (size_t)chunk * sizeof(int));
+    std::vector<double> result((size_t)count * 4);
+    std::vector<int> itres(iters ? (size_t)count : 0);
+    for (long long first = 0; first < count && e == hipSuccess; first += chunk) {
+        const long long cnt = std::min(chunk, count - first);
+        ObsArgs a = obs_args(c);
+        a.mode = mode;
+        a.cells = cells ? dcells : nullptr;
+        a.first = cells ? 0 : first;
+        a.count = cnt;
+        a.out = tmp;
+        a.iters = dit;
+        if (cells)
+            e = hipMemcpyAsync(dcells, cells + first, (size_t)cnt * sizeof(long long), hipMemcpyHostToDevice,
+                               c->stream);
+        if (mode == 1 && first != 0) e = hipErrorInvalidValue;  // wall records come in one chunk
+        if (e == hipSuccess) e = launch_observe(c->store, a, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(result.data() + (size_t)first * 4, tmp, (size_t)cnt * 4 * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && iters)
+            e = hipMemcpyAsync(itres.data() + first, dit, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    (void)hipFree(tmp);
+    if (dcells) (void)hipFree(dcells);
+    if (dit) (void)hipFree(dit);
+    if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("observe: ") + hipGetErrorString(e));
+    std::memcpy(out, result.data(), result.size() * sizeof(double));
+    if (iters) std::memcpy(iters, itres.data(), itres.size() * sizeof(int));
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    std::vector<double> buf;
+    try {
+        buf.resize((size_t)c->n * 4);
+    } catch (...) {
+        return fail(c, LBM_E_OOM, "host buffer allocation failed");
+    }
+    int st = observe_impl(c, 0, c->n, nullptr, buf.data(), nullptr);
+    if (st != LBM_OK) return st;
+    for (long long i = 0; i < c->n; ++i) {
+        if (rho) rho[i] = buf[4 * i];
+        if (ux) ux[i] = buf[4 * i + 1];
+        if (uy) uy[i] = buf[4 * i + 2];
+        if (uz) uz[i] = buf[4 * i + 3];
+    }
+    return LBM_OK;
+}
+
+int lbm_moments_cells(lbm_ctx* c, int64_t n, const int64_t* cells, double* out)
+{
+    if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
+    if (n == 0) return LBM_OK;
+    return observe_impl(c, 0, n, cells, out, nullptr);
+}
+
+int lbm_wall_shear(lbm_ctx* c, double* tx, double* tz, double* ut, double* U)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    const long long m = 2ll * c->nx * c->nz;
+    std::vector<double> buf((size_t)m * 4);
+    int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr);
+    if (st != LBM_OK) return st;
+    for (long long i = 0; i < m; ++i) {
+        if (tx) tx[i] = buf[4 * i];
+        if (tz) tz[i] = buf[4 * i + 1];
+        if (ut) ut[i] = buf[4 * i + 2];
+        if (U) U[i] = buf[4 * i + 3];
+    }
+    return LBM_OK;
+}
+
+int lbm_stats_reset(lbm_ctx* c)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
+    DeviceGuard dg(c->dev);
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+    LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
+    c->nsamples = 0;
+    return LBM_OK;
+}
+
+int lbm_stats_sums(lbm_ctx* c, double* out, int64_t* nsamples)
+{
+    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+    if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
+    DeviceGuard dg(c->dev);
+    int st = sync_check(c);
+    if (st != LBM_OK) return st;
+    LBM_HIP(c, hipMemcpy(out, c->dacc, (size_t)c->ny * 8 * sizeof(double), hipMemcpyDeviceToHost));
+    if (nsamples) *nsamples = c->nsamples;
+    return LBM_OK;
+}
+
+int lbm_stats_get(lbm_ctx* c, double* out, int64_t* nsamples)
+{
+    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+    std::vector<double> s((size_t)c->ny * 8);
+    int st = lbm_stats_sums(c, s.data(), nsamples);
+    if (st != LBM_OK) return st;
+    for (int y = 0; y < c->ny; ++y) {
+        const double* r = &s[(size_t)y * 8];
+        double* o = out + (size_t)y * 8;
+        const double m = r[7];
+        if (m <= 0.0) {
+            for (int k = 0; k < 8; ++k) o[k] = 0.0;
+            continue;
+        }
+        const double mx = r[0] / m, my = r[1] / m, mz = r[2] / m;
+        o[0] = mx; o[1] = my; o[2] = mz;
+        o[3] = r[3] / m - mx * mx;
+        o[4] = r[4] / m - my * my;
+        o[5] = r[5] / m - mz * mz;
+        o[6] = r[6] / m - mx * my;
+        o[7] = m;
+    }
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+    if (c->initialized) return fail(c, LBM_E_STATE, "autotune runs before the state is initialised");
+    if (steps < 2) return fail(c, LBM_E_ARG, "steps must be >= 2");
+    DeviceGuard dg(c->dev);
+    // a representative state: the initial profile the body force implies
+    const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
+    int st = lbm_init_spalding(c, ut, 0.05, 0);
+    if (st != LBM_OK) return st;
+    const int cand[4] = {64, 128, 256, 512};
+    const int save_every = c->stats_every, save_graph = c->graph_steps;
+    c->stats_every = 0;
+    hipEvent_t ev[3];
+    for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
+    float best_o = 1e30f, best_e = 1e30f;
+    int bo = c->tile_odd, be = c->tile_even;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+        c->tile_odd = c->tile_even = cand[k];
+        float to = 0.f, te = 0.f;
+        // one warm-up pair, then timed pairs
+        for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
+            const StepArgs ao = step_args(c, true), ae = step_args(c, false);
+            err = hipEventRecord(ev[0], c->stream);
+            if (err == hipSuccess) err = launch_step(c->store, true, c->bc, false, ao, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
+            if (err == hipSuccess) err = launch_step(c->store, false, c->bc, false, ae, c->stream);
+            if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
+            if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+            float a = 0.f, b = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
+            if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
+            if (r > 0) {
+                to += a;
+                te += b;
+            }
+        }
+        if (to < best_o) { best_o = to; bo = cand[k]; }
+        if (te < best_e) { best_e = te; be = cand[k]; }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    c->stats_every = save_every;
+    c->graph_steps = save_graph;
+    c->tile_odd = bo;
+    c->tile_even = be;
+    c->initialized = false;
+    drop_graphs(c);
+    if (err != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+    DevFlags f;
+    if ((st = read_flags(c, &f)) != LBM_OK) return st;
+    if (tiles) {
+        tiles[0] = bo;
+        tiles[1] = be;
+    }
+    return LBM_OK;
+}
+
+int lbm_spalding_uplus(double yplus, double kappa, double B, double* uplus)
+{
+    if (!uplus || !std::isfinite(yplus) || yplus < 0.0 || !(kappa > 0.0) || !std::isfinite(B))
+        return fail(nullptr, LBM_E_ARG, "need y+ >= 0, kappa > 0, finite B");
+    *uplus = spalding_uplus_host(yplus, kappa, B);
+    return LBM_OK;
+}
+
+int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, double kappa, double B, double tol,
+                         int32_t maxit, double* ut, int32_t* iters)
+{
+    if (n < 0 || (n > 0 && (!U || !ut || !iters))) return fail(nullptr, LBM_E_ARG, "bad argument");
+    if (!(y1 > 0) || !(nu > 0) || !(kappa > 0) || !(tol > 0) || maxit < 1) return fail(nullptr, LBM_E_ARG, "bad parameter");
+    if (n == 0) return LBM_OK;
+    double *dU = nullptr, *dut = nullptr;
+    int* dit = nullptr;
+    hipError_t e = hipMalloc((void**)&dU, (size_t)n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&dut, (size_t)n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&dit, (size_t)n * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(dU, U, (size_t)n * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_wall_utau(dU, n, y1, nu, kappa, B, tol, maxit, dut, dit, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(ut, dut, (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(iters, dit, (size_t)n * sizeof(int), hipMemcpyDeviceToHost);
+    if (dU) (void)hipFree(dU);
+    if (dut) (void)hipFree(dut);
+    if (dit) (void)hipFree(dit);
+    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("device wall solve: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* s)
+{
+    if (!dst || !src || bytes % 16 != 0) return fail(nullptr, LBM_E_ARG, "need device pointers and bytes % 16 == 0");
+    hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)s);
+    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+}  // extern "C"

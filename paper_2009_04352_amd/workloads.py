@@ -1,0 +1,75 @@
+"""The channel workloads measured and parity-tested, as seeded synthetic inputs.
+
+Every workload is the paper's channel (Sec. 3.1: x streamwise and periodic, y
+wall-normal with walls at both ends, z spanwise and periodic, D = ny / 2) with
+Smagorinsky Cs = 0.1 and Spalding constants kappa = 0.41, B = 5.5 (Eq. 16),
+started from the Spalding profile with 5 % seeded uniform noise.  Lattice
+parameters follow the low-Mach mapping of Table 1: the centreline speed is
+Ma_LB * c_s, u_tau = u_c / u+(Re_tau), nu0 = u_tau D / Re_tau,
+tau0 = 1/2 + 3 nu0, Fx = u_tau^2 / D.  A workload may instead name tau
+directly, keeping u_tau and Fx.
+
+No workload reads a dataset: the paper's inputs are the geometry and these
+parameters, not data.
+"""
+import math
+
+from .channel import spalding_uplus
+
+KAPPA, B, CS = 0.41, 5.5, 0.1
+
+
+def rule_m(ny, re_tau, ma, y1=1.0, kappa=KAPPA, b=B):
+    D = ny / 2.0
+    uc = ma / math.sqrt(3.0)
+    u_tau = uc / spalding_uplus(re_tau, kappa, b)
+    nu0 = u_tau * D / re_tau
+    return dict(u_tau=u_tau, nu0=nu0, tau0=0.5 + 3.0 * nu0, fx=u_tau * u_tau / D, yplus1=y1 * u_tau / nu0)
+
+
+# name: grid, Re_tau, Ma_LB (Table 1), steps, stores, boundaries, named tau (or None)
+WORKLOADS = {
+    "c1": dict(grid=(32, 16, 16), re_tau=640.0, ma=0.060, steps=200, stores=("f64",), bcs=("wfb", "bb"),
+               tau=0.51, desc="plain FP64 single channel 32x16x16, Re_tau 640, 200 steps"),
+    "c2": dict(grid=(128, 64, 64), re_tau=640.0, ma=0.060, steps=10000, stores=("f32",), bcs=("wfb", "bb"),
+               tau=None, stats_every=1, desc="single channel 128x64x64, Re_tau 640, FP32, 10k steps, FP64 plane statistics"),
+    "c3": dict(grid=(512, 128, 256), re_tau=2003.0, ma=0.069, steps=2000, stores=("f64", "f32", "f16", "bf16"),
+               bcs=("wfb",), tau=0.503, desc="single channel 512x128x256 (16.8M cells), Re_tau 2003, WFB, 2k steps"),
+    "c5": dict(grid=(2048, 512, 1024), re_tau=2003.0, ma=0.069, steps=500, stores=("f16", "f32"), bcs=("wfb",),
+               tau=None, desc="large channel 2048x512x1024 (1.07B cells), Re_tau 2003, WFB, 500 steps"),
+}
+
+
+def params(name, named_tau=False):
+    """Lattice parameters of a workload: dict(grid, tau0, fx, u_tau, ...)."""
+    w = WORKLOADS[name]
+    nx, ny, nz = w["grid"]
+    p = rule_m(ny, w["re_tau"], w["ma"])
+    if named_tau:
+        if w["tau"] is None:
+            raise ValueError("workload %s names no tau" % name)
+        p["tau0"] = w["tau"]
+        p["nu0"] = (w["tau"] - 0.5) / 3.0
+        p["yplus1"] = p["u_tau"] / p["nu0"]
+    p.update(grid=(nx, ny, nz), cs=CS, kappa=KAPPA, B=B, noise=0.05, seed=0)
+    return p
+
+
+# Block sizes (cells per block) of the odd and even step kernels used by the
+# benchmark and by the full-size parity tests, per store format.
+LAUNCH_TILES = {"f64": (256, 256), "f32": (256, 256), "f16": (256, 256), "bf16": (256, 256)}
+
+
+def sample_cells(grid, n, seed=0):
+    """Cell indices for sampled full-size checks: every corner and edge cell of
+    the wall rows' periodic seams plus n uniformly drawn cells."""
+    import numpy as np
+    nx, ny, nz = grid
+    rng = np.random.default_rng(seed)
+    xs = np.array([0, 1, nx - 2, nx - 1])
+    ys = np.array([0, 1, ny - 2, ny - 1])
+    zs = np.array([0, 1, nz - 2, nz - 1])
+    X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+    seam = (X + nx * (Y + ny * Z)).ravel()
+    rand = rng.integers(0, nx * ny * nz, n)
+    return np.unique(np.concatenate([seam, rand])).astype(np.int64)

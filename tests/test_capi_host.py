@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/lbmwf.h declares, validates arguments without touching a
+device, and its host Spalding inversion agrees with the oracle's."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbmwf.h")).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2009_04352_amd import _lib
+    return _lib
+
+
+def test_exports_every_declared_symbol(L):
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def test_create_validates_arguments(L):
+    lib = L.lib()
+    h = C.c_void_p()
+    bad = [((4, 1, 4), 0.6, 0.1, 0.41, 5.5, 0.0), ((0, 4, 4), 0.6, 0.1, 0.41, 5.5, 0.0),
+           ((4, 4, 4), 0.5, 0.1, 0.41, 5.5, 0.0), ((4, 4, 4), float("nan"), 0.1, 0.41, 5.5, 0.0),
+           ((4, 4, 4), 0.6, -0.1, 0.41, 5.5, 0.0), ((4, 4, 4), 0.6, 0.1, 0.0, 5.5, 0.0),
+           ((4, 4, 4), 0.6, 0.1, 0.41, 5.5, float("inf")), ((2048, 1024, 1024), 0.6, 0.1, 0.41, 5.5, 0.0)]
+    for g, *args in bad:
+        assert lib.lbm_create(C.byref(L.Grid(*g)), *args, C.byref(h)) == L.LBM_E_ARG
+        assert not h.value          # untouched on error
+        assert lib.lbm_last_error(None)
+    assert lib.lbm_create(C.byref(L.Grid(4, 4, 4)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(h)) == L.LBM_OK
+    try:
+        nb = C.c_size_t(0)
+        assert lib.lbm_required_bytes(h, C.byref(nb)) == 0 and nb.value == 19 * 64 * 8
+        assert lib.lbm_set_param(h, L.LBM_P_STORE, 2) == 0
+        assert lib.lbm_required_bytes(h, C.byref(nb)) == 0 and nb.value == 19 * 64 * 2
+        assert lib.lbm_set_param(h, L.LBM_P_STORE, 4) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_TILE_ODD, 96) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_NEWTON_MAXIT, 2.5) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_Y1, 0.0) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_BC, 1) == L.LBM_E_ARG       # read-only key
+        assert lib.lbm_set_boundary(h, 7) == L.LBM_E_ARG
+        v = C.c_double()
+        assert lib.lbm_get_param(h, L.LBM_P_TAU0, C.byref(v)) == 0 and v.value == 0.6
+        # nothing bound yet: stepping or observing is a state error, never a crash
+        assert lib.lbm_step(h, 1) == L.LBM_E_STATE
+        assert lib.lbm_init_spalding(h, 1e-3, 0.05, 0) == L.LBM_E_STATE
+        assert lib.lbm_moments(h, None, None, None, None) == L.LBM_E_STATE
+        assert lib.lbm_bind_storage(h, None, 10**6) == L.LBM_E_ARG
+        assert lib.lbm_bind_storage(h, C.c_void_p(256), 10) == L.LBM_E_ARG   # too small
+        assert b"too small" in lib.lbm_last_error(h)
+    finally:
+        lib.lbm_destroy(h)
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.lbm_status_str(code)
+    assert lib.lbm_status_str(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("yplus", [1e-3, 0.5, 5.0, 11.0, 31.3, 80.0, 640.0, 2003.0, 1e5])
+def test_host_spalding_matches_oracle(orc, yplus):
+    from paper_2009_04352_amd import spalding_uplus
+    up = spalding_uplus(yplus)
+    # the oracle evaluates the bracket of Eq. 16 without expm1: ~1e-14 relative at tiny y+
+    assert abs(up - orc.spalding_uplus(yplus)) <= 5e-14 * up
+    assert abs(orc.spalding_yplus(up) - yplus) <= 1e-12 * yplus
+
+
+def test_workload_parameters_match_oracle_mapping(orc):
+    from paper_2009_04352_amd import workloads as W
+    for name, w in W.WORKLOADS.items():
+        p = W.params(name)
+        q = orc.rule_m(w["grid"][1], w["re_tau"], w["ma"])
+        for k in ("u_tau", "nu0", "tau0", "fx", "yplus1"):
+            assert abs(p[k] - q[k]) <= 1e-13 * abs(q[k]), (name, k)

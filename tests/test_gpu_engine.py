@@ -1,0 +1,123 @@
+"""GPU checks of the launch machinery: graph replay equals eager launches,
+results do not depend on the block size or the XCD remap, checkpoint/resume
+is exact, and device-side failures surface with their step."""
+import numpy as np
+import pytest
+
+from gpu_common import random_state, weights
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_04352_amd as P
+    return P
+
+
+def _state(orc, grid, store, seed):
+    return random_state(orc, grid[::-1], store, np.random.default_rng(seed))
+
+
+@pytest.mark.parametrize("store", ("f64", "f32", "f16"))
+def test_graph_replay_equals_eager(P, orc, store):
+    grid = (130, 6, 5)
+    h0 = _state(orc, grid, store, 1)
+    out = []
+    for gs in (0, 8, 5):
+        ch = P.Channel(*grid, 0.51, cs=0.1, fx=1e-6, store=store, bc="wfb", graph_steps=gs, stats_every=3)
+        ch.set_state(h0)
+        for n in (3, 17, 8):       # chunks that start at both parities and stats phases
+            ch.step(n)
+        out.append((ch.get_state(), ch.stats_sums()[0]))
+    for s, st in out[1:]:
+        assert np.array_equal(s, out[0][0])
+        assert np.array_equal(st, out[0][1])
+
+
+@pytest.mark.parametrize("store", ("f64", "f32", "bf16"))
+def test_block_size_and_remap_invariance(P, orc, store):
+    grid = (200, 7, 6)
+    h0 = _state(orc, grid, store, 2)
+    ref = None
+    for tiles in ((64, 64), (128, 256), (256, 512), (512, 128)):
+        for remap in (0, 1):
+            ch = P.Channel(*grid, 0.505, cs=0.1, fx=1e-6, store=store, bc="wfb", tiles=tiles)
+            ch.set_param(7, remap)
+            ch.set_state(h0)
+            ch.step(9)
+            s = ch.get_state()
+            if ref is None:
+                ref = s
+            assert np.array_equal(s, ref), (tiles, remap)
+
+
+def test_autotune_picks_valid_tiles(P):
+    ch = P.Channel(256, 16, 16, 0.51, fx=1e-6, store="f32", bc="wfb")
+    t = ch.autotune(steps=4)
+    assert t[0] in (64, 128, 256, 512) and t[1] in (64, 128, 256, 512)
+    with pytest.raises(P.LbmError):
+        ch.init_spalding(1e-3)
+        ch.autotune()           # only before the state is initialised
+
+
+@pytest.mark.parametrize("k", (3, 4))
+def test_checkpoint_resume_is_exact(P, orc, k):
+    grid = (67, 5, 4)
+    h0 = _state(orc, grid, "f32", 5)
+    a = P.Channel(*grid, 0.51, cs=0.1, fx=1e-6, store="f32", bc="wfb")
+    a.set_state(h0)
+    a.step(10)
+    ref = a.get_state()
+    b = P.Channel(*grid, 0.51, cs=0.1, fx=1e-6, store="f32", bc="wfb")
+    b.set_state(h0)
+    b.step(k)
+    saved, steps = b.get_state(), b.steps
+    c = P.Channel(*grid, 0.51, cs=0.1, fx=1e-6, store="f32", bc="wfb")
+    c.set_state(saved, steps=steps)
+    c.step(10 - k)
+    assert c.steps == 10
+    assert np.array_equal(c.get_state(), ref)
+
+
+def test_nonfinite_is_reported_with_its_step(P, orc):
+    grid = (64, 4, 4)
+    h0 = _state(orc, grid, "f64", 6)
+    h0[5, 2, 1, 7] = np.nan
+    ch = P.Channel(*grid, 0.52, fx=0.0, store="f64", bc="bb")
+    ch.set_state(h0, steps=40)
+    ch.step(3)
+    st, first = ch.sync()
+    assert st == -5 and first == 41
+    with pytest.raises(P.LbmError):
+        ch.moments()
+
+
+def test_newton_cap_is_reported(P, orc):
+    grid = (64, 4, 4)
+    ch = P.Channel(*grid, 0.50001, cs=0.0, fx=0.0, store="f64", bc="wfb")
+    ch.set_param(2, 1)            # one Newton iteration cannot converge
+    h0 = _state(orc, grid, "f64", 7)
+    ch.set_state(h0)
+    ch.step(1)
+    st, first = ch.sync()
+    assert st == -6 and first == 1
+
+
+def test_argument_errors_do_not_touch_outputs(P):
+    ch = P.Channel(8, 4, 4, 0.6, store="f32")
+    with pytest.raises(P.LbmError):
+        ch.step(1)                 # not initialised
+    ch.init_spalding(1e-3)
+    out = np.full(19 * 2, 7.0)
+    import ctypes as C
+    from paper_2009_04352_amd import _lib as L
+    bad = np.array([0, 10**6], dtype=np.int64)
+    st = L.lib().lbm_get_state_cells(ch._h, 2, L.i64ptr(bad), L.dptr(out))
+    assert st == L.LBM_E_ARG and np.all(out == 7.0)
+    assert L.lib().lbm_step(ch._h, -1) == L.LBM_E_ARG
+    assert L.lib().lbm_set_param(ch._h, L.LBM_P_STORE, 0) == L.LBM_E_STATE
+    assert C is not None
