@@ -61,14 +61,15 @@ extern "C" {
 #define LBM_P_NEWTON_MAXIT 2  /* Newton iteration cap (default 100) */
 #define LBM_P_STATS_EVERY 3   /* sample plane statistics on steps t with t % k == 0; 0 = off (default) */
 #define LBM_P_STORE 4         /* LBM_STORE_*; settable only before lbm_bind_storage (default F64) */
-#define LBM_P_TILE_ODD 5      /* cells per block of the odd-step kernel: 64, 128, 256 or 512 */
-#define LBM_P_TILE_EVEN 6     /* cells per block of the even-step kernel */
+#define LBM_P_TILE_ODD 5      /* threads per block of the odd-step kernel: 64, 128, 256 or 512 */
+#define LBM_P_TILE_EVEN 6     /* threads per block of the even-step kernel */
 #define LBM_P_XCD_REMAP 7     /* 1: contiguous tile ranges per XCD (default), 0: identity */
 #define LBM_P_GRAPH_STEPS 8   /* steps per captured HIP graph chunk; 0 = launch eagerly (default 32) */
 #define LBM_P_BC 9            /* read-only here: the current boundary */
 #define LBM_P_TAU0 10         /* read-only: molecular relaxation time */
 #define LBM_P_FX 11           /* body force density along x; settable at any time */
 #define LBM_P_CS 12           /* Smagorinsky constant; settable at any time */
+#define LBM_P_VECTOR 13       /* cells per thread: 0 = auto (groups of 8 bytes), or 1, 2, 4 (group <= 8 bytes, divides nx) */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -165,11 +166,12 @@ int lbm_stats_reset(lbm_ctx* ctx);
 int lbm_stats_sums(lbm_ctx* ctx, double* out, int64_t* nsamples);
 int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
 
-/* Picks the block size of the odd and even step kernels by timing each
- * candidate for `steps` steps (>= 2) on the bound storage.  Valid only before
- * the state is initialised (it writes a rest state); afterwards the state is
- * undefined until lbm_init_* / lbm_set_state.  Synchronises.  tiles (may be
- * NULL) receives the chosen odd and even tile sizes. */
+/* Picks the block sizes of the odd and even step kernels and the cells per
+ * thread by timing each candidate for `steps` steps (>= 2) on the bound
+ * storage.  Valid only before the state is initialised (it writes the initial
+ * profile the body force implies); afterwards the state is undefined until
+ * lbm_init_* / lbm_set_state.  Synchronises.  tiles (may be NULL) receives
+ * three values: the odd and even block sizes and the cells per thread. */
 int lbm_autotune(lbm_ctx* ctx, int steps, int32_t* tiles);
 
 /* Spalding's law inverted on the host (Eq. 16): u+ for a given y+ >= 0. */
@@ -180,6 +182,11 @@ int lbm_spalding_uplus(double yplus, double kappa, double B, double* uplus);
  * same device code as the step.  Synchronises the default stream. */
 int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, double kappa, double B, double tol,
                          int32_t maxit, double* u_tau, int32_t* iterations);
+
+/* Round trip of n host floats through the store format's device codec, the
+ * same conversion code the step kernels use (narrowing rounds to nearest,
+ * ties to even): out[i] = decode(encode(in[i])).  Synchronises. */
+int lbm_codec_roundtrip(int store, int64_t n, const float* in, float* out);
 
 /* Streams `bytes` (a multiple of 16) from src to dst on the device with a
  * plain copy kernel; a probe of the achievable HBM bandwidth. */

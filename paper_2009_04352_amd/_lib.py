@@ -14,7 +14,8 @@ LBM_E_ARG, LBM_E_STATE, LBM_E_OOM, LBM_E_DEVICE, LBM_E_NONFINITE, LBM_E_NEWTON =
 LBM_BB, LBM_WFB, LBM_FREESLIP = 0, 1, 2
 LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2, 3
 (LBM_P_Y1, LBM_P_NEWTON_TOL, LBM_P_NEWTON_MAXIT, LBM_P_STATS_EVERY, LBM_P_STORE, LBM_P_TILE_ODD,
- LBM_P_TILE_EVEN, LBM_P_XCD_REMAP, LBM_P_GRAPH_STEPS, LBM_P_BC, LBM_P_TAU0, LBM_P_FX, LBM_P_CS) = range(13)
+ LBM_P_TILE_EVEN, LBM_P_XCD_REMAP, LBM_P_GRAPH_STEPS, LBM_P_BC, LBM_P_TAU0, LBM_P_FX, LBM_P_CS,
+ LBM_P_VECTOR) = range(14)
 
 # every symbol the header declares, with (restype, argtypes)
 _dp = C.POINTER(C.c_double)
@@ -54,6 +55,7 @@ SIGNATURES = {
     "lbm_spalding_uplus": (C.c_int, [C.c_double, C.c_double, C.c_double, _dp]),
     "lbm_device_wall_utau": (C.c_int, [C.c_int32, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                        C.c_double, C.c_int32, _dp, _i32p]),
+    "lbm_codec_roundtrip": (C.c_int, [C.c_int, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "lbm_copy_probe": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "lbm_status_str": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, [_vp]),

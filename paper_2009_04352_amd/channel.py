@@ -31,6 +31,15 @@ def device_wall_utau(U, y1, nu, kappa=0.41, B=5.5, tol=1e-14, maxit=100):
     return ut, it
 
 
+def codec_roundtrip(store, values):
+    """decode(encode(v)) through the store format's device codec (float32 in and out)."""
+    v = np.ascontiguousarray(values, dtype=np.float32)
+    out = np.empty_like(v)
+    fp = C.POINTER(C.c_float)
+    L.check(L.lib().lbm_codec_roundtrip(STORES[store], v.size, v.ctypes.data_as(fp), out.ctypes.data_as(fp)))
+    return out
+
+
 def copy_probe(dst, src, nbytes, stream=None):
     """Plain device copy of nbytes (multiple of 16) between two torch tensors."""
     import torch
@@ -43,7 +52,8 @@ class Channel:
     """A D3Q19 channel (x, z periodic, walls in y) advanced on the GPU."""
 
     def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
-                 device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False):
+                 device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False,
+                 vector=0):
         import torch
         self.lib = L.lib()
         self.shape = (nz, ny, nx)
@@ -62,6 +72,10 @@ class Channel:
         if tiles is not None:
             self._set(L.LBM_P_TILE_ODD, tiles[0])
             self._set(L.LBM_P_TILE_EVEN, tiles[1])
+            if len(tiles) > 2:
+                vector = tiles[2]
+        if vector:
+            self._set(L.LBM_P_VECTOR, vector)
         nbytes = C.c_size_t(0)
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value
@@ -107,9 +121,10 @@ class Channel:
         self._chk(self.lib.lbm_set_boundary(self._h, BOUNDARIES[bc] if isinstance(bc, str) else int(bc)))
 
     def autotune(self, steps=6):
-        t = (C.c_int32 * 2)()
+        """Returns (odd block size, even block size, cells per thread)."""
+        t = (C.c_int32 * 3)()
         self._chk(self.lib.lbm_autotune(self._h, int(steps), t))
-        self.tiles = (t[0], t[1])
+        self.tiles = (t[0], t[1], t[2])
         return self.tiles
 
     def init_spalding(self, u_tau, noise=0.05, seed=0):

@@ -44,6 +44,7 @@ struct lbm_ctx {
     int bc = kWFB;
     int stats_every = 0;
     int tile_odd = 256, tile_even = 256, xcd_remap = 1, graph_steps = 32;
+    int vw_req = 0;              // cells per thread requested; 0 = widest the store and nx allow
 
     void* h = nullptr;
     size_t bytes = 0;
@@ -97,11 +98,22 @@ struct DeviceGuard {
     }
 };
 
-int tiles_per_row(int nx, int tile) { return (nx + tile - 1) / tile; }
+int vector_width(const lbm_ctx* c)
+{
+    if (c->vw_req > 0 && step_vector_width_ok(c->store, c->nx, c->vw_req)) return c->vw_req;
+    return step_vector_width(c->store, c->nx);
+}
+
+// a tile is `tile` threads, each owning vw consecutive cells of one x-row
+int tiles_per_row(const lbm_ctx* c, int tile)
+{
+    const int cells = tile * vector_width(c);
+    return (c->nx + cells - 1) / cells;
+}
 
 long long ntiles_for(const lbm_ctx* c, int tile)
 {
-    return (long long)tiles_per_row(c->nx, tile) * c->ny * c->nz;
+    return (long long)tiles_per_row(c, tile) * c->ny * c->nz;
 }
 
 bool tile_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
@@ -121,7 +133,8 @@ StepArgs step_args(const lbm_ctx* c, bool odd)
     a.ny = c->ny;
     a.nz = c->nz;
     a.tile_x = odd ? c->tile_odd : c->tile_even;
-    a.ntx = tiles_per_row(c->nx, a.tile_x);
+    a.vw = vector_width(c);
+    a.ntx = tiles_per_row(c, a.tile_x);
     a.ntiles = (int)ntiles_for(c, a.tile_x);
     a.xcd_remap = c->xcd_remap;
     a.newton_maxit = c->newton_maxit;
@@ -135,7 +148,7 @@ StepArgs step_args(const lbm_ctx* c, bool odd)
     a.ekb = std::exp(-c->kappa * c->bconst);
     a.newton_tol = c->newton_tol;
     a.flags = c->dflags;
-    a.partials = c->dpart;
+    a.partials = nullptr;
     return a;
 }
 
@@ -173,10 +186,11 @@ hipError_t enqueue_steps(const lbm_ctx* c, hipStream_t s, int layout_s, long lon
         const long long t = t0 + 1 + i;
         const bool odd = (layout_s == 0);
         const bool st = sampled(c, t);
-        hipError_t e = launch_step(c->store, odd, c->bc, st, odd ? ao : ae, s);
+        StepArgs a = odd ? ao : ae;
+        if (st) a.partials = c->dpart;
+        hipError_t e = launch_step(c->store, odd, c->bc, a, s);
         if (e != hipSuccess) return e;
         if (st) {
-            const StepArgs& a = odd ? ao : ae;
             e = launch_stats_reduce(c->dpart, a.ntx, c->ny, c->nz, c->nx, c->dacc, s);
             if (e != hipSuccess) return e;
         }
@@ -393,6 +407,11 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
             if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
             c->xcd_remap = (int)v;
             break;
+        case LBM_P_VECTOR:
+            if (!integral || (v != 0.0 && !step_vector_width_ok(c->store, c->nx, (int)v)))
+                return fail(c, LBM_E_ARG, "cells per thread must be 0 (auto) or 1, 2, 4 with groups of at most 8 bytes dividing nx");
+            c->vw_req = (int)v;
+            break;
         case LBM_P_GRAPH_STEPS:
             if (!integral || v < 0 || v > 4096) return fail(c, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
             c->graph_steps = (int)v;
@@ -423,6 +442,7 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
         case LBM_P_TILE_ODD: *v = c->tile_odd; break;
         case LBM_P_TILE_EVEN: *v = c->tile_even; break;
         case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
+        case LBM_P_VECTOR: *v = vector_width(c); break;
         case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
         case LBM_P_BC: *v = c->bc; break;
         case LBM_P_TAU0: *v = c->tau0; break;
@@ -823,42 +843,53 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
     const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
     int st = lbm_init_spalding(c, ut, 0.05, 0);
     if (st != LBM_OK) return st;
-    const int cand[4] = {64, 128, 256, 512};
-    const int save_every = c->stats_every, save_graph = c->graph_steps;
-    c->stats_every = 0;
+    const int tcand[4] = {64, 128, 256, 512};
+    const int vcand[3] = {1, 2, 4};
     hipEvent_t ev[3];
     for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
-    float best_o = 1e30f, best_e = 1e30f;
-    int bo = c->tile_odd, be = c->tile_even;
+    // the odd and even kernels are timed separately; the group width is shared
+    float best = 1e30f;
+    int bo = c->tile_odd, be = c->tile_even, bv = vector_width(c);
     hipError_t err = hipSuccess;
-    for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-        c->tile_odd = c->tile_even = cand[k];
-        float to = 0.f, te = 0.f;
-        // one warm-up pair, then timed pairs
-        for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
-            const StepArgs ao = step_args(c, true), ae = step_args(c, false);
-            err = hipEventRecord(ev[0], c->stream);
-            if (err == hipSuccess) err = launch_step(c->store, true, c->bc, false, ao, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
-            if (err == hipSuccess) err = launch_step(c->store, false, c->bc, false, ae, c->stream);
-            if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
-            if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
-            float a = 0.f, b = 0.f;
-            if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
-            if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
-            if (r > 0) {
-                to += a;
-                te += b;
+    for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
+        if (!step_vector_width_ok(c->store, c->nx, vcand[iv])) continue;
+        c->vw_req = vcand[iv];
+        float bo_t = 1e30f, be_t = 1e30f;
+        int bo_k = 256, be_k = 256;
+        for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+            c->tile_odd = c->tile_even = tcand[k];
+            float to = 0.f, te = 0.f;
+            // one warm-up pair, then timed pairs
+            for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
+                const StepArgs ao = step_args(c, true), ae = step_args(c, false);
+                err = hipEventRecord(ev[0], c->stream);
+                if (err == hipSuccess) err = launch_step(c->store, true, c->bc, ao, c->stream);
+                if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
+                if (err == hipSuccess) err = launch_step(c->store, false, c->bc, ae, c->stream);
+                if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                float a = 0.f, b = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
+                if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
+                if (r > 0) {
+                    to += a;
+                    te += b;
+                }
             }
+            if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
+            if (te < be_t) { be_t = te; be_k = tcand[k]; }
         }
-        if (to < best_o) { best_o = to; bo = cand[k]; }
-        if (te < best_e) { best_e = te; be = cand[k]; }
+        if (bo_t + be_t < best) {
+            best = bo_t + be_t;
+            bo = bo_k;
+            be = be_k;
+            bv = vcand[iv];
+        }
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
-    c->stats_every = save_every;
-    c->graph_steps = save_graph;
     c->tile_odd = bo;
     c->tile_even = be;
+    c->vw_req = bv;
     c->initialized = false;
     drop_graphs(c);
     if (err != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
@@ -867,6 +898,7 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
     if (tiles) {
         tiles[0] = bo;
         tiles[1] = be;
+        tiles[2] = bv;
     }
     return LBM_OK;
 }
@@ -899,6 +931,24 @@ int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, doubl
     if (dut) (void)hipFree(dut);
     if (dit) (void)hipFree(dit);
     if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("device wall solve: ") + hipGetErrorString(e));
+    return LBM_OK;
+}
+
+int lbm_codec_roundtrip(int store, int64_t n, const float* in, float* out)
+{
+    if (store < 0 || store > 3 || n < 0 || (n > 0 && (!in || !out)))
+        return fail(nullptr, LBM_E_ARG, "bad argument");
+    if (n == 0) return LBM_OK;
+    float *din = nullptr, *dout = nullptr;
+    hipError_t e = hipMalloc((void**)&din, (size_t)n * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&dout, (size_t)n * sizeof(float));
+    if (e == hipSuccess) e = hipMemcpy(din, in, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_codec(store, din, dout, n, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+    if (din) (void)hipFree(din);
+    if (dout) (void)hipFree(dout);
+    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("codec round trip: ") + hipGetErrorString(e));
     return LBM_OK;
 }
 

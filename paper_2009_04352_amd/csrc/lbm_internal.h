@@ -16,13 +16,14 @@ struct DevFlags {
 
 enum Boundary { kBB = 0, kWFB = 1, kFreeSlip = 2 };
 
-// Parameters of one fused step launch.  One block processes one tile: tile_x
-// consecutive cells of one x-row (y, z).
+// Parameters of one fused step launch.  One block processes one tile:
+// tile_x * vw consecutive cells of one x-row (y, z).
 struct StepArgs {
     void* h;              // populations h_a = f_a - w_a, [a][z][y][x]
     long long n;          // cells
     int nx, ny, nz;
-    int tile_x;           // cells per tile (= threads per block)
+    int tile_x;           // threads per block; a tile is tile_x * vw consecutive cells of one x-row
+    int vw;               // cells per thread (1, 2 or 4): a group of vw * sizeof(store) <= 8 bytes
     int ntx;              // tiles per x-row
     int ntiles;           // tiles in the grid (= blocks)
     int xcd_remap;        // 1: give each XCD a contiguous range of tiles
@@ -36,7 +37,7 @@ struct StepArgs {
     double ekb;           // exp(-kappa B)
     double newton_tol;
     DevFlags* flags;
-    double* partials;     // [ntiles][7] statistics partial sums (sampled steps)
+    double* partials;     // [ntiles][7] statistics partial sums; nullptr on steps not sampled
 };
 
 struct ObsArgs {
@@ -57,7 +58,9 @@ struct ObsArgs {
 };
 
 // launchers (lbm_kernels.hip); each returns the launch status
-hipError_t launch_step(int store, bool odd, int bc, bool stats, const StepArgs& a, hipStream_t s);
+int step_vector_width(int store, int nx);
+bool step_vector_width_ok(int store, int nx, int vw);
+hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_stats_reduce(const double* partials, int ntx, int ny, int nz, int nx, double* acc, hipStream_t s);
 hipError_t launch_init_spalding(int store, void* h, long long n, int nx, int ny, int nz, const double* profile,
                                 double noise, unsigned long long seed, hipStream_t s);
@@ -70,6 +73,7 @@ hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s);
 hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int from_spec, int to_spec,
                            double* tmp, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t launch_codec(int store, const float* in, float* out, long long n, hipStream_t s);
 hipError_t launch_wall_utau(const double* U, int n, double y1, double nu, double kappa, double bconst, double tol,
                             int maxit, double* utau, int* iters, hipStream_t s);
 

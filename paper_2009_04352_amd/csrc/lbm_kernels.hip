@@ -168,36 +168,53 @@ struct Moments {
     R rho, ux, uy, uz;
 };
 
+// Reciprocal and square root: one hardware instruction in FP32 (about one ulp),
+// the IEEE operations in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
+// The pairs (a, a + 1) of opposite directions, a odd, used below with these
+// velocities (Table A-1).
+static_assert(kEx[1] == 1 && kEy[3] == 1 && kEz[5] == 1, "axis pairs");
+static_assert(kEx[7] == 1 && kEy[7] == 1 && kEz[7] == 0, "pair 7");
+static_assert(kEx[9] == 1 && kEy[9] == 0 && kEz[9] == 1, "pair 9");
+static_assert(kEx[11] == 0 && kEy[11] == 1 && kEz[11] == 1, "pair 11");
+static_assert(kEx[13] == 1 && kEy[13] == -1 && kEz[13] == 0, "pair 13");
+static_assert(kEx[15] == 1 && kEy[15] == 0 && kEz[15] == -1, "pair 15");
+static_assert(kEx[17] == 0 && kEy[17] == 1 && kEz[17] == -1, "pair 17");
+
 // Moments (Eq. 2, half-force shift), Smagorinsky relaxation time from the
 // non-equilibrium stress, BGK towards the second-order equilibrium and the
-// Guo force term, in place on h = f - w.
+// Guo force term, in place on h = f - w.  Opposite directions are handled as
+// pairs: with s = h_a + h_b and d = h_a - h_b the moments are sums of s or d,
+// the equilibrium splits into an even part w (drho + rho (4.5 (e.u)^2 - 1.5 u.u))
+// and an odd part 3 w rho e.u, and the force term into -3 u_x + 9 e_x e.u and
+// 3 e_x (per unit force along x).
 template <typename R>
 __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx)
 {
-    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
-    R sxx = R(0), syy = R(0), szz = R(0), sxy = R(0), sxz = R(0), syz = R(0);
+    R s[kQ], d[kQ];  // indexed by the odd member of each pair
+    R drho = f[0];
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
-        const R v = f[a];
-        drho += v;
-        if constexpr (kEx[a] == 1) jx += v;
-        if constexpr (kEx[a] == -1) jx -= v;
-        if constexpr (kEy[a] == 1) jy += v;
-        if constexpr (kEy[a] == -1) jy -= v;
-        if constexpr (kEz[a] == 1) jz += v;
-        if constexpr (kEz[a] == -1) jz -= v;
-        if constexpr (kEx[a] != 0) sxx += v;
-        if constexpr (kEy[a] != 0) syy += v;
-        if constexpr (kEz[a] != 0) szz += v;
-        if constexpr (kEx[a] * kEy[a] == 1) sxy += v;
-        if constexpr (kEx[a] * kEy[a] == -1) sxy -= v;
-        if constexpr (kEx[a] * kEz[a] == 1) sxz += v;
-        if constexpr (kEx[a] * kEz[a] == -1) sxz -= v;
-        if constexpr (kEy[a] * kEz[a] == 1) syz += v;
-        if constexpr (kEy[a] * kEz[a] == -1) syz -= v;
+        if constexpr (a % 2 == 1) {
+            s[a] = f[a] + f[a + 1];
+            d[a] = f[a] - f[a + 1];
+            drho += s[a];
+        }
     });
+    const R jx = ((d[1] + d[7]) + (d[9] + d[13])) + d[15];
+    const R jy = ((d[3] + d[7]) + (d[11] - d[13])) + d[17];
+    const R jz = ((d[5] + d[9]) + (d[11] - d[15])) - d[17];
+    const R sxx = ((s[1] + s[7]) + (s[9] + s[13])) + s[15];
+    const R syy = ((s[3] + s[7]) + (s[11] + s[13])) + s[17];
+    const R szz = ((s[5] + s[9]) + (s[11] + s[15])) + s[17];
+    const R sxy = s[7] - s[13], sxz = s[9] - s[15], syz = s[11] - s[17];
+
     const R rho = R(1) + drho;
-    const R inv = R(1) / rho;
+    const R inv = rcp(rho);
     const R ux = fmad(R(0.5), fx, jx) * inv, uy = jy * inv, uz = jz * inv;
     // Pi_neq = sum e e h - sum e e h_eq, with sum e e h_eq = drho/3 I + rho u u
     const R c3 = drho * R(1.0 / 3.0);
@@ -206,26 +223,43 @@ __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx
     const R pxy = fmad(-rux, uy, sxy), pxz = fmad(-rux, uz, sxz), pyz = fmad(-ruy, uz, syz);
     const R offd = fmad(pxy, pxy, fmad(pxz, pxz, pyz * pyz));
     const R pp = fmad(pxx, pxx, fmad(pyy, pyy, fmad(pzz, pzz, R(2) * offd)));
-    const R qn = sqrt(R(2) * pp);
-    const R taue = R(0.5) * (tau0 + sqrt(fmad(tau0, tau0, cs2_18 * qn * inv)));
-    const R om = R(1) / taue;
-    const R fc = fmad(R(-0.5), om, R(1)) * fx;  // (1 - 1/(2 tau_e)) Fx
+    const R qn = sqrt_r(R(2) * pp);
+    const R taue = R(0.5) * (tau0 + sqrt_r(fmad(tau0, tau0, cs2_18 * qn * inv)));
+    const R om = rcp(taue);
+    const R omh = R(0.5) - R(0.5) * om;          // (1 - omega) / 2
+    const R fc = fmad(R(-0.5), om, R(1)) * fx;   // (1 - 1/(2 tau_e)) Fx
     const R usq = R(1.5) * fmad(ux, ux, fmad(uy, uy, uz * uz));
+    const R m3ux = R(-3) * ux;
+
+    {   // rest population: e = 0
+        constexpr R w = weight<R>(0);
+        const R heq = w * fmad(rho, -usq, drho);
+        f[0] = fmad(-om, f[0] - heq, f[0]) + (w * fc) * m3ux;
+    }
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
-        R eu = R(0);
-        if constexpr (kEx[a] == 1) eu += ux;
-        if constexpr (kEx[a] == -1) eu -= ux;
-        if constexpr (kEy[a] == 1) eu += uy;
-        if constexpr (kEy[a] == -1) eu -= uy;
-        if constexpr (kEz[a] == 1) eu += uz;
-        if constexpr (kEz[a] == -1) eu -= uz;
-        constexpr R w = weight<R>(a);
-        const R t = fmad(eu, fmad(R(4.5), eu, R(3)), -usq);  // 3 e.u + 4.5 (e.u)^2 - 1.5 u.u
-        const R heq = w * fmad(rho, t, drho);
-        R force = R(-3) * ux;                                 // 3 (e - u) . F + 9 (e . u)(e . F), per unit Fx
-        if constexpr (kEx[a] != 0) force += fmad(R(9 * kEx[a]), eu, R(3 * kEx[a]));
-        f[a] = fmad(w * fc, force, fmad(-om, f[a] - heq, f[a]));
+        if constexpr (a % 2 == 1) {
+            constexpr int ex = kEx[a];
+            constexpr R w = weight<R>(a);
+            R eu = R(0);
+            if constexpr (kEx[a] == 1) eu = ux;
+            if constexpr (kEy[a] == 1) eu = (kEx[a] != 0) ? eu + uy : uy;
+            if constexpr (kEy[a] == -1) eu = eu - uy;
+            if constexpr (kEz[a] == 1) eu = (kEx[a] != 0 || kEy[a] != 0) ? eu + uz : uz;
+            if constexpr (kEz[a] == -1) eu = eu - uz;
+            const R hs = w * fmad(rho, fmad(R(4.5) * eu, eu, -usq), drho);   // even part of h_eq
+            const R hd = (R(3) * w) * rho * eu;                              // odd part of h_eq
+            R fs = m3ux;                                                     // even part of the force term
+            if constexpr (ex != 0) fs = fmad(R(9 * ex), eu, m3ux);
+            fs = (w * fc) * fs;
+            // half sum and half difference of the post-collision pair
+            const R S = fmad(omh, s[a], fmad(om, hs, fs));
+            R D;
+            if constexpr (ex != 0) D = fmad(omh, d[a], fmad(om, hd, (w * fc) * R(3 * ex)));
+            else D = fmad(omh, d[a], om * hd);
+            f[a] = S + D;
+            f[a + 1] = S - D;
+        }
     });
     return Moments<R>{rho, ux, uy, uz};
 }
@@ -248,133 +282,428 @@ __device__ __forceinline__ int wave_max(int v)
 
 constexpr int kMaxBlock = 512;
 
-template <typename S, bool ODD, bool SPEC, bool WFB, bool STATS>
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// A group of V consecutive populations of one direction, G = V * sizeof(T)
+// bytes (2, 4 or 8), held in the low bytes of a u32x2.  Groups that no other
+// thread touches move with non-temporal loads and stores (every slot is read
+// once and written once per step); single elements at tile edges, which
+// neighbouring blocks share cache lines with, stay cached.
+template <typename S, int V>
+struct Lane {
+    using T = typename S::T;
+    using R = typename S::R;
+    static constexpr int kBytes = (int)sizeof(T);
+    static constexpr int G = V * kBytes;
+    static_assert(G == 2 || G == 4 || G == 8, "a group is 2, 4 or 8 bytes");
+
+    template <bool NT>
+    __device__ __forceinline__ static u32x2 load(const T* p)
+    {
+        if constexpr (G == 8) {
+            if constexpr (NT) return __builtin_nontemporal_load((const u32x2*)p);
+            else return *(const u32x2*)p;
+        } else if constexpr (G == 4) {
+            if constexpr (NT) return u32x2{__builtin_nontemporal_load((const unsigned int*)p), 0u};
+            else return u32x2{*(const unsigned int*)p, 0u};
+        } else {
+            if constexpr (NT) return u32x2{(unsigned int)__builtin_nontemporal_load((const unsigned short*)p), 0u};
+            else return u32x2{(unsigned int)*(const unsigned short*)p, 0u};
+        }
+    }
+    template <bool NT>
+    __device__ __forceinline__ static void store(T* p, u32x2 v)
+    {
+        if constexpr (G == 8) {
+            if constexpr (NT) __builtin_nontemporal_store(v, (u32x2*)p);
+            else *(u32x2*)p = v;
+        } else if constexpr (G == 4) {
+            if constexpr (NT) __builtin_nontemporal_store(v.x, (unsigned int*)p);
+            else *(unsigned int*)p = v.x;
+        } else {
+            if constexpr (NT) __builtin_nontemporal_store((unsigned short)v.x, (unsigned short*)p);
+            else *(unsigned short*)p = (unsigned short)v.x;
+        }
+    }
+    // raw bits of one element (element sizes 2 and 4; groups of V >= 2)
+    __device__ __forceinline__ static unsigned int load_elem(const T* p)
+    {
+        if constexpr (kBytes == 4) return *(const unsigned int*)p;
+        else return (unsigned int)*(const unsigned short*)p;
+    }
+    __device__ __forceinline__ static void store_elem(T* p, unsigned int b)
+    {
+        if constexpr (kBytes == 4) *(unsigned int*)p = b;
+        else *(unsigned short*)p = (unsigned short)b;
+    }
+    __device__ __forceinline__ static unsigned int first(u32x2 v)
+    {
+        if constexpr (kBytes == 4) return v.x;
+        else return v.x & 0xffffu;
+    }
+    __device__ __forceinline__ static unsigned int last(u32x2 v)
+    {
+        if constexpr (kBytes == 4) return v.y;
+        else if constexpr (V == 4) return v.y >> 16;
+        else return v.x >> 16;
+    }
+    // the group holding only element b, as its last (first) element
+    __device__ __forceinline__ static u32x2 as_last(unsigned int b)
+    {
+        if constexpr (kBytes == 4) return u32x2{0u, b};
+        else if constexpr (V == 4) return u32x2{0u, b << 16};
+        else return u32x2{b << 16, 0u};
+    }
+    __device__ __forceinline__ static u32x2 as_first(unsigned int b) { return u32x2{b, 0u}; }
+    // [p, e0 .. e(V-2)]
+    __device__ __forceinline__ static u32x2 shift_in_left(u32x2 v, unsigned int p)
+    {
+        if constexpr (kBytes == 4) return u32x2{p, v.x};
+        else if constexpr (V == 4) return u32x2{(v.x << 16) | p, (v.y << 16) | (v.x >> 16)};
+        else return u32x2{(v.x << 16) | p, 0u};
+    }
+    // [e1 .. e(V-1), q]
+    __device__ __forceinline__ static u32x2 shift_in_right(u32x2 v, unsigned int q)
+    {
+        if constexpr (kBytes == 4) return u32x2{v.y, q};
+        else if constexpr (V == 4) return u32x2{(v.x >> 16) | (v.y << 16), (v.y >> 16) | (q << 16)};
+        else return u32x2{(v.x >> 16) | (q << 16), 0u};
+    }
+    // elements 1 .. V-1 of the group at p (the first one belongs to another block)
+    __device__ __forceinline__ static void store_tail(T* p, u32x2 v)
+    {
+        if constexpr (kBytes == 4) {
+            *(unsigned int*)(p + 1) = v.y;
+        } else if constexpr (V == 4) {
+            *(unsigned short*)(p + 1) = (unsigned short)(v.x >> 16);
+            *(unsigned int*)(p + 2) = v.y;
+        } else {
+            *(unsigned short*)(p + 1) = (unsigned short)(v.x >> 16);
+        }
+    }
+    // elements 0 .. V-2 of the group at p (the last one belongs to another block)
+    __device__ __forceinline__ static void store_head(T* p, u32x2 v)
+    {
+        if constexpr (kBytes == 4) {
+            *(unsigned int*)p = v.x;
+        } else if constexpr (V == 4) {
+            *(unsigned int*)p = v.x;
+            *(unsigned short*)(p + 2) = (unsigned short)(v.y & 0xffffu);
+        } else {
+            *(unsigned short*)p = (unsigned short)(v.x & 0xffffu);
+        }
+    }
+    __device__ __forceinline__ static R get(u32x2 v, int k)
+    {
+        if constexpr (kBytes == 8) {
+            return __hiloint2double((int)v.y, (int)v.x);
+        } else if constexpr (kBytes == 4) {
+            return __uint_as_float(k == 0 ? v.x : v.y);
+        } else {
+            const unsigned int word = (k < 2) ? v.x : v.y;
+            const unsigned short b = (unsigned short)((k & 1) ? (word >> 16) : (word & 0xffffu));
+            if constexpr (S::kind == kStoreBF16) return bf16_to_f32(b);
+            else return (float)__builtin_bit_cast(_Float16, b);
+        }
+    }
+    __device__ __forceinline__ static void set(u32x2& v, int k, R r)
+    {
+        if constexpr (kBytes == 8) {
+            v.x = (unsigned int)__double2loint(r);
+            v.y = (unsigned int)__double2hiint(r);
+        } else if constexpr (kBytes == 4) {
+            if (k == 0) v.x = __float_as_uint(r);
+            else v.y = __float_as_uint(r);
+        } else {
+            unsigned short b;
+            if constexpr (S::kind == kStoreBF16) b = __builtin_bit_cast(unsigned short, (__bf16)r);
+            else b = __builtin_bit_cast(unsigned short, (_Float16)r);
+            const unsigned int word = (k < 2) ? v.x : v.y;
+            const unsigned int nw = (k & 1) ? ((word & 0xffffu) | ((unsigned int)b << 16)) : ((word & 0xffff0000u) | b);
+            if (k < 2) v.x = nw;
+            else v.y = nw;
+        }
+    }
+};
+
+// Cells x0 .. x0 + V - 1 of one x-row owned by one thread.
+struct RowLanes {
+    int x0, nx;
+    bool active;
+    __device__ __forceinline__ unsigned wrapx(int x) const
+    {
+        return (unsigned)(x < 0 ? x + nx : (x >= nx ? x - nx : x));
+    }
+};
+
+// Directions with a streamwise component: the only ones whose odd-step source
+// and destination are shifted along x.  Each has an exchange slot in LDS.
+constexpr int kNX = 10;
+constexpr int xslot(int a)
+{
+    int j = 0;
+    for (int b = 0; b < kQ; ++b)
+        if (kEx[b] != 0) {
+            if (b == a) return j;
+            ++j;
+        }
+    return -1;
+}
+
+// The group [last element of nb, v0 .. v(V-2)] and [v1 .. v(V-1), first of nb].
+template <typename S, int V>
+__device__ __forceinline__ u32x2 join_left(u32x2 v, u32x2 nb)
+{
+    if constexpr (V == 1) return nb;
+    else return Lane<S, V>::shift_in_left(v, Lane<S, V>::last(nb));
+}
+template <typename S, int V>
+__device__ __forceinline__ u32x2 join_right(u32x2 v, u32x2 nb)
+{
+    if constexpr (V == 1) return nb;
+    else return Lane<S, V>::shift_in_right(v, Lane<S, V>::first(nb));
+}
+
+// One element read straight from a row, placed as the last (first) element of a group.
+template <typename S, int V>
+__device__ __forceinline__ u32x2 halo_as_last(const typename S::T* row, unsigned x)
+{
+    using Ln = Lane<S, V>;
+    if constexpr (V == 1) return Ln::template load<false>(row + x);
+    else return Ln::as_last(Ln::load_elem(row + x));
+}
+template <typename S, int V>
+__device__ __forceinline__ u32x2 halo_as_first(const typename S::T* row, unsigned x)
+{
+    using Ln = Lane<S, V>;
+    if constexpr (V == 1) return Ln::template load<false>(row + x);
+    else return Ln::as_first(Ln::load_elem(row + x));
+}
+
+// One time step for V consecutive cells per thread; a block owns one tile of
+// an x-row.  Wall rows (y = 0 and y = ny - 1) are uniform over a block, so
+// the wall logic never diverges.  Every global access is an aligned
+// V-element group.  In the odd step the x-shifted directions exchange their
+// groups through LDS: a thread takes the element it lacks from its neighbour
+// in the tile; when the tile is the whole row the neighbours wrap around
+// (periodic x) and no other access is needed, otherwise the tile's two edge
+// threads read (write) the single element beyond the tile directly.
+template <typename S, int V, bool ODD, bool SPEC, bool WFB, bool STATS>
 __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p)
 {
     using T = typename S::T;
     using R = typename S::R;
-    T* __restrict__ h = (T*)p.h;
+    using Ln = Lane<S, V>;
+    extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x]
+    T* h = (T*)p.h;
     const long long N = p.n;
     const int tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
     const int row = tile / p.ntx;
     const int xt = tile - row * p.ntx;
     const int y = row % p.ny;
     const int z = row / p.ny;
-    const int x = xt * p.tile_x + (int)threadIdx.x;
-    const bool active = x < p.nx;
-    const bool bot = (y == 0), top = (y == p.ny - 1);  // uniform over the block
+    const bool bot = (y == 0), top = (y == p.ny - 1);
+
+    const int t = (int)threadIdx.x;
+    const int nthr = (int)blockDim.x;
+    const int tile_start = xt * p.tile_x * V;
+    const int nact = min(p.tile_x * V, p.nx - tile_start) / V;  // threads holding cells
+    const bool whole = (p.ntx == 1);                             // the tile is the whole row
+    RowLanes L;
+    L.nx = p.nx;
+    L.x0 = tile_start + t * V;
+    L.active = t < nact;
+    const int lane = t & 63;
 
     const unsigned nx = (unsigned)p.nx, ny = (unsigned)p.ny;
-    const unsigned xm = (x == 0) ? nx - 1 : (unsigned)x - 1;
-    const unsigned xp = (x == p.nx - 1) ? 0u : (unsigned)x + 1;
     const unsigned zm = (z == 0) ? (unsigned)p.nz - 1 : (unsigned)z - 1;
     const unsigned zp = (z == p.nz - 1) ? 0u : (unsigned)z + 1;
-    // cell offset of (x + dx, y + dy, z + dz), x and z periodic; dy must stay inside
-    auto off = [&](int dx, int dy, int dz) -> unsigned {
-        const unsigned xx = dx < 0 ? xm : (dx > 0 ? xp : (unsigned)x);
+    // start of the x-row (y + dy, z + dz) of direction slot s; dy stays inside the channel
+    auto rowp = [&](int s, int dy, int dz) -> T* {
         const unsigned zz = dz < 0 ? zm : (dz > 0 ? zp : (unsigned)z);
-        return xx + nx * ((unsigned)(y + dy) + ny * zz);
+        return h + (long long)s * N + (long long)(nx * ((unsigned)(y + dy) + ny * zz));
+    };
+    auto ld = [&](const T* r) -> u32x2 { return L.active ? Ln::template load<true>(r + L.x0) : u32x2{0u, 0u}; };
+    auto st = [&](T* r, u32x2 v) {
+        if (L.active) Ln::template store<true>(r + L.x0, v);
     };
 
-    R f[kQ];
-    Moments<R> m{R(1), R(0), R(0), R(0)};
-    int iters = 0;
-    if (active) {
-        // a1/a2: gather (odd: pull from neighbours with wall reflections; even: own slots)
+    // a1/a2: gather.  Odd: pull from neighbours with wall reflections; even: own slots.
+    u32x2 w[kQ];
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int ey = kEy[a], ez = kEz[a];
+        if constexpr (ODD) {
+            const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+            if (from_wall) {
+                if constexpr (!SPEC || !is_tangential(a)) w[a] = ld(rowp(a, 0, 0));
+                else w[a] = ld(rowp(opp(mirror_y(a)), 0, -ez));
+            } else {
+                w[a] = ld(rowp(opp(a), -ey, -ez));
+            }
+        } else {
+            w[a] = ld(rowp(a, 0, 0));
+        }
+    });
+    if constexpr (ODD) {
+        // the x-shifted groups hold cells x0 .. x0 + V - 1 of the source row; shift by -e_x
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (kEx[a] != 0) xbuf[xslot(a) * nthr + t] = w[a];
+        });
+        __syncthreads();
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
-            if constexpr (ODD) {
+            if constexpr (ex != 0) {
                 const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
-                if (from_wall) {
-                    if constexpr (!SPEC || !is_tangential(a))
-                        f[a] = S::load(h + (long long)a * N + off(0, 0, 0));
-                    else
-                        f[a] = S::load(h + (long long)opp(mirror_y(a)) * N + off(-ex, 0, -ez));
-                } else {
-                    f[a] = S::load(h + (long long)opp(a) * N + off(-ex, -ey, -ez));
+                const bool shifted = !from_wall || (SPEC && is_tangential(a));
+                if (shifted && L.active) {
+                    const u32x2* xb = xbuf + xslot(a) * nthr;
+                    const T* src = from_wall ? rowp(opp(mirror_y(a)), 0, -ez) : rowp(opp(a), -ey, -ez);
+                    if constexpr (ex == 1) {  // needs the element at x0 - 1
+                        const u32x2 nb = t > 0 ? xb[t - 1] : (whole ? xb[nact - 1] : halo_as_last<S, V>(src, L.wrapx(L.x0 - 1)));
+                        w[a] = join_left<S, V>(w[a], nb);
+                    } else {                  // needs the element at x0 + V
+                        const u32x2 nb = t < nact - 1 ? xb[t + 1] : (whole ? xb[0] : halo_as_first<S, V>(src, L.wrapx(L.x0 + V)));
+                        w[a] = join_right<S, V>(w[a], nb);
+                    }
                 }
-            } else {
-                f[a] = S::load(h + (long long)a * N + off(0, 0, 0));
             }
         });
-        // a3: wall-function bounce at wall-adjacent cells (wave-uniform branch)
+    }
+
+    double sm[7] = {0, 0, 0, 0, 0, 0, 0};
+    int iters = 0;
+    bool bad = false, newton_fail = false;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        R f[kQ];
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            f[a] = Ln::get(w[a], k);
+        });
+        // a3: wall-function bounce at wall-adjacent cells
         if constexpr (WFB) {
             if (bot || top) {
+                int it = 0;
                 bool fail = false;
-                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.ekb, p.newton_tol, p.newton_maxit, iters, fail);
-                if (fail) {
-                    atomicOr(&p.flags->status, 2);
-                    atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
-                }
+                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.ekb, p.newton_tol, p.newton_maxit, it, fail);
+                iters = max(iters, it);
+                newton_fail = newton_fail || fail;
             }
         }
         // a4-a6: moments, Smagorinsky, BGK + body force
-        m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
-        if (!(m.rho > R(0)) || !(m.rho < R(INFINITY))) {
-            atomicOr(&p.flags->status, 1);
-            atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
+        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
+        bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            Ln::set(w[a], k, f[a]);
+        });
+        if constexpr (STATS) {
+            const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
+            sm[0] += ux; sm[1] += uy; sm[2] += uz;
+            sm[3] += ux * ux; sm[4] += uy * uy; sm[5] += uz * uz; sm[6] += ux * uy;
         }
-        // a7: store (odd: push to neighbours with wall reflections; even: own opposite slots)
+    }
+    if (L.active && (bad || newton_fail)) {
+        atomicOr(&p.flags->status, (bad ? 1 : 0) | (newton_fail ? 2 : 0));
+        atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
+    }
+
+    // a7: store.  Odd: push to neighbours with wall reflections; even: own opposite slots.
+    if constexpr (ODD) {
+        __syncthreads();  // every thread is done reading the exchange buffer
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (kEx[a] != 0) xbuf[xslot(a) * nthr + t] = w[a];
+        });
+        __syncthreads();
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
-            if constexpr (ODD) {
-                const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+            const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+            if constexpr (ex == 0) {
                 if (to_wall) {
-                    if constexpr (!SPEC || !is_tangential(a))
-                        S::store(h + (long long)opp(a) * N + off(0, 0, 0), f[a]);
-                    else
-                        S::store(h + (long long)mirror_y(a) * N + off(ex, 0, ez), f[a]);
+                    if constexpr (!SPEC || !is_tangential(a)) st(rowp(opp(a), 0, 0), w[a]);
+                    else st(rowp(mirror_y(a), 0, ez), w[a]);
                 } else {
-                    S::store(h + (long long)a * N + off(ex, ey, ez), f[a]);
+                    st(rowp(a, ey, ez), w[a]);
                 }
             } else {
-                S::store(h + (long long)opp(a) * N + off(0, 0, 0), f[a]);
+                if (to_wall && !(SPEC && is_tangential(a))) {
+                    st(rowp(opp(a), 0, 0), w[a]);  // bounce-back into the cell's own slot
+                } else if (L.active) {
+                    T* dst = to_wall ? rowp(mirror_y(a), 0, ez) : rowp(a, ey, ez);
+                    const u32x2* xb = xbuf + xslot(a) * nthr;
+                    if constexpr (ex == 1) {  // cell x goes to x + 1: the group at x0 starts with x0 - 1's value
+                        if (t > 0 || whole) {
+                            Ln::template store<true>(dst + L.x0, join_left<S, V>(w[a], xb[t > 0 ? t - 1 : nact - 1]));
+                        } else {
+                            if constexpr (V > 1) Ln::store_tail(dst + L.x0, Ln::shift_in_left(w[a], 0u));
+                        }
+                        if (!whole && t == nact - 1) {
+                            if constexpr (V == 1) Ln::template store<false>(dst + L.wrapx(L.x0 + 1), w[a]);
+                            else Ln::store_elem(dst + L.wrapx(L.x0 + V), Ln::last(w[a]));
+                        }
+                    } else {                  // cell x goes to x - 1: the group at x0 ends with x0 + V's value
+                        if (t < nact - 1 || whole) {
+                            Ln::template store<true>(dst + L.x0, join_right<S, V>(w[a], xb[t < nact - 1 ? t + 1 : 0]));
+                        } else {
+                            if constexpr (V > 1) Ln::store_head(dst + L.x0, Ln::shift_in_right(w[a], 0u));
+                        }
+                        if (!whole && t == 0) {
+                            if constexpr (V == 1) Ln::template store<false>(dst + L.wrapx(L.x0 - 1), w[a]);
+                            else Ln::store_elem(dst + L.wrapx(L.x0 - 1), Ln::first(w[a]));
+                        }
+                    }
+                }
             }
         });
+    } else {
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            st(rowp(opp(a), 0, 0), w[a]);
+        });
     }
+
     if constexpr (WFB) {
         if (bot || top) {
-            const int mx = wave_max(iters);
-            if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
+            const int mx = wave_max(L.active ? iters : 0);
+            if (lane == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
         }
     }
-    // a8: plane statistics of the sampled velocity, FP64, fixed order
+    // a8: plane statistics of the sampled velocity, FP64, fixed order (sampled steps only)
     if constexpr (STATS) {
         __shared__ double red[kMaxBlock / 64][7];
-        double v[7];
-        const double ux = active ? (double)m.ux : 0.0, uy = active ? (double)m.uy : 0.0,
-                     uz = active ? (double)m.uz : 0.0;
-        v[0] = ux; v[1] = uy; v[2] = uz;
-        v[3] = ux * ux; v[4] = uy * uy; v[5] = uz * uz; v[6] = ux * uy;
-        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+        const int wv = t >> 6;
 #pragma unroll
         for (int k = 0; k < 7; ++k) {
-            const double s = wave_sum(v[k]);
-            if (ln == 0) red[wv][k] = s;
+            const double s = wave_sum(L.active ? sm[k] : 0.0);
+            if (lane == 0) red[wv][k] = s;
         }
         __syncthreads();
-        if (threadIdx.x < 7) {
+        if (t < 7) {
             double s = 0.0;
-            const int nw = (blockDim.x + 63) >> 6;
-            for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
-            p.partials[(long long)tile * 7 + threadIdx.x] = s;
+            const int nw = (nthr + 63) >> 6;
+            for (int q = 0; q < nw; ++q) s += red[q][t];
+            p.partials[(long long)tile * 7 + t] = s;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) p.flags->cnt[ODD ? 0 : 1] = p.flags->cnt[ODD ? 1 : 0] + 1;
+    if (blockIdx.x == 0 && t == 0) p.flags->cnt[ODD ? 0 : 1] = p.flags->cnt[ODD ? 1 : 0] + 1;
 }
 
-template <typename S, bool ODD>
-static hipError_t launch_step_bc(int bc, bool stats, const StepArgs& a, hipStream_t s)
+template <typename S, int V, bool ODD>
+static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
-#define LBM_STEP(SPEC, WFB)                                                                     \
-    do {                                                                                        \
-        if (stats)                                                                              \
-            hipLaunchKernelGGL((k_step<S, ODD, SPEC, WFB, true>), grid, block, 0, s, a);        \
-        else                                                                                    \
-            hipLaunchKernelGGL((k_step<S, ODD, SPEC, WFB, false>), grid, block, 0, s, a);       \
+    const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
+#define LBM_STEP(SPEC, WFB)                                                                        \
+    do {                                                                                           \
+        if (a.partials)                                                                            \
+            hipLaunchKernelGGL((k_step<S, V, ODD, SPEC, WFB, true>), grid, block, lds, s, a);     \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_step<S, V, ODD, SPEC, WFB, false>), grid, block, lds, s, a);    \
     } while (0)
     if (bc == kBB) LBM_STEP(false, false);
     else if (bc == kWFB) LBM_STEP(true, true);
@@ -383,20 +712,46 @@ static hipError_t launch_step_bc(int bc, bool stats, const StepArgs& a, hipStrea
     return hipGetLastError();
 }
 
-template <typename S>
-static hipError_t launch_step_s(bool odd, int bc, bool stats, const StepArgs& a, hipStream_t s)
+template <typename S, int V>
+static hipError_t launch_step_v(bool odd, int bc, const StepArgs& a, hipStream_t s)
 {
-    return odd ? launch_step_bc<S, true>(bc, stats, a, s) : launch_step_bc<S, false>(bc, stats, a, s);
+    return odd ? launch_step_bc<S, V, true>(bc, a, s) : launch_step_bc<S, V, false>(bc, a, s);
 }
 
-hipError_t launch_step(int store, bool odd, int bc, bool stats, const StepArgs& a, hipStream_t s)
+template <typename S>
+static hipError_t launch_step_s(int vw, bool odd, int bc, const StepArgs& a, hipStream_t s)
 {
-    if (a.tile_x < 1 || a.tile_x > kMaxBlock || a.ntiles < 1) return hipErrorInvalidValue;
+    constexpr int kB = (int)sizeof(typename S::T);
+    if (vw == 1) return launch_step_v<S, 1>(odd, bc, a, s);
+    if constexpr (kB <= 4)
+        if (vw == 2) return launch_step_v<S, 2>(odd, bc, a, s);
+    if constexpr (kB == 2)
+        if (vw == 4) return launch_step_v<S, 4>(odd, bc, a, s);
+    return hipErrorInvalidValue;
+}
+
+// Largest group width the store and the row length allow: 8-byte groups.
+int step_vector_width(int store, int nx)
+{
+    int vw = 8 / store_bytes(store);
+    while (vw > 1 && nx % vw != 0) vw /= 2;
+    return vw;
+}
+
+bool step_vector_width_ok(int store, int nx, int vw)
+{
+    return vw >= 1 && vw * store_bytes(store) <= 8 && (vw & (vw - 1)) == 0 && nx % vw == 0;
+}
+
+hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s)
+{
+    if (a.tile_x < 64 || a.tile_x > kMaxBlock || (a.tile_x & 63) || a.ntiles < 1) return hipErrorInvalidValue;
+    if (!step_vector_width_ok(store, a.nx, a.vw)) return hipErrorInvalidValue;
     switch (store) {
-        case kStoreF64: return launch_step_s<StoreF64>(odd, bc, stats, a, s);
-        case kStoreF32: return launch_step_s<StoreF32>(odd, bc, stats, a, s);
-        case kStoreF16: return launch_step_s<StoreF16>(odd, bc, stats, a, s);
-        case kStoreBF16: return launch_step_s<StoreBF16>(odd, bc, stats, a, s);
+        case kStoreF64: return launch_step_s<StoreF64>(a.vw, odd, bc, a, s);
+        case kStoreF32: return launch_step_s<StoreF32>(a.vw, odd, bc, a, s);
+        case kStoreF16: return launch_step_s<StoreF16>(a.vw, odd, bc, a, s);
+        case kStoreBF16: return launch_step_s<StoreBF16>(a.vw, odd, bc, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -687,6 +1042,24 @@ __global__ __launch_bounds__(256) void k_wall_utau(const double* __restrict__ U,
     iters[i] = it;
 }
 
+// Store-format round trip through the same group codec the step kernels use:
+// out[i] = decode(encode(in[i])), groups of the widest width for the format.
+template <typename S>
+__global__ __launch_bounds__(256) void k_codec(const float* __restrict__ in, float* __restrict__ out, long long n)
+{
+    constexpr int V = 8 / (int)sizeof(typename S::T);
+    using Ln = Lane<S, V>;
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g * V >= n) return;
+    u32x2 w{0u, 0u};
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+        if (g * V + k < n) Ln::set(w, k, (typename S::R)in[g * V + k]);
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+        if (g * V + k < n) out[g * V + k] = (float)Ln::get(w, k);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <template <typename> class K, typename... Args>
@@ -707,6 +1080,7 @@ template <typename S> struct SetK { static constexpr auto fn = k_set_state<S>; }
 template <typename S> struct GetK { static constexpr auto fn = k_get_state<S>; };
 template <typename S> struct ObsK { static constexpr auto fn = k_observe<S>; };
 template <typename S> struct RelK { static constexpr auto fn = k_relayout<S>; };
+template <typename S> struct CodecK { static constexpr auto fn = k_codec<S>; };
 
 static dim3 blocks_for(long long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
@@ -749,6 +1123,13 @@ hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int 
     if (e != hipSuccess) return e;
     return dispatch_store<RelK>(store, blocks_for(m, 256), dim3(256), s, h, n, nx, ny, nz, from_spec, to_spec, tmp,
                                 1);
+}
+
+hipError_t launch_codec(int store, const float* in, float* out, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    // one thread per group; n threads cover the narrowest (one-element) groups
+    return dispatch_store<CodecK>(store, blocks_for(n, 256), dim3(256), s, in, out, n);
 }
 
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)

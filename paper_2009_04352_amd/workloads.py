@@ -55,9 +55,11 @@ def params(name, named_tau=False):
     return p
 
 
-# Block sizes (cells per block) of the odd and even step kernels used by the
-# benchmark and by the full-size parity tests, per store format.
-LAUNCH_TILES = {"f64": (256, 256), "f32": (256, 256), "f16": (256, 256), "bf16": (256, 256)}
+# Launch shapes used by the benchmark and by the full-size parity tests, per
+# store format: (threads per block of the odd kernel, of the even kernel,
+# cells per thread).  Measured on the 512 x 128 x 256 channel: a block covers a
+# whole x-row with 8-byte groups per thread.
+LAUNCH_TILES = {"f64": (512, 512, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)}
 
 
 def sample_cells(grid, n, seed=0):
