@@ -192,6 +192,50 @@ int lbm_codec_roundtrip(int store, int64_t n, const float* in, float* out);
  * plain copy kernel; a probe of the achievable HBM bandwidth. */
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent channels (own grid, tau, Cs, Fx and
+ * boundary each) advanced together, one launch per time step over the tiles
+ * of every instance (and HIP-graph chunks of such launches).  Instances share
+ * the store format, block sizes, cells per thread, stream and one pooled
+ * storage buffer; instance i's populations start at a 256-byte aligned
+ * offset in the order of creation.  Each instance evolves exactly as the same
+ * channel stepped alone with the same launch shape.  Plane statistics are not
+ * sampled in batches.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch lbm_batch;
+
+/* n >= 1 instances: grids[i], tau[i], Cs[i], Fx[i] and bc[i] (LBM_BB, LBM_WFB
+ * or LBM_FREESLIP) as for lbm_create; kappa and B shared.  LBM_E_ARG names
+ * the first bad instance in lbm_batch_last_error(NULL); *out untouched on error. */
+int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const double* Cs, const double* Fx,
+                     const int32_t* bc, double kappa, double B, lbm_batch** out);
+void lbm_batch_destroy(lbm_batch* batch);
+/* Keys LBM_P_STORE (before binding), LBM_P_TILE_ODD, LBM_P_TILE_EVEN,
+ * LBM_P_VECTOR (0 = the widest group every instance allows), LBM_P_XCD_REMAP,
+ * LBM_P_GRAPH_STEPS, and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT
+ * applied to every instance. */
+int lbm_batch_set_param(lbm_batch* batch, int key, double value);
+/* Sum over instances of their required bytes, each rounded up to 256. */
+int lbm_batch_required_bytes(const lbm_batch* batch, size_t* bytes);
+/* Caller-owned device memory, 256-byte aligned, at least the required bytes. */
+int lbm_batch_bind_storage(lbm_batch* batch, void* dev_ptr, size_t bytes);
+int lbm_batch_set_stream(lbm_batch* batch, void* hip_stream);
+/* lbm_init_spalding for every instance: u_tau[i], seeds[i], shared noise. */
+int lbm_batch_init_spalding(lbm_batch* batch, const double* u_tau, double noise, const uint64_t* seeds);
+/* Advances every instance n >= 0 steps.  Asynchronous. */
+int lbm_batch_step(lbm_batch* batch, int64_t n);
+/* Synchronises; reports the first instance (and its first step) whose device
+ * status is set, else LBM_OK.  Either pointer may be NULL. */
+int lbm_batch_sync(lbm_batch* batch, int64_t* first_bad_step, int32_t* first_bad_instance);
+/* Instance i as a context for observation (lbm_moments, lbm_wall_shear,
+ * lbm_get_state, ...); stepping, setting state or parameters through it
+ * returns LBM_E_STATE.  Owned by the batch.  NULL when i is out of range. */
+lbm_ctx* lbm_batch_instance(lbm_batch* batch, int32_t i);
+/* As lbm_autotune, over the batched launch; tiles receives the odd and even
+ * block sizes and the cells per thread. */
+int lbm_batch_autotune(lbm_batch* batch, int steps, int32_t* tiles);
+const char* lbm_batch_last_error(const lbm_batch* batch);
+
 const char* lbm_status_str(int status);
 /* Text of the last error of ctx (valid until the next call on ctx), or of the
  * last error of a call without a context when ctx is NULL. */

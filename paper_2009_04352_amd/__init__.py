@@ -7,5 +7,5 @@ include/lbmwf.h); this package only marshals arguments and provides device
 memory and streams through PyTorch.
 """
 from ._lib import LbmError, lib  # noqa: F401
-from .channel import (BOUNDARIES, STORES, Channel, codec_roundtrip, copy_probe, device_wall_utau,  # noqa: F401
+from .channel import (BOUNDARIES, STORES, Batch, Channel, codec_roundtrip, copy_probe, device_wall_utau,  # noqa: F401
                       spalding_uplus)

@@ -57,6 +57,19 @@ SIGNATURES = {
                                        C.c_double, C.c_int32, _dp, _i32p]),
     "lbm_codec_roundtrip": (C.c_int, [C.c_int, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
     "lbm_copy_probe": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "lbm_batch_create": (C.c_int, [C.c_int32, C.POINTER(Grid), _dp, _dp, _dp, _i32p, C.c_double, C.c_double,
+                                   C.POINTER(_vp)]),
+    "lbm_batch_destroy": (None, [_vp]),
+    "lbm_batch_set_param": (C.c_int, [_vp, C.c_int, C.c_double]),
+    "lbm_batch_required_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "lbm_batch_bind_storage": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "lbm_batch_set_stream": (C.c_int, [_vp, _vp]),
+    "lbm_batch_init_spalding": (C.c_int, [_vp, _dp, C.c_double, C.POINTER(C.c_uint64)]),
+    "lbm_batch_step": (C.c_int, [_vp, C.c_int64]),
+    "lbm_batch_sync": (C.c_int, [_vp, _i64p, _i32p]),
+    "lbm_batch_instance": (_vp, [_vp, C.c_int32]),
+    "lbm_batch_autotune": (C.c_int, [_vp, C.c_int, _i32p]),
+    "lbm_batch_last_error": (C.c_char_p, [_vp]),
     "lbm_status_str": (C.c_char_p, [C.c_int]),
     "lbm_last_error": (C.c_char_p, [_vp]),
 }
@@ -89,6 +102,12 @@ class LbmError(RuntimeError):
 def check(code, ctx=None):
     if code != LBM_OK:
         raise LbmError(code, lib().lbm_last_error(ctx).decode())
+    return code
+
+
+def check_batch(code, batch=None):
+    if code != LBM_OK:
+        raise LbmError(code, lib().lbm_batch_last_error(batch).decode())
     return code
 
 

@@ -196,3 +196,102 @@ class Channel:
         ns = C.c_int64(0)
         self._chk(self.lib.lbm_stats_get(self._h, L.dptr(out), C.byref(ns)))
         return out.reshape(self.ny, 8), ns.value
+
+
+class _InstanceView(Channel):
+    """Observation handle on one instance of a Batch (owned by the batch)."""
+
+    def __init__(self, batch, i, nx, ny, nz, store):
+        self.lib = L.lib()
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.ncell = nx * ny * nz
+        self.store = store
+        self._h = C.c_void_p(self.lib.lbm_batch_instance(batch._h, i))
+        self._batch = batch  # keeps the batch (and its storage) alive
+
+    def close(self):
+        self._h = C.c_void_p()
+
+
+class Batch:
+    """Independent channels advanced together: one launch per step over the
+    tiles of every instance.  specs: list of dicts with keys nx, ny, nz, tau,
+    cs, fx, bc."""
+
+    def __init__(self, specs, kappa=0.41, B=5.5, store="f32", device="cuda", stream=None, tiles=None,
+                 graph_steps=None, vector=0):
+        import torch
+        self.lib = L.lib()
+        n = len(specs)
+        grids = (L.Grid * n)(*[L.Grid(s["nx"], s["ny"], s["nz"]) for s in specs])
+        arr = lambda k: np.ascontiguousarray([float(s[k]) for s in specs])
+        self._tau, self._cs, self._fx = arr("tau"), arr("cs"), arr("fx")
+        bcs = np.ascontiguousarray([BOUNDARIES[s["bc"]] if isinstance(s["bc"], str) else int(s["bc"]) for s in specs],
+                                   dtype=np.int32)
+        h = C.c_void_p()
+        L.check_batch(self.lib.lbm_batch_create(n, grids, L.dptr(self._tau), L.dptr(self._cs), L.dptr(self._fx),
+                                                bcs.ctypes.data_as(C.POINTER(C.c_int32)), kappa, B, C.byref(h)))
+        self._h = h
+        self.specs = specs
+        self.n = n
+        self.store = store
+        self._set(L.LBM_P_STORE, STORES[store])
+        if graph_steps is not None:
+            self._set(L.LBM_P_GRAPH_STEPS, graph_steps)
+        if tiles is not None:
+            self._set(L.LBM_P_TILE_ODD, tiles[0])
+            self._set(L.LBM_P_TILE_EVEN, tiles[1])
+            if len(tiles) > 2:
+                vector = tiles[2]
+        if vector:
+            self._set(L.LBM_P_VECTOR, vector)
+        nbytes = C.c_size_t(0)
+        L.check_batch(self.lib.lbm_batch_required_bytes(self._h, C.byref(nbytes)), self._h)
+        self.nbytes = nbytes.value
+        self.device = torch.device(device)
+        self.storage = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        L.check_batch(self.lib.lbm_batch_bind_storage(self._h, C.c_void_p(self.storage.data_ptr()), self.nbytes),
+                      self._h)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        L.check_batch(self.lib.lbm_batch_set_stream(self._h, C.c_void_p(self.stream.cuda_stream)), self._h)
+        self.ncell = sum(s["nx"] * s["ny"] * s["nz"] for s in specs)
+
+    def _set(self, key, value):
+        L.check_batch(self.lib.lbm_batch_set_param(self._h, key, float(value)), self._h)
+
+    def autotune(self, steps=6):
+        t = (C.c_int32 * 3)()
+        L.check_batch(self.lib.lbm_batch_autotune(self._h, int(steps), t), self._h)
+        return (t[0], t[1], t[2])
+
+    def init_spalding(self, u_tau, noise=0.05, seeds=None):
+        ut = np.ascontiguousarray(u_tau, dtype=np.float64)
+        sd = np.ascontiguousarray(seeds if seeds is not None else np.arange(self.n), dtype=np.uint64)
+        L.check_batch(self.lib.lbm_batch_init_spalding(self._h, L.dptr(ut), float(noise),
+                                                       sd.ctypes.data_as(C.POINTER(C.c_uint64))), self._h)
+
+    def step(self, n=1):
+        L.check_batch(self.lib.lbm_batch_step(self._h, int(n)), self._h)
+
+    def sync(self):
+        """Returns (status, first bad step, first bad instance)."""
+        fb, fi = C.c_int64(-1), C.c_int32(-1)
+        st = self.lib.lbm_batch_sync(self._h, C.byref(fb), C.byref(fi))
+        return st, fb.value, fi.value
+
+    def instance(self, i):
+        s = self.specs[i]
+        return _InstanceView(self, i, s["nx"], s["ny"], s["nz"], self.store)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lbm_batch_destroy(self._h)
+            self._h = C.c_void_p()
+        self.storage = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

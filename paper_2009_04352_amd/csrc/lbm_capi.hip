@@ -67,6 +67,7 @@ struct lbm_ctx {
 
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::string err;
+    bool batch_member = false;   // stepped by its batch; observation only
 };
 
 namespace {
@@ -104,16 +105,12 @@ int vector_width(const lbm_ctx* c)
     return step_vector_width(c->store, c->nx);
 }
 
-// a tile is `tile` threads, each owning vw consecutive cells of one x-row
-int tiles_per_row(const lbm_ctx* c, int tile)
+// row segments (x segments times rows) of the statistics partial sums
+long long segments_for(const lbm_ctx* c, int tile)
 {
-    const int cells = tile * vector_width(c);
-    return (c->nx + cells - 1) / cells;
-}
-
-long long ntiles_for(const lbm_ctx* c, int tile)
-{
-    return (long long)tiles_per_row(c, tile) * c->ny * c->nz;
+    StepArgs g{};
+    step_geometry(c->nx, c->ny, c->nz, tile, vector_width(c), g);
+    return (long long)g.ntx * c->ny * c->nz;
 }
 
 bool tile_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
@@ -132,10 +129,9 @@ StepArgs step_args(const lbm_ctx* c, bool odd)
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
-    a.tile_x = odd ? c->tile_odd : c->tile_even;
-    a.vw = vector_width(c);
-    a.ntx = tiles_per_row(c, a.tile_x);
-    a.ntiles = (int)ntiles_for(c, a.tile_x);
+    step_geometry(c->nx, c->ny, c->nz, odd ? c->tile_odd : c->tile_even, vector_width(c), a);
+    a.tile_begin = 0;
+    a.bc = c->bc;
     a.xcd_remap = c->xcd_remap;
     a.newton_maxit = c->newton_maxit;
     a.tau0 = c->tau0;
@@ -213,7 +209,7 @@ void advance_bookkeeping(lbm_ctx* c, long long len)
 int ensure_partials(lbm_ctx* c)
 {
     if (c->stats_every <= 0) return LBM_OK;
-    const size_t need = (size_t)std::max(ntiles_for(c, c->tile_odd), ntiles_for(c, c->tile_even));
+    const size_t need = (size_t)std::max(segments_for(c, c->tile_odd), segments_for(c, c->tile_even));
     if (need <= c->part_cap) return LBM_OK;
     drop_graphs(c);
     if (c->dpart) (void)hipFree(c->dpart);
@@ -374,6 +370,7 @@ void lbm_destroy(lbm_ctx* c)
 int lbm_set_param(lbm_ctx* c, int key, double v)
 {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's parameters are set through its batch");
     if (!std::isfinite(v)) return fail(c, LBM_E_ARG, "parameter value must be finite");
     const bool integral = (v == std::floor(v));
     switch (key) {
@@ -497,6 +494,7 @@ int lbm_set_stream(lbm_ctx* c, void* s)
 int lbm_set_boundary(lbm_ctx* c, int bc)
 {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's boundary is fixed at batch creation");
     if (bc != LBM_BB && bc != LBM_WFB && bc != LBM_FREESLIP) return fail(c, LBM_E_ARG, "unknown boundary");
     DeviceGuard dg(c->dev);
     c->bc = bc;
@@ -504,9 +502,17 @@ int lbm_set_boundary(lbm_ctx* c, int bc)
     return fix_layout(c);
 }
 
+static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t seed);
+
 int lbm_init_spalding(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
 {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
+    return init_spalding_impl(c, u_tau, noise, seed);
+}
+
+static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
+{
     if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
     if (!std::isfinite(u_tau) || u_tau < 0.0 || !std::isfinite(noise) || noise < 0.0 || noise >= 1.0)
         return fail(c, LBM_E_ARG, "need 0 <= u_tau, 0 <= noise < 1");
@@ -534,6 +540,7 @@ int lbm_init_spalding(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
 int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
 {
     if (!c || !in) return fail(c, LBM_E_ARG, "null argument");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's state is set through its batch");
     if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
     if (steps < 0) return fail(c, LBM_E_ARG, "steps must be >= 0");
     DeviceGuard dg(c->dev);
@@ -627,6 +634,7 @@ int lbm_step(lbm_ctx* c, int64_t n)
 {
     int st = check_ready(c);
     if (st != LBM_OK) return st;
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is stepped by lbm_batch_step");
     if (n < 0) return fail(c, LBM_E_ARG, "n must be >= 0");
     if (n == 0) return LBM_OK;
     DeviceGuard dg(c->dev);
@@ -835,13 +843,14 @@ int lbm_stats_get(lbm_ctx* c, double* out, int64_t* nsamples)
 int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
 {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch is tuned with lbm_batch_autotune");
     if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
     if (c->initialized) return fail(c, LBM_E_STATE, "autotune runs before the state is initialised");
     if (steps < 2) return fail(c, LBM_E_ARG, "steps must be >= 2");
     DeviceGuard dg(c->dev);
     // a representative state: the initial profile the body force implies
     const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
-    int st = lbm_init_spalding(c, ut, 0.05, 0);
+    int st = init_spalding_impl(c, ut, 0.05, 0);
     if (st != LBM_OK) return st;
     const int tcand[4] = {64, 128, 256, 512};
     const int vcand[3] = {1, 2, 4};
@@ -959,5 +968,441 @@ int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* s)
     if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
     return LBM_OK;
 }
+
+}  // extern "C"
+
+// ================================================================ batches
+
+struct lbm_batch {
+    int n = 0;
+    std::vector<lbm_ctx*> inst;
+    int store = kStoreF64;
+    int tile_odd = 256, tile_even = 256, vw_req = 0, xcd_remap = 1, graph_steps = 32;
+    void* h = nullptr;
+    size_t bytes = 0;
+    int dev = -1;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::vector<size_t> offset;      // byte offset of each instance's populations
+    std::vector<StepArgs> tab[2];    // [even, odd] per-instance launch parameters
+    StepArgs* dtab[2] = {nullptr, nullptr};
+    int* dmap[2] = {nullptr, nullptr};
+    int ntiles[2] = {0, 0};
+    bool tables_ready = false;
+    bool initialized = false;
+    long long steps = 0;
+    int layout_s = 0;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::string err;
+};
+
+namespace {
+
+int bfail(lbm_batch* b, int code, const std::string& msg)
+{
+    if (b) b->err = msg;
+    else g_err = msg;
+    return code;
+}
+
+#define LBM_BHIP(b, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return bfail((b), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int batch_width(const lbm_batch* b)
+{
+    auto ok_all = [&](int vw) {
+        for (const lbm_ctx* c : b->inst)
+            if (!step_vector_width_ok(b->store, c->nx, vw)) return false;
+        return true;
+    };
+    if (b->vw_req > 0 && ok_all(b->vw_req)) return b->vw_req;
+    for (int vw = 8 / store_bytes(b->store); vw > 1; vw /= 2)
+        if (ok_all(vw)) return vw;
+    return 1;
+}
+
+void batch_drop_graphs(lbm_batch* b)
+{
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+void batch_free_tables(lbm_batch* b)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (b->dtab[k]) (void)hipFree(b->dtab[k]);
+        if (b->dmap[k]) (void)hipFree(b->dmap[k]);
+        b->dtab[k] = nullptr;
+        b->dmap[k] = nullptr;
+        b->tab[k].clear();
+        b->ntiles[k] = 0;
+    }
+    b->tables_ready = false;
+}
+
+// Per-instance launch parameters and the tile -> instance map of both kernels.
+int batch_tables(lbm_batch* b)
+{
+    if (b->tables_ready) return LBM_OK;
+    batch_drop_graphs(b);
+    batch_free_tables(b);
+    const int vw = batch_width(b);
+    for (int k = 0; k < 2; ++k) {
+        const bool odd = (k == 1);
+        std::vector<int> map;
+        int total = 0;
+        for (int i = 0; i < b->n; ++i) {
+            lbm_ctx* c = b->inst[i];
+            c->vw_req = vw;
+            c->tile_odd = b->tile_odd;
+            c->tile_even = b->tile_even;
+            StepArgs a = step_args(c, odd);
+            a.tile_begin = total;
+            total += a.ntiles;
+            map.insert(map.end(), (size_t)a.ntiles, i);
+            b->tab[k].push_back(a);
+        }
+        b->ntiles[k] = total;
+        LBM_BHIP(b, hipMalloc((void**)&b->dtab[k], sizeof(StepArgs) * b->n));
+        LBM_BHIP(b, hipMalloc((void**)&b->dmap[k], sizeof(int) * map.size()));
+        LBM_BHIP(b, hipMemcpy(b->dtab[k], b->tab[k].data(), sizeof(StepArgs) * b->n, hipMemcpyHostToDevice));
+        LBM_BHIP(b, hipMemcpy(b->dmap[k], map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice));
+    }
+    b->tables_ready = true;
+    return LBM_OK;
+}
+
+hipError_t batch_enqueue(const lbm_batch* b, hipStream_t s, int layout_s, long long len)
+{
+    for (long long i = 0; i < len; ++i) {
+        const int k = (layout_s == 0) ? 1 : 0;  // layout P -> odd kernel
+        hipError_t e = launch_batch_step(b->store, k == 1, b->tab[k].data(), b->n, b->dtab[k], b->dmap[k],
+                                         b->ntiles[k], b->xcd_remap, s);
+        if (e != hipSuccess) return e;
+        layout_s ^= 1;
+    }
+    return hipSuccess;
+}
+
+void batch_advance(lbm_batch* b, long long len)
+{
+    for (long long i = 0; i < len; ++i) {
+        for (lbm_ctx* c : b->inst) {
+            if (c->layout_s == 0) c->layout_spec = (c->bc != kBB);
+            c->layout_s ^= 1;
+            c->steps += 1;
+        }
+        b->layout_s ^= 1;
+        b->steps += 1;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const double* Cs, const double* Fx,
+                     const int32_t* bc, double kappa, double B, lbm_batch** out)
+{
+    if (n < 1 || !grids || !tau || !Cs || !Fx || !bc || !out) return bfail(nullptr, LBM_E_ARG, "bad argument");
+    for (int i = 0; i < n; ++i)
+        if (bc[i] != LBM_BB && bc[i] != LBM_WFB && bc[i] != LBM_FREESLIP)
+            return bfail(nullptr, LBM_E_ARG, "unknown boundary of instance " + std::to_string(i));
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_E_OOM, "batch allocation failed");
+    b->n = n;
+    for (int i = 0; i < n; ++i) {
+        lbm_ctx* c = nullptr;
+        int st = lbm_create(&grids[i], tau[i], Cs[i], kappa, B, Fx[i], &c);
+        if (st != LBM_OK) {
+            std::string msg = "instance " + std::to_string(i) + ": " + g_err;
+            for (lbm_ctx* q : b->inst) lbm_destroy(q);
+            delete b;
+            return bfail(nullptr, st, msg);
+        }
+        c->bc = bc[i];
+        c->graph_steps = 0;
+        b->inst.push_back(c);
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b)
+{
+    if (!b) return;
+    DeviceGuard dg(b->dev);
+    if (b->h) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    batch_free_tables(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (lbm_ctx* c : b->inst) lbm_destroy(c);
+    delete b;
+}
+
+int lbm_batch_set_param(lbm_batch* b, int key, double v)
+{
+    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+    if (!std::isfinite(v)) return bfail(b, LBM_E_ARG, "parameter value must be finite");
+    const bool integral = (v == std::floor(v));
+    switch (key) {
+        case LBM_P_STORE:
+            if (b->h) return bfail(b, LBM_E_STATE, "the store format is fixed once storage is bound");
+            if (!integral || v < 0 || v > 3) return bfail(b, LBM_E_ARG, "store must be 0..3");
+            b->store = (int)v;
+            for (lbm_ctx* c : b->inst) c->store = b->store;
+            break;
+        case LBM_P_TILE_ODD:
+        case LBM_P_TILE_EVEN:
+            if (!integral || !tile_ok((int)v)) return bfail(b, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
+            (key == LBM_P_TILE_ODD ? b->tile_odd : b->tile_even) = (int)v;
+            break;
+        case LBM_P_VECTOR:
+            if (!integral || v < 0 || v > 4) return bfail(b, LBM_E_ARG, "cells per thread must be 0, 1, 2 or 4");
+            b->vw_req = (int)v;
+            break;
+        case LBM_P_XCD_REMAP:
+            if (v != 0.0 && v != 1.0) return bfail(b, LBM_E_ARG, "XCD remap is 0 or 1");
+            b->xcd_remap = (int)v;
+            break;
+        case LBM_P_GRAPH_STEPS:
+            if (!integral || v < 0 || v > 4096) return bfail(b, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
+            b->graph_steps = (int)v;
+            break;
+        case LBM_P_Y1:
+        case LBM_P_NEWTON_TOL:
+        case LBM_P_NEWTON_MAXIT:
+            for (lbm_ctx* c : b->inst) {
+                c->batch_member = false;
+                int st = lbm_set_param(c, key, v);
+                c->batch_member = (b->h != nullptr);
+                if (st != LBM_OK) return bfail(b, st, c->err);
+            }
+            break;
+        default:
+            return bfail(b, LBM_E_ARG, "unknown or per-instance parameter key");
+    }
+    b->tables_ready = false;
+    batch_drop_graphs(b);
+    return LBM_OK;
+}
+
+int lbm_batch_required_bytes(const lbm_batch* b, size_t* bytes)
+{
+    if (!b || !bytes) return bfail(nullptr, LBM_E_ARG, "null argument");
+    size_t total = 0;
+    for (const lbm_ctx* c : b->inst) {
+        size_t s = 0;
+        lbm_required_bytes(c, &s);
+        total += align256(s);
+    }
+    *bytes = total;
+    return LBM_OK;
+}
+
+int lbm_batch_bind_storage(lbm_batch* b, void* ptr, size_t bytes)
+{
+    if (!b || !ptr) return bfail(b, LBM_E_ARG, "null argument");
+    size_t need = 0;
+    lbm_batch_required_bytes(b, &need);
+    if (bytes < need) return bfail(b, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
+    if (((uintptr_t)ptr) % 256 != 0) return bfail(b, LBM_E_ARG, "storage must be 256-byte aligned");
+    b->offset.clear();
+    size_t off = 0;
+    for (lbm_ctx* c : b->inst) {
+        size_t s = 0;
+        lbm_required_bytes(c, &s);
+        c->batch_member = false;
+        int st = lbm_bind_storage(c, (char*)ptr + off, s);
+        c->batch_member = true;
+        if (st != LBM_OK) return bfail(b, st, c->err);
+        c->stream = b->stream;
+        b->offset.push_back(off);
+        off += align256(s);
+    }
+    b->dev = b->inst[0]->dev;
+    b->h = ptr;
+    b->bytes = bytes;
+    b->initialized = false;
+    b->tables_ready = false;
+    batch_drop_graphs(b);
+    return LBM_OK;
+}
+
+int lbm_batch_set_stream(lbm_batch* b, void* s)
+{
+    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+    b->stream = (hipStream_t)s;
+    for (lbm_ctx* c : b->inst) c->stream = b->stream;
+    return LBM_OK;
+}
+
+int lbm_batch_init_spalding(lbm_batch* b, const double* u_tau, double noise, const uint64_t* seeds)
+{
+    if (!b || !u_tau || !seeds) return bfail(b, LBM_E_ARG, "null argument");
+    if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
+    DeviceGuard dg(b->dev);
+    for (int i = 0; i < b->n; ++i) {
+        int st = init_spalding_impl(b->inst[i], u_tau[i], noise, seeds[i]);
+        if (st != LBM_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+    }
+    b->steps = 0;
+    b->layout_s = 0;
+    b->initialized = true;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int64_t n)
+{
+    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+    if (!b->h || !b->initialized) return bfail(b, LBM_E_STATE, "batch not bound and initialised");
+    if (n < 0) return bfail(b, LBM_E_ARG, "n must be >= 0");
+    if (n == 0) return LBM_OK;
+    DeviceGuard dg(b->dev);
+    int st = batch_tables(b);
+    if (st != LBM_OK) return st;
+    long long left = n;
+    while (left > 0) {
+        if (b->graph_steps > 0 && left >= b->graph_steps) {
+            const long long L = b->graph_steps;
+            GraphKey key{b->layout_s, (int)L, 0, 0};
+            auto it = b->graphs.find(key);
+            if (it == b->graphs.end()) {
+                if (!b->cap_stream) LBM_BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                LBM_BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = batch_enqueue(b, b->cap_stream, b->layout_s, L);
+                hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return bfail(b, LBM_E_DEVICE, std::string("graph capture: ") +
+                                                      hipGetErrorString(e != hipSuccess ? e : e2));
+                }
+                hipGraphExec_t ex = nullptr;
+                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                it = b->graphs.emplace(key, ex).first;
+            }
+            LBM_BHIP(b, hipGraphLaunch(it->second, b->stream));
+            batch_advance(b, L);
+            left -= L;
+        } else {
+            LBM_BHIP(b, batch_enqueue(b, b->stream, b->layout_s, 1));
+            batch_advance(b, 1);
+            left -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_batch_sync(lbm_batch* b, int64_t* first_bad_step, int32_t* first_bad_instance)
+{
+    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+    if (first_bad_step) *first_bad_step = -1;
+    if (first_bad_instance) *first_bad_instance = -1;
+    if (!b->h) return LBM_OK;
+    DeviceGuard dg(b->dev);
+    LBM_BHIP(b, hipStreamSynchronize(b->stream));
+    int worst = LBM_OK;
+    for (int i = 0; i < b->n; ++i) {
+        int64_t fb = -1;
+        int st = lbm_sync(b->inst[i], &fb);
+        if (st == LBM_E_DEVICE) return bfail(b, st, b->inst[i]->err);
+        if (st != LBM_OK && worst == LBM_OK) {
+            worst = st;
+            if (first_bad_step) *first_bad_step = fb;
+            if (first_bad_instance) *first_bad_instance = i;
+            b->err = "instance " + std::to_string(i) + ": " + b->inst[i]->err;
+        }
+    }
+    return worst;
+}
+
+lbm_ctx* lbm_batch_instance(lbm_batch* b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->n) return nullptr;
+    return b->inst[i];
+}
+
+int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
+{
+    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+    if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
+    if (b->initialized) return bfail(b, LBM_E_STATE, "autotune runs before the state is initialised");
+    if (steps < 2) return bfail(b, LBM_E_ARG, "steps must be >= 2");
+    DeviceGuard dg(b->dev);
+    std::vector<double> ut(b->n);
+    std::vector<uint64_t> seeds(b->n, 0);
+    for (int i = 0; i < b->n; ++i) ut[i] = std::sqrt(std::fabs(b->inst[i]->fx) * b->inst[i]->ny * 0.5);
+    int st = lbm_batch_init_spalding(b, ut.data(), 0.05, seeds.data());
+    if (st != LBM_OK) return st;
+    const int tcand[4] = {64, 128, 256, 512};
+    const int vcand[3] = {1, 2, 4};
+    hipEvent_t ev[3];
+    for (auto& e : ev) LBM_BHIP(b, hipEventCreate(&e));
+    float best = 1e30f;
+    int bo = b->tile_odd, be = b->tile_even, bv = batch_width(b);
+    hipError_t err = hipSuccess;
+    const int save_req = b->vw_req;
+    for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
+        b->vw_req = vcand[iv];
+        if (batch_width(b) != vcand[iv]) continue;
+        float bo_t = 1e30f, be_t = 1e30f;
+        int bo_k = 256, be_k = 256;
+        for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+            b->tile_odd = b->tile_even = tcand[k];
+            b->tables_ready = false;
+            if ((st = batch_tables(b)) != LBM_OK) return st;
+            float to = 0.f, te = 0.f;
+            for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
+                err = hipEventRecord(ev[0], b->stream);
+                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 0, 1);
+                if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
+                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 1, 1);
+                if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                float x = 0.f, y = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&x, ev[0], ev[1]);
+                if (err == hipSuccess) err = hipEventElapsedTime(&y, ev[1], ev[2]);
+                if (r > 0) {
+                    to += x;
+                    te += y;
+                }
+            }
+            if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
+            if (te < be_t) { be_t = te; be_k = tcand[k]; }
+        }
+        if (bo_t + be_t < best) {
+            best = bo_t + be_t;
+            bo = bo_k;
+            be = be_k;
+            bv = vcand[iv];
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    b->vw_req = (err == hipSuccess) ? bv : save_req;
+    b->tile_odd = bo;
+    b->tile_even = be;
+    b->tables_ready = false;
+    b->initialized = false;
+    for (lbm_ctx* c : b->inst) c->initialized = false;
+    batch_drop_graphs(b);
+    if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+    if (tiles) {
+        tiles[0] = bo;
+        tiles[1] = be;
+        tiles[2] = bv;
+    }
+    return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
 
 }  // extern "C"

@@ -16,16 +16,21 @@ struct DevFlags {
 
 enum Boundary { kBB = 0, kWFB = 1, kFreeSlip = 2 };
 
-// Parameters of one fused step launch.  One block processes one tile:
-// tile_x * vw consecutive cells of one x-row (y, z).
+// Parameters of one fused step launch (or of one instance of a batched
+// launch).  A block processes one tile: rpb whole x-rows of one z-plane, or
+// one segment of tile_x * vw cells of a single x-row.
 struct StepArgs {
     void* h;              // populations h_a = f_a - w_a, [a][z][y][x]
     long long n;          // cells
     int nx, ny, nz;
-    int tile_x;           // threads per block; a tile is tile_x * vw consecutive cells of one x-row
+    int tile_x;           // threads per block
     int vw;               // cells per thread (1, 2 or 4): a group of vw * sizeof(store) <= 8 bytes
-    int ntx;              // tiles per x-row
-    int ntiles;           // tiles in the grid (= blocks)
+    int ntx;              // x segments per row (1: a block holds whole rows)
+    int rpb;              // whole rows per block (1 when rows are split into segments)
+    int nyt;              // row groups along y per z-plane
+    int ntiles;           // tiles (= blocks) of this instance
+    int tile_begin;       // first tile of this instance in a batched launch
+    int bc;               // boundary (read by batched launches)
     int xcd_remap;        // 1: give each XCD a contiguous range of tiles
     int newton_maxit;
     double tau0;          // molecular relaxation time
@@ -37,7 +42,7 @@ struct StepArgs {
     double ekb;           // exp(-kappa B)
     double newton_tol;
     DevFlags* flags;
-    double* partials;     // [ntiles][7] statistics partial sums; nullptr on steps not sampled
+    double* partials;     // [nz][ny][ntx][7] statistics partial sums; nullptr on steps not sampled
 };
 
 struct ObsArgs {
@@ -59,6 +64,9 @@ struct ObsArgs {
 
 // launchers (lbm_kernels.hip); each returns the launch status
 int step_vector_width(int store, int nx);
+void step_geometry(int nx, int ny, int nz, int tile_x, int vw, StepArgs& a);
+hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, int n, const StepArgs* dev_table,
+                             const int* dev_tile_inst, int ntiles, int xcd_remap, hipStream_t s);
 bool step_vector_width_ok(int store, int nx, int vw);
 hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_stats_reduce(const double* partials, int ntx, int ny, int nz, int nx, double* acc, hipStream_t s);

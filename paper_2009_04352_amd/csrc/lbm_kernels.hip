@@ -480,69 +480,96 @@ __device__ __forceinline__ u32x2 halo_as_first(const typename S::T* row, unsigne
     else return Ln::as_first(Ln::load_elem(row + x));
 }
 
-// One time step for V consecutive cells per thread; a block owns one tile of
-// an x-row.  Wall rows (y = 0 and y = ny - 1) are uniform over a block, so
-// the wall logic never diverges.  Every global access is an aligned
-// V-element group.  In the odd step the x-shifted directions exchange their
-// groups through LDS: a thread takes the element it lacks from its neighbour
-// in the tile; when the tile is the whole row the neighbours wrap around
-// (periodic x) and no other access is needed, otherwise the tile's two edge
-// threads read (write) the single element beyond the tile directly.
-template <typename S, int V, bool ODD, bool SPEC, bool WFB, bool STATS>
-__global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p)
+// Boundary of a launch: fixed at compile time for a single channel, read
+// from the instance table for batched launches (instances differ).
+constexpr int kBCRuntime = 3;
+
+// One time step for V consecutive cells per thread.  A block holds one tile
+// of an instance: either `rpb` whole x-rows of one z-plane (nx / V threads
+// per row) or one segment of a single x-row (tile_x threads).  Every global
+// access is an aligned V-element group.  In the odd step the x-shifted
+// directions exchange neighbouring elements through LDS: a thread takes the
+// element it lacks from its neighbour in the row segment; a whole row wraps
+// around inside the block (periodic x), a partial segment's two edge threads
+// read (write) the one element beyond the segment directly.
+// BATCH: the instance of the tile and its parameters come from tables.
+template <typename S, int V, bool ODD, int BCT, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
+                                                    const int* __restrict__ tile_inst, int ntiles_all)
 {
+    constexpr bool BATCH = (BCT == kBCRuntime);
     using T = typename S::T;
     using R = typename S::R;
     using Ln = Lane<S, V>;
     extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x]
+
+    int tile;
+    StepArgs p;
+    if constexpr (BATCH) {
+        const int gt = tile_of_block(blockIdx.x, ntiles_all, p0.xcd_remap);
+        p = table[tile_inst[gt]];
+        tile = gt - p.tile_begin;
+    } else {
+        p = p0;
+        tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
+    }
+    const bool spec = BATCH ? (p.bc != kBB) : (BCT != kBB);
+    const bool wfb = BATCH ? (p.bc == kWFB) : (BCT == kWFB);
+    constexpr bool MAYBE_WFB = BATCH || BCT == kWFB;
+    constexpr bool MAYBE_SPEC = BATCH || BCT != kBB;
+
     T* h = (T*)p.h;
     const long long N = p.n;
-    const int tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
-    const int row = tile / p.ntx;
-    const int xt = tile - row * p.ntx;
-    const int y = row % p.ny;
-    const int z = row / p.ny;
-    const bool bot = (y == 0), top = (y == p.ny - 1);
-
     const int t = (int)threadIdx.x;
     const int nthr = (int)blockDim.x;
-    const int tile_start = xt * p.tile_x * V;
-    const int nact = min(p.tile_x * V, p.nx - tile_start) / V;  // threads holding cells
-    const bool whole = (p.ntx == 1);                             // the tile is the whole row
+    // tile -> (x segment, group of rows, z)
+    const int xt = tile % p.ntx;
+    const int rest = tile / p.ntx;
+    const int yt = rest % p.nyt;
+    const int z = rest / p.nyt;
+    const bool whole = (p.ntx == 1);
+    const int tpr = whole ? p.nx / V : nthr;        // threads per row segment
+    const int r = t / tpr, tr = t - r * tpr;
+    const int y = yt * p.rpb + r;
+    const int seg0 = xt * nthr * V;                  // first cell of the segment
+    const int nact = whole ? tpr : min(nthr, (p.nx - seg0) / V);
     RowLanes L;
     L.nx = p.nx;
-    L.x0 = tile_start + t * V;
-    L.active = t < nact;
+    L.x0 = seg0 + tr * V;
+    L.active = (r < p.rpb) && (y < p.ny) && (tr < nact);
+    const bool bot = (y == 0), top = (y == p.ny - 1);
     const int lane = t & 63;
+    const int tb = t - tr;                          // first thread of this row segment
 
     const unsigned nx = (unsigned)p.nx, ny = (unsigned)p.ny;
     const unsigned zm = (z == 0) ? (unsigned)p.nz - 1 : (unsigned)z - 1;
     const unsigned zp = (z == p.nz - 1) ? 0u : (unsigned)z + 1;
-    // start of the x-row (y + dy, z + dz) of direction slot s; dy stays inside the channel
+    // start of the x-row (y + dy, z + dz) of direction slot s; only formed for rows inside the channel
     auto rowp = [&](int s, int dy, int dz) -> T* {
         const unsigned zz = dz < 0 ? zm : (dz > 0 ? zp : (unsigned)z);
         return h + (long long)s * N + (long long)(nx * ((unsigned)(y + dy) + ny * zz));
     };
-    auto ld = [&](const T* r) -> u32x2 { return L.active ? Ln::template load<true>(r + L.x0) : u32x2{0u, 0u}; };
-    auto st = [&](T* r, u32x2 v) {
-        if (L.active) Ln::template store<true>(r + L.x0, v);
-    };
+    auto ld = [&](const T* rw) -> u32x2 { return Ln::template load<true>(rw + L.x0); };
+    auto st = [&](T* rw, u32x2 v) { Ln::template store<true>(rw + L.x0, v); };
 
     // a1/a2: gather.  Odd: pull from neighbours with wall reflections; even: own slots.
     u32x2 w[kQ];
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
         constexpr int ey = kEy[a], ez = kEz[a];
-        if constexpr (ODD) {
-            const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
-            if (from_wall) {
-                if constexpr (!SPEC || !is_tangential(a)) w[a] = ld(rowp(a, 0, 0));
-                else w[a] = ld(rowp(opp(mirror_y(a)), 0, -ez));
+        w[a] = u32x2{0u, 0u};
+        if (L.active) {
+            if constexpr (ODD) {
+                const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+                if (from_wall) {
+                    if (MAYBE_SPEC && spec && is_tangential(a)) w[a] = ld(rowp(opp(mirror_y(a)), 0, -ez));
+                    else w[a] = ld(rowp(a, 0, 0));
+                } else {
+                    w[a] = ld(rowp(opp(a), -ey, -ez));
+                }
             } else {
-                w[a] = ld(rowp(opp(a), -ey, -ez));
+                w[a] = ld(rowp(a, 0, 0));
             }
-        } else {
-            w[a] = ld(rowp(a, 0, 0));
         }
     });
     if constexpr (ODD) {
@@ -557,15 +584,22 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p)
             constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
             if constexpr (ex != 0) {
                 const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
-                const bool shifted = !from_wall || (SPEC && is_tangential(a));
+                const bool shifted = !from_wall || (MAYBE_SPEC && spec && is_tangential(a));
                 if (shifted && L.active) {
                     const u32x2* xb = xbuf + xslot(a) * nthr;
-                    const T* src = from_wall ? rowp(opp(mirror_y(a)), 0, -ez) : rowp(opp(a), -ey, -ez);
                     if constexpr (ex == 1) {  // needs the element at x0 - 1
-                        const u32x2 nb = t > 0 ? xb[t - 1] : (whole ? xb[nact - 1] : halo_as_last<S, V>(src, L.wrapx(L.x0 - 1)));
+                        u32x2 nb;
+                        if (tr > 0) nb = xb[t - 1];
+                        else if (whole) nb = xb[tb + nact - 1];
+                        else nb = halo_as_last<S, V>(from_wall ? rowp(opp(mirror_y(a)), 0, -ez) : rowp(opp(a), -ey, -ez),
+                                                     L.wrapx(L.x0 - 1));
                         w[a] = join_left<S, V>(w[a], nb);
                     } else {                  // needs the element at x0 + V
-                        const u32x2 nb = t < nact - 1 ? xb[t + 1] : (whole ? xb[0] : halo_as_first<S, V>(src, L.wrapx(L.x0 + V)));
+                        u32x2 nb;
+                        if (tr < nact - 1) nb = xb[t + 1];
+                        else if (whole) nb = xb[tb];
+                        else nb = halo_as_first<S, V>(from_wall ? rowp(opp(mirror_y(a)), 0, -ez) : rowp(opp(a), -ey, -ez),
+                                                      L.wrapx(L.x0 + V));
                         w[a] = join_right<S, V>(w[a], nb);
                     }
                 }
@@ -584,8 +618,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p)
             f[a] = Ln::get(w[a], k);
         });
         // a3: wall-function bounce at wall-adjacent cells
-        if constexpr (WFB) {
-            if (bot || top) {
+        if constexpr (MAYBE_WFB) {
+            if (wfb && (bot || top)) {
                 int it = 0;
                 bool fail = false;
                 wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.ekb, p.newton_tol, p.newton_maxit, it, fail);
@@ -619,78 +653,74 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p)
             if constexpr (kEx[a] != 0) xbuf[xslot(a) * nthr + t] = w[a];
         });
         __syncthreads();
-        for_each_dir([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
-            const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
-            if constexpr (ex == 0) {
-                if (to_wall) {
-                    if constexpr (!SPEC || !is_tangential(a)) st(rowp(opp(a), 0, 0), w[a]);
-                    else st(rowp(mirror_y(a), 0, ez), w[a]);
-                } else {
-                    st(rowp(a, ey, ez), w[a]);
-                }
-            } else {
-                if (to_wall && !(SPEC && is_tangential(a))) {
+        if (L.active) {
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
+                const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+                const bool mirrored = to_wall && MAYBE_SPEC && spec && is_tangential(a);
+                if (to_wall && !mirrored) {
                     st(rowp(opp(a), 0, 0), w[a]);  // bounce-back into the cell's own slot
-                } else if (L.active) {
-                    T* dst = to_wall ? rowp(mirror_y(a), 0, ez) : rowp(a, ey, ez);
+                } else if constexpr (ex == 0) {
+                    st(mirrored ? rowp(mirror_y(a), 0, ez) : rowp(a, ey, ez), w[a]);
+                } else {
+                    T* dst = mirrored ? rowp(mirror_y(a), 0, ez) : rowp(a, ey, ez);
                     const u32x2* xb = xbuf + xslot(a) * nthr;
                     if constexpr (ex == 1) {  // cell x goes to x + 1: the group at x0 starts with x0 - 1's value
-                        if (t > 0 || whole) {
-                            Ln::template store<true>(dst + L.x0, join_left<S, V>(w[a], xb[t > 0 ? t - 1 : nact - 1]));
+                        if (tr > 0 || whole) {
+                            st(dst, join_left<S, V>(w[a], xb[tr > 0 ? t - 1 : tb + nact - 1]));
                         } else {
                             if constexpr (V > 1) Ln::store_tail(dst + L.x0, Ln::shift_in_left(w[a], 0u));
                         }
-                        if (!whole && t == nact - 1) {
+                        if (!whole && tr == nact - 1) {
                             if constexpr (V == 1) Ln::template store<false>(dst + L.wrapx(L.x0 + 1), w[a]);
                             else Ln::store_elem(dst + L.wrapx(L.x0 + V), Ln::last(w[a]));
                         }
                     } else {                  // cell x goes to x - 1: the group at x0 ends with x0 + V's value
-                        if (t < nact - 1 || whole) {
-                            Ln::template store<true>(dst + L.x0, join_right<S, V>(w[a], xb[t < nact - 1 ? t + 1 : 0]));
+                        if (tr < nact - 1 || whole) {
+                            st(dst, join_right<S, V>(w[a], xb[tr < nact - 1 ? t + 1 : tb]));
                         } else {
                             if constexpr (V > 1) Ln::store_head(dst + L.x0, Ln::shift_in_right(w[a], 0u));
                         }
-                        if (!whole && t == 0) {
+                        if (!whole && tr == 0) {
                             if constexpr (V == 1) Ln::template store<false>(dst + L.wrapx(L.x0 - 1), w[a]);
                             else Ln::store_elem(dst + L.wrapx(L.x0 - 1), Ln::first(w[a]));
                         }
                     }
                 }
-            }
-        });
+            });
+        }
     } else {
-        for_each_dir([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            st(rowp(opp(a), 0, 0), w[a]);
-        });
+        if (L.active) {
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                st(rowp(opp(a), 0, 0), w[a]);
+            });
+        }
     }
 
-    if constexpr (WFB) {
-        if (bot || top) {
-            const int mx = wave_max(L.active ? iters : 0);
-            if (lane == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
-        }
+    if constexpr (MAYBE_WFB) {
+        const int mx = wave_max(L.active ? iters : 0);
+        if (lane == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
     }
-    // a8: plane statistics of the sampled velocity, FP64, fixed order (sampled steps only)
+    // a8: plane statistics of the sampled velocity: FP64 sums per row segment,
+    // threads of a row summed in a fixed order (sampled steps only)
     if constexpr (STATS) {
-        __shared__ double red[kMaxBlock / 64][7];
-        const int wv = t >> 6;
+        __shared__ double red[7][kMaxBlock];
 #pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            const double s = wave_sum(L.active ? sm[k] : 0.0);
-            if (lane == 0) red[wv][k] = s;
-        }
+        for (int k = 0; k < 7; ++k) red[k][t] = L.active ? sm[k] : 0.0;
         __syncthreads();
-        if (t < 7) {
-            double s = 0.0;
-            const int nw = (nthr + 63) >> 6;
-            for (int q = 0; q < nw; ++q) s += red[q][t];
-            p.partials[(long long)tile * 7 + t] = s;
+        for (int idx = t; idx < 7 * p.rpb; idx += nthr) {
+            const int rr = idx / 7, k = idx - rr * 7;
+            const int yy = yt * p.rpb + rr;
+            if (yy < p.ny) {
+                double s = 0.0;
+                for (int q = 0; q < tpr; ++q) s += red[k][rr * tpr + q];
+                p.partials[((long long)xt + (long long)p.ntx * ((long long)yy + (long long)p.ny * z)) * 7 + k] = s;
+            }
         }
     }
-    if (blockIdx.x == 0 && t == 0) p.flags->cnt[ODD ? 0 : 1] = p.flags->cnt[ODD ? 1 : 0] + 1;
+    if (tile == 0 && t == 0) p.flags->cnt[ODD ? 0 : 1] = p.flags->cnt[ODD ? 1 : 0] + 1;
 }
 
 template <typename S, int V, bool ODD>
@@ -698,16 +728,16 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
     const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
-#define LBM_STEP(SPEC, WFB)                                                                        \
-    do {                                                                                           \
-        if (a.partials)                                                                            \
-            hipLaunchKernelGGL((k_step<S, V, ODD, SPEC, WFB, true>), grid, block, lds, s, a);     \
-        else                                                                                       \
-            hipLaunchKernelGGL((k_step<S, V, ODD, SPEC, WFB, false>), grid, block, lds, s, a);    \
+#define LBM_STEP(BCT)                                                                                        \
+    do {                                                                                                     \
+        if (a.partials)                                                                                      \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, true>), grid, block, lds, s, a, nullptr, nullptr, 0);  \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false>), grid, block, lds, s, a, nullptr, nullptr, 0); \
     } while (0)
-    if (bc == kBB) LBM_STEP(false, false);
-    else if (bc == kWFB) LBM_STEP(true, true);
-    else LBM_STEP(true, false);
+    if (bc == kBB) LBM_STEP(kBB);
+    else if (bc == kWFB) LBM_STEP(kWFB);
+    else LBM_STEP(kFreeSlip);
 #undef LBM_STEP
     return hipGetLastError();
 }
@@ -718,15 +748,29 @@ static hipError_t launch_step_v(bool odd, int bc, const StepArgs& a, hipStream_t
     return odd ? launch_step_bc<S, V, true>(bc, a, s) : launch_step_bc<S, V, false>(bc, a, s);
 }
 
-template <typename S>
-static hipError_t launch_step_s(int vw, bool odd, int bc, const StepArgs& a, hipStream_t s)
+template <typename S, int V>
+static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* table, const int* tile_inst, int ntiles,
+                                 hipStream_t s)
+{
+    const dim3 grid((unsigned)ntiles), block((unsigned)a0.tile_x);
+    const size_t lds = odd ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
+    if (odd)
+        hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);
+    else
+        hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);
+    return hipGetLastError();
+}
+
+// Dispatch on the group width: F = launch_step_v or launch_batch_v style callable.
+template <typename S, typename F>
+static hipError_t with_width(int vw, F&& f)
 {
     constexpr int kB = (int)sizeof(typename S::T);
-    if (vw == 1) return launch_step_v<S, 1>(odd, bc, a, s);
+    if (vw == 1) return f(std::integral_constant<int, 1>{});
     if constexpr (kB <= 4)
-        if (vw == 2) return launch_step_v<S, 2>(odd, bc, a, s);
+        if (vw == 2) return f(std::integral_constant<int, 2>{});
     if constexpr (kB == 2)
-        if (vw == 4) return launch_step_v<S, 4>(odd, bc, a, s);
+        if (vw == 4) return f(std::integral_constant<int, 4>{});
     return hipErrorInvalidValue;
 }
 
@@ -743,15 +787,73 @@ bool step_vector_width_ok(int store, int nx, int vw)
     return vw >= 1 && vw * store_bytes(store) <= 8 && (vw & (vw - 1)) == 0 && nx % vw == 0;
 }
 
+void step_geometry(int nx, int ny, int nz, int tile_x, int vw, StepArgs& a)
+{
+    a.tile_x = tile_x;
+    a.vw = vw;
+    const int tpr_full = nx / vw;
+    if (tpr_full <= tile_x) {  // whole rows, several per block when they are short
+        a.ntx = 1;
+        a.rpb = tile_x / tpr_full;
+    } else {
+        a.ntx = (tpr_full + tile_x - 1) / tile_x;
+        a.rpb = 1;
+    }
+    a.nyt = (ny + a.rpb - 1) / a.rpb;
+    a.ntiles = a.ntx * a.nyt * nz;
+}
+
+static bool step_args_ok(int store, const StepArgs& a)
+{
+    if (a.tile_x < 64 || a.tile_x > kMaxBlock || (a.tile_x & 63) || a.ntiles < 1) return false;
+    if (!step_vector_width_ok(store, a.nx, a.vw)) return false;
+    StepArgs g = a;
+    step_geometry(a.nx, a.ny, a.nz, a.tile_x, a.vw, g);
+    return g.ntx == a.ntx && g.rpb == a.rpb && g.nyt == a.nyt && g.ntiles == a.ntiles;
+}
+
 hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s)
 {
-    if (a.tile_x < 64 || a.tile_x > kMaxBlock || (a.tile_x & 63) || a.ntiles < 1) return hipErrorInvalidValue;
-    if (!step_vector_width_ok(store, a.nx, a.vw)) return hipErrorInvalidValue;
+    if (!step_args_ok(store, a)) return hipErrorInvalidValue;
+    auto go = [&](auto St) -> hipError_t {
+        using S = decltype(St);
+        return with_width<S>(a.vw, [&](auto Vc) { return launch_step_v<S, decltype(Vc)::value>(odd, bc, a, s); });
+    };
     switch (store) {
-        case kStoreF64: return launch_step_s<StoreF64>(a.vw, odd, bc, a, s);
-        case kStoreF32: return launch_step_s<StoreF32>(a.vw, odd, bc, a, s);
-        case kStoreF16: return launch_step_s<StoreF16>(a.vw, odd, bc, a, s);
-        case kStoreBF16: return launch_step_s<StoreBF16>(a.vw, odd, bc, a, s);
+        case kStoreF64: return go(StoreF64{});
+        case kStoreF32: return go(StoreF32{});
+        case kStoreF16: return go(StoreF16{});
+        case kStoreBF16: return go(StoreBF16{});
+    }
+    return hipErrorInvalidValue;
+}
+
+// Batched step: `host_table` (n entries, validated here) mirrors the device
+// table; all instances share the store, block size and group width.
+hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, int n, const StepArgs* dev_table,
+                             const int* dev_tile_inst, int ntiles, int xcd_remap, hipStream_t s)
+{
+    if (n < 1 || ntiles < 1) return hipErrorInvalidValue;
+    int total = 0;
+    for (int i = 0; i < n; ++i) {
+        if (!step_args_ok(store, host_table[i]) || host_table[i].tile_begin != total) return hipErrorInvalidValue;
+        if (host_table[i].tile_x != host_table[0].tile_x || host_table[i].vw != host_table[0].vw) return hipErrorInvalidValue;
+        total += host_table[i].ntiles;
+    }
+    if (total != ntiles) return hipErrorInvalidValue;
+    StepArgs a0 = host_table[0];
+    a0.xcd_remap = xcd_remap;
+    auto go = [&](auto St) -> hipError_t {
+        using S = decltype(St);
+        return with_width<S>(a0.vw, [&](auto Vc) {
+            return launch_batch_v<S, decltype(Vc)::value>(odd, a0, dev_table, dev_tile_inst, ntiles, s);
+        });
+    };
+    switch (store) {
+        case kStoreF64: return go(StoreF64{});
+        case kStoreF32: return go(StoreF32{});
+        case kStoreF16: return go(StoreF16{});
+        case kStoreBF16: return go(StoreBF16{});
     }
     return hipErrorInvalidValue;
 }

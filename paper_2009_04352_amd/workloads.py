@@ -39,6 +39,39 @@ WORKLOADS = {
                tau=None, desc="large channel 2048x512x1024 (1.07B cells), Re_tau 2003, WFB, 500 steps"),
 }
 
+# the batched ensemble (see ensemble()): 64 channels, FP32 store, 1000 steps
+ENSEMBLE = dict(n=64, store="f32", steps=1000,
+                desc="64 independent channels, grids {32,64,128}x{16,32,64}x{16,32,64}, Re_tau in [300,2003), "
+                     "half WFB half BB, FP32, one launch per step")
+
+
+def splitmix64(seed, k):
+    """Output k of splitmix64 (Steele, Lea & Flood 2014) from state `seed`:
+    the draws of the ensemble recipe below."""
+    m = (1 << 64) - 1
+    z = (seed + (k + 1) * 0x9E3779B97F4A7C15) & m
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31)
+
+
+def ensemble(n=64, ma=0.060):
+    """The batched ensemble: instance i (seed i) draws nx from {32, 64, 128},
+    ny and nz from {16, 32, 64} and Re_tau uniformly in [300, 2003) by
+    splitmix64 of state i; WFB walls for even i, bounce-back for odd i.
+    Returns one dict per instance (grid, lattice parameters, boundary)."""
+    out = []
+    for i in range(n):
+        u = [splitmix64(i, k) for k in range(4)]
+        nx = (32, 64, 128)[u[0] % 3]
+        ny = (16, 32, 64)[u[1] % 3]
+        nz = (16, 32, 64)[u[2] % 3]
+        re_tau = 300.0 + 1703.0 * ((u[3] >> 11) * (1.0 / 9007199254740992.0))
+        p = rule_m(ny, re_tau, ma)
+        out.append(dict(nx=nx, ny=ny, nz=nz, re_tau=re_tau, tau=p["tau0"], cs=CS, fx=p["fx"], u_tau=p["u_tau"],
+                        bc="wfb" if i % 2 == 0 else "bb", seed=i))
+    return out
+
 
 def params(name, named_tau=False):
     """Lattice parameters of a workload: dict(grid, tau0, fx, u_tau, ...)."""

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     text = open(os.path.join(ROOT, "include", "lbmwf.h")).read()
-    return sorted(set(re.findall(r"^(?:int|void|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^(?:int|void|const char\*|lbm_ctx\*)\s+(lbm_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")

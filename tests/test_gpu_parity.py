@@ -230,6 +230,27 @@ def test_statistics_match_oracle(P, orc):
     assert ch.stats_sums()[1] == 0 and np.all(ch.stats_sums()[0] == 0)
 
 
+def test_statistics_with_many_rows_per_block(P, orc):
+    """Short rows packed many to a block (16 cells, 4 per thread: 32 rows per
+    128-thread block) still give every layer its plane sums."""
+    grid = (16, 40, 3)
+    rng = np.random.default_rng(12)
+    w = weights(orc)
+    ch, o = _pair(P, orc, grid, "f16", "wfb", stats_every=1, tiles=(128, 128, 4))
+    h0 = random_state(orc, grid[::-1], "f16", rng)
+    ch.set_state(h0)
+    o.set_state(h0 + w)
+    ch.step(2)
+    o.step(2)
+    sg, ng = ch.stats_sums()
+    so, no = o.stats_sums()
+    assert ng == no == 2
+    np.testing.assert_array_equal(sg[:, 7], so[:, 7])
+    # the second sample sees the state rounded once to FP16: per cell at most 19
+    # half-ulps of FP16 at |h| < 0.03 (7.6e-6 each) in each velocity component
+    assert np.all(np.abs(sg[:, :7] - so[:, :7]) <= 2e-4 * so[:, 7:8]), np.abs(sg - so).max()
+
+
 def test_boundary_switch_after_odd_step(P, orc):
     """Switching the boundary between an odd and an even step re-reflects the
     pending wall populations: the result equals the oracle, which reflects at
