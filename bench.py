@@ -34,10 +34,13 @@ FULL_FIELD_LIMIT = 64 << 20    # cells; larger grids compare sampled cells
 
 
 def kernel_source_hash():
+    """Hash of the device sources (every kernel file and header of csrc/)."""
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lattice.h", "store.h", "lbm_internal.h"):
-        with open(os.path.join(ROOT, "paper_2009_04352_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    d = os.path.join(ROOT, "paper_2009_04352_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")) and f != "lbm_capi.hip":
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 

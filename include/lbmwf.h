@@ -13,9 +13,13 @@
  *   viscosity (Sec. 3.1) and BGK relaxation with the body force term F_a of
  *   Eq. 1.
  *
- * Units are lattice units: dx = dt = 1, reference density 1.  A population
- * array is [a][z][y][x] with x fastest; cell index c = x + nx (y + ny z).
- * Directions a = 0..18 follow Table A-1.
+ * Units are lattice units: dx = dt = 1, reference density 1.  Host arrays of
+ * populations are [a][z][y][x] with x fastest; cell index c = x + nx (y + ny z).
+ * Directions a = 0..18 follow Table A-1.  The device array bound with
+ * lbm_bind_storage is internal: 19 slots of nx ny nz values whose rows are
+ * grouped in bricks of LBM_P_BRICK consecutive y, ordered
+ * [y / brick][z][y % brick][x] (brick = ny: the plain [z][y][x] order);
+ * lbm_get_state / lbm_set_state convert.
  *
  * Conventions for every function returning int:
  *   - LBM_OK (0) on success, a negative LBM_E_* code otherwise;
@@ -63,13 +67,17 @@ extern "C" {
 #define LBM_P_STORE 4         /* LBM_STORE_*; settable only before lbm_bind_storage (default F64) */
 #define LBM_P_TILE_ODD 5      /* threads per block of the odd-step kernel: 64, 128, 256 or 512 */
 #define LBM_P_TILE_EVEN 6     /* threads per block of the even-step kernel */
-#define LBM_P_XCD_REMAP 7     /* 1: contiguous tile ranges per XCD (default), 0: identity */
+#define LBM_P_XCD_REMAP 7     /* 1: the 8 XCDs take chunks of 32 consecutive tiles in turn (default), 0: identity */
 #define LBM_P_GRAPH_STEPS 8   /* steps per captured HIP graph chunk; 0 = launch eagerly (default 32) */
 #define LBM_P_BC 9            /* read-only here: the current boundary */
 #define LBM_P_TAU0 10         /* read-only: molecular relaxation time */
 #define LBM_P_FX 11           /* body force density along x; settable at any time */
 #define LBM_P_CS 12           /* Smagorinsky constant; settable at any time */
 #define LBM_P_VECTOR 13       /* cells per thread: 0 = auto (groups of 8 bytes), or 1, 2, 4 (group <= 8 bytes, divides nx) */
+#define LBM_P_BRICK 14        /* rows per brick of the device layout: 0 = auto (8; capped at ny).  Used only
+                               * when every block of both step kernels holds a single row, otherwise the
+                               * plain order (brick = ny).  Fixed once the state is initialised; reading it
+                               * gives the height in use.  Results do not depend on it. */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -78,7 +86,7 @@ typedef struct {
 } lbm_grid;
 
 /* Creates a channel context (no device memory yet).
- * g: grid with nx >= 1, ny >= 2, nz >= 1 and nx * ny * nz < 2^31.
+ * g: grid with nx >= 1, ny >= 2, nz >= 1, nx * ny * nz < 2^31 and nx * ny < 2^29.
  * tau: molecular relaxation time, > 1/2; nu0 = (tau - 1/2) / 3 (BGK, Eq. 1).
  * Cs: Smagorinsky constant >= 0 (Sec. 3.1; the paper uses 0.1).
  * kappa, B: Spalding's law constants (Eq. 16; the paper uses 0.41 and 5.5).
@@ -212,8 +220,10 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const 
 void lbm_batch_destroy(lbm_batch* batch);
 /* Keys LBM_P_STORE (before binding), LBM_P_TILE_ODD, LBM_P_TILE_EVEN,
  * LBM_P_VECTOR (0 = the widest group every instance allows), LBM_P_XCD_REMAP,
- * LBM_P_GRAPH_STEPS, and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT
- * applied to every instance. */
+ * LBM_P_GRAPH_STEPS, and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT /
+ * LBM_P_BRICK (before initialisation) applied to every instance.  Block
+ * sizes and cells per thread that an initialised instance's layout cannot
+ * run with give LBM_E_STATE. */
 int lbm_batch_set_param(lbm_batch* batch, int key, double value);
 /* Sum over instances of their required bytes, each rounded up to 256. */
 int lbm_batch_required_bytes(const lbm_batch* batch, size_t* bytes);

@@ -53,7 +53,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
                  device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False,
-                 vector=0):
+                 vector=0, brick=0):
         import torch
         self.lib = L.lib()
         self.shape = (nz, ny, nx)
@@ -76,6 +76,8 @@ class Channel:
                 vector = tiles[2]
         if vector:
             self._set(L.LBM_P_VECTOR, vector)
+        if brick:
+            self._set(L.LBM_P_BRICK, brick)
         nbytes = C.c_size_t(0)
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value
@@ -220,7 +222,7 @@ class Batch:
     cs, fx, bc."""
 
     def __init__(self, specs, kappa=0.41, B=5.5, store="f32", device="cuda", stream=None, tiles=None,
-                 graph_steps=None, vector=0):
+                 graph_steps=None, vector=0, brick=0):
         import torch
         self.lib = L.lib()
         n = len(specs)
@@ -246,6 +248,8 @@ class Batch:
                 vector = tiles[2]
         if vector:
             self._set(L.LBM_P_VECTOR, vector)
+        if brick:
+            self._set(L.LBM_P_BRICK, brick)
         nbytes = C.c_size_t(0)
         L.check_batch(self.lib.lbm_batch_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value

@@ -13,7 +13,7 @@ PKG = os.path.dirname(CSRC)
 ROOT = os.path.dirname(PKG)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "liblbmwf.so")
-SOURCES = ["lbm_kernels.hip", "lbm_capi.hip"]
+SOURCES = ["step_f16.hip", "step_bf16.hip", "step_f32.hip", "step_f64.hip", "lbm_kernels.hip", "lbm_capi.hip"]
 ARCH = os.environ.get("LBMWF_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -45,6 +45,8 @@ struct lbm_ctx {
     int stats_every = 0;
     int tile_odd = 256, tile_even = 256, xcd_remap = 1, graph_steps = 32;
     int vw_req = 0;              // cells per thread requested; 0 = widest the store and nx allow
+    int brick_req = 0;           // rows per brick of the population layout requested; 0 = automatic
+    int brick = 0;               // rows per brick in use; fixed while the state is initialised
 
     void* h = nullptr;
     size_t bytes = 0;
@@ -109,8 +111,39 @@ int vector_width(const lbm_ctx* c)
 long long segments_for(const lbm_ctx* c, int tile)
 {
     StepArgs g{};
-    step_geometry(c->nx, c->ny, c->nz, tile, vector_width(c), g);
+    step_geometry(c->nx, c->ny, c->nz, tile, vector_width(c), c->ny, g);
     return (long long)g.ntx * c->ny * c->nz;
+}
+
+int rows_per_block(const lbm_ctx* c, int tile, int vw)
+{
+    StepArgs g{};
+    step_geometry(c->nx, c->ny, c->nz, tile, vw, c->ny, g);
+    return g.rpb;
+}
+
+// Rows per brick for the current launch shapes: bricks of 8 rows (or the
+// requested height) when every block holds a single row, else the plain
+// [z][y][x] order (one brick of ny rows).
+constexpr int kAutoBrick = 8;
+constexpr int kXcdChunkLog2 = 5;  // XCDs take chunks of 32 consecutive tiles in turn
+int brick_for_tiles(const lbm_ctx* c)
+{
+    const int vw = vector_width(c);
+    if (rows_per_block(c, c->tile_odd, vw) > 1 || rows_per_block(c, c->tile_even, vw) > 1) return c->ny;
+    return std::min(c->brick_req > 0 ? c->brick_req : kAutoBrick, c->ny);
+}
+
+// the layout of the current state (fixed once it is initialised)
+int brick_rows(const lbm_ctx* c) { return c->initialized ? c->brick : brick_for_tiles(c); }
+
+// launch shapes that can run on the initialised state's layout
+bool shapes_fit_layout(const lbm_ctx* c)
+{
+    if (!c->initialized) return true;
+    const int vw = vector_width(c);
+    return brick_ok(c->ny, c->brick, rows_per_block(c, c->tile_odd, vw)) &&
+           brick_ok(c->ny, c->brick, rows_per_block(c, c->tile_even, vw));
 }
 
 bool tile_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
@@ -129,10 +162,10 @@ StepArgs step_args(const lbm_ctx* c, bool odd)
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
-    step_geometry(c->nx, c->ny, c->nz, odd ? c->tile_odd : c->tile_even, vector_width(c), a);
+    step_geometry(c->nx, c->ny, c->nz, odd ? c->tile_odd : c->tile_even, vector_width(c), brick_rows(c), a);
     a.tile_begin = 0;
     a.bc = c->bc;
-    a.xcd_remap = c->xcd_remap;
+    a.xcd_remap = c->xcd_remap ? kXcdChunkLog2 + 1 : 0;
     a.newton_maxit = c->newton_maxit;
     a.tau0 = c->tau0;
     a.cs2_18 = 18.0 * c->cs * c->cs;
@@ -156,6 +189,7 @@ ObsArgs obs_args(const lbm_ctx* c)
     a.nx = c->nx;
     a.ny = c->ny;
     a.nz = c->nz;
+    a.brick = brick_rows(c);
     a.layout_s = c->layout_s;
     a.bc = c->bc;
     a.layout_spec = c->layout_spec;
@@ -274,7 +308,8 @@ int fix_layout(lbm_ctx* c)
     const int want = (c->bc != kBB);
     if (want == c->layout_spec) return LBM_OK;
     if (!c->dtmp) LBM_HIP(c, hipMalloc((void**)&c->dtmp, (size_t)2 * c->nx * c->nz * 5 * sizeof(double)));
-    LBM_HIP(c, launch_relayout(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->layout_spec, want, c->dtmp, c->stream));
+    LBM_HIP(c, launch_relayout(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->layout_spec, want, c->dtmp,
+                               c->stream));
     c->layout_spec = want;
     return LBM_OK;
 }
@@ -333,6 +368,8 @@ int lbm_create(const lbm_grid* g, double tau, double Cs, double kappa, double B,
     if (g->nx < 1 || g->ny < 2 || g->nz < 1) return fail(nullptr, LBM_E_ARG, "grid needs nx >= 1, ny >= 2, nz >= 1");
     const long long n = (long long)g->nx * g->ny * g->nz;
     if (n >= (1ll << 31)) return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny * nz must be below 2^31");
+    if ((long long)g->nx * g->ny >= (1ll << 29))
+        return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny must be below 2^29 (32-bit offsets within a z-plane)");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(nullptr, LBM_E_ARG, "tau must be finite and > 1/2");
     if (!std::isfinite(Cs) || !(Cs >= 0.0)) return fail(nullptr, LBM_E_ARG, "Cs must be finite and >= 0");
     if (!std::isfinite(kappa) || !(kappa > 0.0)) return fail(nullptr, LBM_E_ARG, "kappa must be finite and > 0");
@@ -396,18 +433,38 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
             c->store = (int)v;
             return LBM_OK;
         case LBM_P_TILE_ODD:
-        case LBM_P_TILE_EVEN:
+        case LBM_P_TILE_EVEN: {
             if (!integral || !tile_ok((int)v)) return fail(c, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
-            (key == LBM_P_TILE_ODD ? c->tile_odd : c->tile_even) = (int)v;
+            int& tile = (key == LBM_P_TILE_ODD ? c->tile_odd : c->tile_even);
+            const int old = tile;
+            tile = (int)v;
+            if (!shapes_fit_layout(c)) {
+                tile = old;
+                return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
+                                            "with bricks of " + std::to_string(c->brick) + " rows");
+            }
             break;
+        }
         case LBM_P_XCD_REMAP:
             if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
             c->xcd_remap = (int)v;
             break;
-        case LBM_P_VECTOR:
+        case LBM_P_VECTOR: {
             if (!integral || (v != 0.0 && !step_vector_width_ok(c->store, c->nx, (int)v)))
                 return fail(c, LBM_E_ARG, "cells per thread must be 0 (auto) or 1, 2, 4 with groups of at most 8 bytes dividing nx");
+            const int old = c->vw_req;
             c->vw_req = (int)v;
+            if (!shapes_fit_layout(c)) {
+                c->vw_req = old;
+                return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
+                                            "with bricks of " + std::to_string(c->brick) + " rows");
+            }
+            break;
+        }
+        case LBM_P_BRICK:
+            if (c->initialized) return fail(c, LBM_E_STATE, "the population layout is fixed once the state is initialised");
+            if (!integral || v < 0 || v > (1 << 30)) return fail(c, LBM_E_ARG, "rows per brick must be an integer >= 0");
+            c->brick_req = (int)v;
             break;
         case LBM_P_GRAPH_STEPS:
             if (!integral || v < 0 || v > 4096) return fail(c, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
@@ -440,6 +497,7 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
         case LBM_P_TILE_EVEN: *v = c->tile_even; break;
         case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
         case LBM_P_VECTOR: *v = vector_width(c); break;
+        case LBM_P_BRICK: *v = brick_rows(c); break;
         case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
         case LBM_P_BC: *v = c->bc; break;
         case LBM_P_TAU0: *v = c->tau0; break;
@@ -525,7 +583,8 @@ static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t s
         prof[y] = u_tau * spalding_uplus_host(dist * u_tau / nu0, c->kappa, c->bconst);
     }
     LBM_HIP(c, hipMemcpyAsync(c->dprof, prof.data(), prof.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    LBM_HIP(c, launch_init_spalding(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->dprof, noise,
+    c->brick = brick_for_tiles(c);
+    LBM_HIP(c, launch_init_spalding(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->dprof, noise,
                                     (unsigned long long)seed, c->stream));
     c->steps = 0;
     c->layout_s = 0;
@@ -548,6 +607,8 @@ int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
     double* tmp = nullptr;
     LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
     std::vector<double> stage((size_t)chunk * 19);
+    c->initialized = false;  // the layout is chosen afresh
+    c->brick = brick_for_tiles(c);
     int st = LBM_OK;
     for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
         const long long cnt = std::min(chunk, c->n - first);
@@ -555,7 +616,8 @@ int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
             std::memcpy(stage.data() + (size_t)a * cnt, in + (size_t)a * c->n + first, (size_t)cnt * sizeof(double));
         hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 19 * sizeof(double), hipMemcpyHostToDevice,
                                       c->stream);
-        if (e == hipSuccess) e = launch_set_state(c->store, c->h, c->n, first, cnt, tmp, c->stream);
+        if (e == hipSuccess)
+            e = launch_set_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("set_state: ") + hipGetErrorString(e));
     }
@@ -598,7 +660,7 @@ static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, dou
             e = hipMemcpyAsync(dcells, cells + first, (size_t)cnt * sizeof(long long), hipMemcpyHostToDevice,
                                c->stream);
         if (e == hipSuccess)
-            e = launch_get_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->layout_s, c->layout_spec,
+            e = launch_get_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->layout_s, c->layout_spec,
                                  cells ? dcells : nullptr, cells ? 0 : first, cnt, tmp, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(stage.data(), tmp, (size_t)cnt * 19 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -852,6 +914,7 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
     const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
     int st = init_spalding_impl(c, ut, 0.05, 0);
     if (st != LBM_OK) return st;
+    c->initialized = false;  // a timing state only: each candidate takes the layout its shapes want
     const int tcand[4] = {64, 128, 256, 512};
     const int vcand[3] = {1, 2, 4};
     hipEvent_t ev[3];
@@ -1046,22 +1109,43 @@ void batch_free_tables(lbm_batch* b)
     b->tables_ready = false;
 }
 
+// The batch's launch shapes on every instance.
+void batch_apply_shapes(lbm_batch* b)
+{
+    const int vw = batch_width(b);
+    for (lbm_ctx* c : b->inst) {
+        c->vw_req = vw;
+        c->tile_odd = b->tile_odd;
+        c->tile_even = b->tile_even;
+    }
+}
+
+// whether the batch's launch shapes fit the layouts of the instances' states
+bool batch_shapes_fit(const lbm_batch* b)
+{
+    const int vw = batch_width(b);
+    for (const lbm_ctx* c : b->inst) {
+        if (!c->initialized) continue;
+        if (!brick_ok(c->ny, c->brick, rows_per_block(c, b->tile_odd, vw)) ||
+            !brick_ok(c->ny, c->brick, rows_per_block(c, b->tile_even, vw)))
+            return false;
+    }
+    return true;
+}
+
 // Per-instance launch parameters and the tile -> instance map of both kernels.
 int batch_tables(lbm_batch* b)
 {
     if (b->tables_ready) return LBM_OK;
     batch_drop_graphs(b);
     batch_free_tables(b);
-    const int vw = batch_width(b);
+    batch_apply_shapes(b);
     for (int k = 0; k < 2; ++k) {
         const bool odd = (k == 1);
         std::vector<int> map;
         int total = 0;
         for (int i = 0; i < b->n; ++i) {
             lbm_ctx* c = b->inst[i];
-            c->vw_req = vw;
-            c->tile_odd = b->tile_odd;
-            c->tile_even = b->tile_even;
             StepArgs a = step_args(c, odd);
             a.tile_begin = total;
             total += a.ntiles;
@@ -1083,7 +1167,7 @@ hipError_t batch_enqueue(const lbm_batch* b, hipStream_t s, int layout_s, long l
     for (long long i = 0; i < len; ++i) {
         const int k = (layout_s == 0) ? 1 : 0;  // layout P -> odd kernel
         hipError_t e = launch_batch_step(b->store, k == 1, b->tab[k].data(), b->n, b->dtab[k], b->dmap[k],
-                                         b->ntiles[k], b->xcd_remap, s);
+                                         b->ntiles[k], b->xcd_remap ? kXcdChunkLog2 + 1 : 0, s);
         if (e != hipSuccess) return e;
         layout_s ^= 1;
     }
@@ -1159,13 +1243,31 @@ int lbm_batch_set_param(lbm_batch* b, int key, double v)
             for (lbm_ctx* c : b->inst) c->store = b->store;
             break;
         case LBM_P_TILE_ODD:
-        case LBM_P_TILE_EVEN:
+        case LBM_P_TILE_EVEN: {
             if (!integral || !tile_ok((int)v)) return bfail(b, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
-            (key == LBM_P_TILE_ODD ? b->tile_odd : b->tile_even) = (int)v;
+            int& tile = (key == LBM_P_TILE_ODD ? b->tile_odd : b->tile_even);
+            const int old = tile;
+            tile = (int)v;
+            if (!batch_shapes_fit(b)) {
+                tile = old;
+                return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
+            }
             break;
-        case LBM_P_VECTOR:
+        }
+        case LBM_P_VECTOR: {
             if (!integral || v < 0 || v > 4) return bfail(b, LBM_E_ARG, "cells per thread must be 0, 1, 2 or 4");
+            const int old = b->vw_req;
             b->vw_req = (int)v;
+            if (!batch_shapes_fit(b)) {
+                b->vw_req = old;
+                return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
+            }
+            break;
+        }
+        case LBM_P_BRICK:
+            if (b->initialized) return bfail(b, LBM_E_STATE, "the population layout is fixed once the state is initialised");
+            if (!integral || v < 0 || v > (1 << 30)) return bfail(b, LBM_E_ARG, "rows per brick must be an integer >= 0");
+            for (lbm_ctx* c : b->inst) c->brick_req = (int)v;
             break;
         case LBM_P_XCD_REMAP:
             if (v != 0.0 && v != 1.0) return bfail(b, LBM_E_ARG, "XCD remap is 0 or 1");
@@ -1248,6 +1350,7 @@ int lbm_batch_init_spalding(lbm_batch* b, const double* u_tau, double noise, con
     if (!b || !u_tau || !seeds) return bfail(b, LBM_E_ARG, "null argument");
     if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
     DeviceGuard dg(b->dev);
+    batch_apply_shapes(b);  // the instances' layouts follow the shapes they will run with
     for (int i = 0; i < b->n; ++i) {
         int st = init_spalding_impl(b->inst[i], u_tau[i], noise, seeds[i]);
         if (st != LBM_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
@@ -1343,6 +1446,7 @@ int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
     for (int i = 0; i < b->n; ++i) ut[i] = std::sqrt(std::fabs(b->inst[i]->fx) * b->inst[i]->ny * 0.5);
     int st = lbm_batch_init_spalding(b, ut.data(), 0.05, seeds.data());
     if (st != LBM_OK) return st;
+    for (lbm_ctx* c : b->inst) c->initialized = false;  // timing states: layouts follow the candidates
     const int tcand[4] = {64, 128, 256, 512};
     const int vcand[3] = {1, 2, 4};
     hipEvent_t ev[3];

@@ -1,0 +1,490 @@
+// Device building blocks of the fused step: lattice loops, the FP64 wall
+// function, the collision, wave reductions and the store-format lane groups.
+// Included by every translation unit that instantiates step kernels.
+//
+// Method: Han, Ooka & Kikumoto, "A wall function approach in lattice
+// Boltzmann method" (arXiv 2009.04352).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <utility>
+
+#include "lattice.h"
+#include "lbm_internal.h"
+#include "store.h"
+
+namespace lbmwf {
+
+// ------------------------------------------------------------- utilities
+
+template <typename F, int... As>
+__device__ __forceinline__ void for_each_dir_impl(F&& fn, std::integer_sequence<int, As...>)
+{
+    (fn(std::integral_constant<int, As>{}), ...);
+}
+
+// Calls fn(std::integral_constant<int, a>) for a = 0 .. 18 in order.
+template <typename F>
+__device__ __forceinline__ void for_each_dir(F&& fn)
+{
+    for_each_dir_impl(fn, std::make_integer_sequence<int, kQ>{});
+}
+
+// Tile of a block.  Blocks are dispatched round-robin over the 8 XCDs (block
+// b to XCD b mod 8).  remap = 0 keeps tile = b.  remap = c + 1 hands the XCDs
+// chunks of 2^c consecutive tiles in turn: XCD k works through chunks k,
+// k + 8, k + 16, ..., so each XCD's L2 sees runs of neighbouring tiles and
+// every XCD gets an even share of each region of the grid (the wall rows'
+// extra work included).  Tiles past the last whole round of 8 chunks keep
+// tile = b.
+__device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap)
+{
+    if (remap <= 0) return b;
+    const int c = remap - 1;
+    const int full = (ntiles >> (c + 3)) << (c + 3);
+    if (b >= full) return b;
+    const int k = b & 7, j = b >> 3;
+    return ((((j >> c) << 3) + k) << c) + (j & ((1 << c) - 1));
+}
+
+// splitmix64 (Steele, Lea & Flood 2014): output k of the generator seeded
+// with `seed`.
+__device__ __forceinline__ unsigned long long splitmix64_at(unsigned long long seed, unsigned long long k)
+{
+    unsigned long long z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double uniform01(unsigned long long seed, unsigned long long k)
+{
+    return (double)(splitmix64_at(seed, k) >> 11) * (1.0 / 9007199254740992.0);
+}
+
+// ------------------------------------------------------ wall function (FP64)
+
+// Start value for the wall-function Newton solve, in FP32: the log law
+// u+ = ln(y+) / kappa + B with y+ = R / p, iterated as a fixed point (it
+// contracts for p > 1 / kappa), taken when it is below the viscous guess
+// sqrt(R); then a few FP32 Newton steps on H below.  Only the start of the
+// FP64 iteration depends on it.
+__device__ __forceinline__ double wall_newton_start(double R, double kappa, double bconst, double ekb)
+{
+    const float Rf = (float)R, kf = (float)kappa, ekf = (float)ekb;
+    float p = sqrtf(Rf);
+    float pl = p;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pl = __logf(Rf / pl) / kf + (float)bconst;
+    if (pl > 1.0f && pl < p) p = pl;
+    for (int i = 0; i < 6; ++i) {
+        const float k = kf * p, ek = __expf(k), k2 = 0.5f * k * k;
+        const float br = ek - 1.0f - k - k2;
+        const float sp = p + ekf * (br - k2 * k * (1.0f / 3.0f));
+        const float dsp = 1.0f + kf * ekf * br;
+        const float pn = p - (p * sp - Rf) / (sp + p * dsp);
+        if (!(pn > 0.0f) || !(pn < INFINITY)) break;
+        const bool done = fabsf(pn - p) <= 1e-6f * pn;
+        p = pn;
+        if (done) break;
+    }
+    return (p > 0.0f && p < INFINITY) ? (double)p : sqrt(R);
+}
+
+// Friction velocity from Spalding's law (Eq. 16-17).  In p = u+ = U / u_tau
+// with R = y1 U / nu the law reads H(p) = p Sp(p) - R = 0.  H is increasing
+// and convex for p > 0, so Newton's method converges from any positive start
+// (after at most one step it is right of the root and then decreases
+// monotonically); it stops when |p_{k+1} - p_k| <= tol p_{k+1}.  The FP64
+// iteration starts from wall_newton_start; `iters` counts FP64 steps.
+__device__ __forceinline__ double wall_utau(double U, double y1, double nu, double kappa, double bconst, double ekb,
+                                            double tol, int maxit, int& iters, bool& fail)
+{
+    const double R = y1 * U / nu;
+    double p = wall_newton_start(R, kappa, bconst, ekb);
+    iters = 0;
+    fail = true;
+    for (int it = 1; it <= maxit; ++it) {
+        const double k = kappa * p;
+        const double ek = exp(k);
+        const double k2 = 0.5 * k * k;
+        const double br = ek - 1.0 - k - k2;              // e^k - 1 - k - k^2/2
+        const double sp = p + ekb * (br - k2 * k * (1.0 / 3.0));
+        const double dsp = 1.0 + kappa * ekb * br;
+        const double pn = p - (p * sp - R) / (sp + p * dsp);
+        iters = it;
+        if (fabs(pn - p) <= tol * pn) {
+            p = pn;
+            fail = false;
+            break;
+        }
+        p = pn;
+    }
+    return U / p;
+}
+
+struct WallRecord {
+    double taux, tauz, utau, U;
+};
+
+// WFB correction of the gathered (free-slip) populations of one wall cell:
+// tau_w from the wall function, split along the wall-parallel velocity
+// (Eq. 15) and added as +-tau/2 to the four reflected diagonal populations
+// (Eq. 13-14 with dt = dy = 1).  Top wall: the bottom rule mirrored in y.
+template <typename R>
+__device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double fx, double y1, double nu0,
+                                                  double kappa, double bconst, double ekb, double tol, int maxit,
+                                                  int& iters, bool& fail)
+{
+    R drho = R(0), jx = R(0), jz = R(0);
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        drho += f[a];
+        if constexpr (kEx[a] == 1) jx += f[a];
+        if constexpr (kEx[a] == -1) jx -= f[a];
+        if constexpr (kEz[a] == 1) jz += f[a];
+        if constexpr (kEz[a] == -1) jz -= f[a];
+    });
+    const R rho = R(1) + drho;
+    const double vx = (double)((jx + R(0.5) * (R)fx) / rho);
+    const double vz = (double)(jz / rho);
+    const double U = sqrt(vx * vx + vz * vz);
+    WallRecord rec{0.0, 0.0, 0.0, U};
+    iters = 0;
+    fail = false;
+    if (U > 0.0) {
+        const double ut = wall_utau(U, y1, nu0, kappa, bconst, ekb, tol, maxit, iters, fail);
+        const double tauw = (double)rho * ut * ut;
+        rec.taux = -(vx / U) * tauw;
+        rec.tauz = -(vz / U) * tauw;
+        rec.utau = ut;
+    }
+    const R hx = (R)(0.5 * rec.taux), hz = (R)(0.5 * rec.tauz);
+    if (!top) {
+        f[7] += hx;
+        f[14] -= hx;
+        f[11] += hz;
+        f[17] -= hz;
+    } else {
+        f[mirror_y(7)] += hx;
+        f[mirror_y(14)] -= hx;
+        f[mirror_y(11)] += hz;
+        f[mirror_y(17)] -= hz;
+    }
+    return rec;
+}
+
+// ------------------------------------------------- collision (Sec. 3.1, Eq. 1)
+
+// The library is compiled without automatic contraction, so that every
+// kernel evaluates the same operations in the same order (odd and even steps,
+// single and batched launches agree bit for bit); fused multiply-adds are
+// written out where they are wanted.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R>
+struct Moments {
+    R rho, ux, uy, uz;
+};
+
+// Reciprocal and square root: one hardware instruction in FP32 (about one ulp),
+// the IEEE operations in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+
+// The pairs (a, a + 1) of opposite directions, a odd, used below with these
+// velocities (Table A-1).
+static_assert(kEx[1] == 1 && kEy[3] == 1 && kEz[5] == 1, "axis pairs");
+static_assert(kEx[7] == 1 && kEy[7] == 1 && kEz[7] == 0, "pair 7");
+static_assert(kEx[9] == 1 && kEy[9] == 0 && kEz[9] == 1, "pair 9");
+static_assert(kEx[11] == 0 && kEy[11] == 1 && kEz[11] == 1, "pair 11");
+static_assert(kEx[13] == 1 && kEy[13] == -1 && kEz[13] == 0, "pair 13");
+static_assert(kEx[15] == 1 && kEy[15] == 0 && kEz[15] == -1, "pair 15");
+static_assert(kEx[17] == 0 && kEy[17] == 1 && kEz[17] == -1, "pair 17");
+
+// Moments (Eq. 2, half-force shift), Smagorinsky relaxation time from the
+// non-equilibrium stress, BGK towards the second-order equilibrium and the
+// Guo force term, in place on h = f - w.  Opposite directions are handled as
+// pairs: with s = h_a + h_b and d = h_a - h_b the moments are sums of s or d,
+// the equilibrium splits into an even part w (drho + rho (4.5 (e.u)^2 - 1.5 u.u))
+// and an odd part 3 w rho e.u, and the force term into -3 u_x + 9 e_x e.u and
+// 3 e_x (per unit force along x); both halves of the update are then
+// polynomials in e.u whose coefficients depend only on the weight class.
+template <typename R>
+__device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx)
+{
+    R s[kQ], d[kQ];  // indexed by the odd member of each pair
+    R drho = f[0];
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if constexpr (a % 2 == 1) {
+            s[a] = f[a] + f[a + 1];
+            d[a] = f[a] - f[a + 1];
+            drho += s[a];
+        }
+    });
+    const R jx = ((d[1] + d[7]) + (d[9] + d[13])) + d[15];
+    const R jy = ((d[3] + d[7]) + (d[11] - d[13])) + d[17];
+    const R jz = ((d[5] + d[9]) + (d[11] - d[15])) - d[17];
+    const R sxx = ((s[1] + s[7]) + (s[9] + s[13])) + s[15];
+    const R syy = ((s[3] + s[7]) + (s[11] + s[13])) + s[17];
+    const R szz = ((s[5] + s[9]) + (s[11] + s[15])) + s[17];
+    const R sxy = s[7] - s[13], sxz = s[9] - s[15], syz = s[11] - s[17];
+
+    const R rho = R(1) + drho;
+    const R inv = rcp(rho);
+    const R ux = fmad(R(0.5), fx, jx) * inv, uy = jy * inv, uz = jz * inv;
+    // Pi_neq = sum e e h - sum e e h_eq, with sum e e h_eq = drho/3 I + rho u u
+    const R c3 = drho * R(1.0 / 3.0);
+    const R rux = rho * ux, ruy = rho * uy;
+    const R pxx = fmad(-rux, ux, sxx - c3), pyy = fmad(-ruy, uy, syy - c3), pzz = fmad(-rho * uz, uz, szz - c3);
+    const R pxy = fmad(-rux, uy, sxy), pxz = fmad(-rux, uz, sxz), pyz = fmad(-ruy, uz, syz);
+    const R offd = fmad(pxy, pxy, fmad(pxz, pxz, pyz * pyz));
+    const R pp = fmad(pxx, pxx, fmad(pyy, pyy, fmad(pzz, pzz, R(2) * offd)));
+    const R qn = sqrt_r(R(2) * pp);
+    const R taue = R(0.5) * (tau0 + sqrt_r(fmad(tau0, tau0, cs2_18 * qn * inv)));
+    const R om = rcp(taue);
+    const R omh = R(0.5) - R(0.5) * om;          // (1 - omega) / 2
+    const R fc = fmad(R(-0.5), om, R(1)) * fx;   // (1 - 1/(2 tau_e)) Fx
+    const R usq = R(1.5) * fmad(ux, ux, fmad(uy, uy, uz * uz));
+    const R m3ux = R(-3) * ux;
+    const R t0 = fmad(rho, -usq, drho);          // drho - rho * 1.5 u.u
+
+    {   // rest population: e = 0
+        constexpr R w = weight<R>(0);
+        const R heq = w * t0;
+        f[0] = fmad(-om, f[0] - heq, f[0]) + (w * fc) * m3ux;
+    }
+    // Per weight class (c = 0: 1/18, 1: 1/36) the pair update is linear in
+    // e.u and (e.u)^2:
+    //   S = omh s + A (e.u)^2 + C e_x e.u + B,   D = omh d + E e.u + G e_x
+    // with A = 4.5 om w rho, E = 3 om w rho, B = om w t0 - 3 w fc ux,
+    // C = 9 w fc, G = 3 w fc (the odd member of every pair has e_x = 0 or 1).
+    const R rho45 = R(4.5) * rho, rho3 = R(3) * rho;
+    R cA[2], cB[2], cC[2], cE[2], cG[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const R w = c == 0 ? weight<R>(1) : weight<R>(7);
+        const R omw = om * w, fcw = w * fc;
+        cA[c] = rho45 * omw;
+        cE[c] = rho3 * omw;
+        cB[c] = fmad(omw, t0, m3ux * fcw);
+        cC[c] = R(9) * fcw;
+        cG[c] = R(3) * fcw;
+    }
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if constexpr (a % 2 == 1) {
+            constexpr int ex = kEx[a];
+            static_assert(ex == 0 || ex == 1, "odd members move in +x or not at all");
+            constexpr int c = norm2(a) == 1 ? 0 : 1;
+            R eu = R(0);
+            if constexpr (kEx[a] == 1) eu = ux;
+            if constexpr (kEy[a] == 1) eu = (kEx[a] != 0) ? eu + uy : uy;
+            if constexpr (kEy[a] == -1) eu = eu - uy;
+            if constexpr (kEz[a] == 1) eu = (kEx[a] != 0 || kEy[a] != 0) ? eu + uz : uz;
+            if constexpr (kEz[a] == -1) eu = eu - uz;
+            // half sum and half difference of the post-collision pair
+            const R sc = (ex != 0) ? fmad(cC[c], eu, cB[c]) : cB[c];
+            const R S = fmad(omh, s[a], fmad(cA[c], eu * eu, sc));
+            const R D = fmad(omh, d[a], (ex != 0) ? fmad(cE[c], eu, cG[c]) : cE[c] * eu);
+            f[a] = S + D;
+            f[a + 1] = S - D;
+        }
+    });
+    return Moments<R>{rho, ux, uy, uz};
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// --------------------------------------------------------- the fused step
+
+constexpr int kMaxBlock = 512;
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// A group of V consecutive populations of one direction, G = V * sizeof(T)
+// bytes (2, 4 or 8), held in the low bytes of a u32x2.  Groups that no other
+// thread touches move with non-temporal loads and stores (every slot is read
+// once and written once per step); single elements at tile edges, which
+// neighbouring blocks share cache lines with, stay cached.
+template <typename S, int V>
+struct Lane {
+    using T = typename S::T;
+    using R = typename S::R;
+    static constexpr int kBytes = (int)sizeof(T);
+    static constexpr int G = V * kBytes;
+    static_assert(G == 2 || G == 4 || G == 8, "a group is 2, 4 or 8 bytes");
+
+    template <bool NT>
+    __device__ __forceinline__ static u32x2 load(const T* p)
+    {
+        if constexpr (G == 8) {
+            if constexpr (NT) return __builtin_nontemporal_load((const u32x2*)p);
+            else return *(const u32x2*)p;
+        } else if constexpr (G == 4) {
+            if constexpr (NT) return u32x2{__builtin_nontemporal_load((const unsigned int*)p), 0u};
+            else return u32x2{*(const unsigned int*)p, 0u};
+        } else {
+            if constexpr (NT) return u32x2{(unsigned int)__builtin_nontemporal_load((const unsigned short*)p), 0u};
+            else return u32x2{(unsigned int)*(const unsigned short*)p, 0u};
+        }
+    }
+    template <bool NT>
+    __device__ __forceinline__ static void store(T* p, u32x2 v)
+    {
+        if constexpr (G == 8) {
+            if constexpr (NT) __builtin_nontemporal_store(v, (u32x2*)p);
+            else *(u32x2*)p = v;
+        } else if constexpr (G == 4) {
+            if constexpr (NT) __builtin_nontemporal_store(v.x, (unsigned int*)p);
+            else *(unsigned int*)p = v.x;
+        } else {
+            if constexpr (NT) __builtin_nontemporal_store((unsigned short)v.x, (unsigned short*)p);
+            else *(unsigned short*)p = (unsigned short)v.x;
+        }
+    }
+    // raw bits of one element (element sizes 2 and 4; groups of V >= 2)
+    __device__ __forceinline__ static unsigned int load_elem(const T* p)
+    {
+        if constexpr (kBytes == 4) return *(const unsigned int*)p;
+        else return (unsigned int)*(const unsigned short*)p;
+    }
+    __device__ __forceinline__ static void store_elem(T* p, unsigned int b)
+    {
+        if constexpr (kBytes == 4) *(unsigned int*)p = b;
+        else *(unsigned short*)p = (unsigned short)b;
+    }
+    __device__ __forceinline__ static unsigned int first(u32x2 v)
+    {
+        if constexpr (kBytes == 4) return v.x;
+        else return v.x & 0xffffu;
+    }
+    __device__ __forceinline__ static unsigned int last(u32x2 v)
+    {
+        if constexpr (kBytes == 4) return v.y;
+        else if constexpr (V == 4) return v.y >> 16;
+        else return v.x >> 16;
+    }
+    // the group holding only element b, as its last (first) element
+    __device__ __forceinline__ static u32x2 as_last(unsigned int b)
+    {
+        if constexpr (kBytes == 4) return u32x2{0u, b};
+        else if constexpr (V == 4) return u32x2{0u, b << 16};
+        else return u32x2{b << 16, 0u};
+    }
+    __device__ __forceinline__ static u32x2 as_first(unsigned int b) { return u32x2{b, 0u}; }
+    // [p, e0 .. e(V-2)]
+    __device__ __forceinline__ static u32x2 shift_in_left(u32x2 v, unsigned int p)
+    {
+        if constexpr (kBytes == 4) return u32x2{p, v.x};
+        else if constexpr (V == 4) return u32x2{(v.x << 16) | p, (v.y << 16) | (v.x >> 16)};
+        else return u32x2{(v.x << 16) | p, 0u};
+    }
+    // [e1 .. e(V-1), q]
+    __device__ __forceinline__ static u32x2 shift_in_right(u32x2 v, unsigned int q)
+    {
+        if constexpr (kBytes == 4) return u32x2{v.y, q};
+        else if constexpr (V == 4) return u32x2{(v.x >> 16) | (v.y << 16), (v.y >> 16) | (q << 16)};
+        else return u32x2{(v.x >> 16) | (q << 16), 0u};
+    }
+    // elements 1 .. V-1 of the group at p (the first one belongs to another block)
+    __device__ __forceinline__ static void store_tail(T* p, u32x2 v)
+    {
+        if constexpr (kBytes == 4) {
+            *(unsigned int*)(p + 1) = v.y;
+        } else if constexpr (V == 4) {
+            *(unsigned short*)(p + 1) = (unsigned short)(v.x >> 16);
+            *(unsigned int*)(p + 2) = v.y;
+        } else {
+            *(unsigned short*)(p + 1) = (unsigned short)(v.x >> 16);
+        }
+    }
+    // elements 0 .. V-2 of the group at p (the last one belongs to another block)
+    __device__ __forceinline__ static void store_head(T* p, u32x2 v)
+    {
+        if constexpr (kBytes == 4) {
+            *(unsigned int*)p = v.x;
+        } else if constexpr (V == 4) {
+            *(unsigned int*)p = v.x;
+            *(unsigned short*)(p + 2) = (unsigned short)(v.y & 0xffffu);
+        } else {
+            *(unsigned short*)p = (unsigned short)(v.x & 0xffffu);
+        }
+    }
+    __device__ __forceinline__ static R get(u32x2 v, int k)
+    {
+        if constexpr (kBytes == 8) {
+            return __hiloint2double((int)v.y, (int)v.x);
+        } else if constexpr (kBytes == 4) {
+            return __uint_as_float(k == 0 ? v.x : v.y);
+        } else {
+            const unsigned int word = (k < 2) ? v.x : v.y;
+            const unsigned short b = (unsigned short)((k & 1) ? (word >> 16) : (word & 0xffffu));
+            if constexpr (S::kind == kStoreBF16) return bf16_to_f32(b);
+            else return (float)__builtin_bit_cast(_Float16, b);
+        }
+    }
+    __device__ __forceinline__ static void set(u32x2& v, int k, R r)
+    {
+        if constexpr (kBytes == 8) {
+            v.x = (unsigned int)__double2loint(r);
+            v.y = (unsigned int)__double2hiint(r);
+        } else if constexpr (kBytes == 4) {
+            if (k == 0) v.x = __float_as_uint(r);
+            else v.y = __float_as_uint(r);
+        } else {
+            unsigned short b;
+            if constexpr (S::kind == kStoreBF16) b = __builtin_bit_cast(unsigned short, (__bf16)r);
+            else b = __builtin_bit_cast(unsigned short, (_Float16)r);
+            const unsigned int word = (k < 2) ? v.x : v.y;
+            const unsigned int nw = (k & 1) ? ((word & 0xffffu) | ((unsigned int)b << 16)) : ((word & 0xffff0000u) | b);
+            if (k < 2) v.x = nw;
+            else v.y = nw;
+        }
+    }
+    // elements k and k + 1 (k even) of a group of 2-byte elements, both
+    // rounded to nearest even by one packed conversion
+    __device__ __forceinline__ static void set_pair(u32x2& v, int k, float r0, float r1)
+    {
+        static_assert(kBytes == 2, "pairs of 2-byte elements");
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        unsigned int word;
+        if constexpr (S::kind == kStoreBF16) {
+            typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+            word = __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2{r0, r1}), b16x2));
+        } else {
+            typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+            word = __builtin_bit_cast(unsigned int, __builtin_convertvector((f32x2{r0, r1}), h16x2));
+        }
+        if (k < 2) v.x = word;
+        else v.y = word;
+    }
+};
+
+// Cells x0 .. x0 + V - 1 of one x-row owned by one thread.
+struct RowLanes {
+    int x0, nx;
+    bool active;
+    __device__ __forceinline__ unsigned wrapx(int x) const
+    {
+        return (unsigned)(x < 0 ? x + nx : (x >= nx ? x - nx : x));
+    }
+};
+
+}  // namespace lbmwf

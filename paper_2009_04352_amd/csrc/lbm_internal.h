@@ -1,5 +1,6 @@
 // Internal interface between the C-ABI (lbm_capi.hip) and the device kernels
-// (lbm_kernels.hip).  Not installed; the public interface is include/lbmwf.h.
+// (lbm_kernels.hip; the step kernels in lbm_step.h, instantiated per store in
+// step_*.hip).  Not installed; the public interface is include/lbmwf.h.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,13 +17,57 @@ struct DevFlags {
 
 enum Boundary { kBB = 0, kWFB = 1, kFreeSlip = 2 };
 
+// Population layout on the device: slot a holds N = nx ny nz values; within
+// a slot, x-rows are grouped in bricks of `brick` consecutive y (the last
+// brick may be shorter), ordered [y / brick][z][y % brick][x].  brick = ny is
+// the plain [z][y][x] order.  Neighbouring z-planes of a brick lie brick rows
+// apart instead of a whole plane, which keeps the shifted accesses of a step
+// close to each other in memory.
+__host__ __device__ inline long long row_index(int y, int z, int ny, int nz, int brick)
+{
+    const int yb = y / brick, yi = y - yb * brick;
+    const int bk = (ny - yb * brick) < brick ? (ny - yb * brick) : brick;
+    return (long long)yb * brick * nz + (long long)z * bk + yi;
+}
+
+__host__ __device__ inline long long cell_index(int x, int y, int z, int nx, int ny, int nz, int brick)
+{
+    return row_index(y, z, ny, nz, brick) * nx + x;
+}
+
+// Division by a launch constant d as a multiply and a shift: for 0 <= n < 2^31,
+// n / d == (n m) >> s with s = 31 + ceil(log2 d), m = floor(2^s / d) + 1
+// (Granlund & Montgomery 1994, Thm. 4.2: 2^s < m d <= 2^s + 2^(s-31)).
+struct FastDiv {
+    unsigned long long m;
+    int s;
+};
+
+inline FastDiv make_fastdiv(int d)
+{
+    int l = 0;
+    while ((1ll << l) < d) ++l;
+    FastDiv f;
+    f.s = 31 + l;
+    f.m = ((1ull << f.s) / (unsigned long long)d) + 1;
+    return f;
+}
+
+__host__ __device__ inline int fdiv(int n, FastDiv f) { return (int)(((unsigned long long)n * f.m) >> f.s); }
+
 // Parameters of one fused step launch (or of one instance of a batched
 // launch).  A block processes one tile: rpb whole x-rows of one z-plane, or
-// one segment of tile_x * vw cells of a single x-row.
+// one segment of tile_x * vw cells of a single x-row.  Tiles are numbered in
+// memory order: x segment, row group within a brick, z, brick.
 struct StepArgs {
-    void* h;              // populations h_a = f_a - w_a, [a][z][y][x]
+    void* h;              // populations h_a = f_a - w_a, bricked layout (row_index)
     long long n;          // cells
     int nx, ny, nz;
+    int brick;            // rows per brick (1 <= brick <= ny; rpb > 1 needs brick == ny)
+    int bgroups;          // row groups per brick (brick / rpb, or nyt for a single brick)
+    int nbricks;          // bricks (the last one may hold fewer groups)
+    int bg_last;          // row groups of the last brick
+    FastDiv fd_ntx, fd_brick_tiles, fd_bgroups, fd_bg_last, fd_tpr;  // tile and thread decomposition
     int tile_x;           // threads per block
     int vw;               // cells per thread (1, 2 or 4): a group of vw * sizeof(store) <= 8 bytes
     int ntx;              // x segments per row (1: a block holds whole rows)
@@ -31,7 +76,7 @@ struct StepArgs {
     int ntiles;           // tiles (= blocks) of this instance
     int tile_begin;       // first tile of this instance in a batched launch
     int bc;               // boundary (read by batched launches)
-    int xcd_remap;        // 1: give each XCD a contiguous range of tiles
+    int xcd_remap;        // 0: tile = block; c + 1: XCDs take chunks of 2^c tiles in turn
     int newton_maxit;
     double tau0;          // molecular relaxation time
     double cs2_18;        // 18 Cs^2 (Smagorinsky closure)
@@ -49,6 +94,7 @@ struct ObsArgs {
     const void* h;
     long long n;
     int nx, ny, nz;
+    int brick;            // rows per brick of the population layout
     int layout_s;         // 0: post-collision layout (after an even number of steps), 1: streamed
     int bc;               // boundary used for the reflections still to be made
     int layout_spec;      // reflections already made (streamed layout) were mirror images
@@ -64,24 +110,32 @@ struct ObsArgs {
 
 // launchers (lbm_kernels.hip); each returns the launch status
 int step_vector_width(int store, int nx);
-void step_geometry(int nx, int ny, int nz, int tile_x, int vw, StepArgs& a);
+void step_geometry(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a);
+bool brick_ok(int ny, int brick, int rpb);
 hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, int n, const StepArgs* dev_table,
                              const int* dev_tile_inst, int ntiles, int xcd_remap, hipStream_t s);
 bool step_vector_width_ok(int store, int nx, int vw);
 hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s);
 hipError_t launch_stats_reduce(const double* partials, int ntx, int ny, int nz, int nx, double* acc, hipStream_t s);
-hipError_t launch_init_spalding(int store, void* h, long long n, int nx, int ny, int nz, const double* profile,
-                                double noise, unsigned long long seed, hipStream_t s);
-hipError_t launch_set_state(int store, void* h, long long n, long long first, long long count, const double* in,
-                            hipStream_t s);
-hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int layout_s,
+hipError_t launch_init_spalding(int store, void* h, long long n, int nx, int ny, int nz, int brick,
+                                const double* profile, double noise, unsigned long long seed, hipStream_t s);
+hipError_t launch_set_state(int store, void* h, long long n, int nx, int ny, int nz, int brick, long long first,
+                            long long count, const double* in, hipStream_t s);
+hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int brick, int layout_s,
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
                             hipStream_t s);
 hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s);
-hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int from_spec, int to_spec,
-                           double* tmp, hipStream_t s);
+hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int brick, int from_spec,
+                           int to_spec, double* tmp, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_codec(int store, const float* in, float* out, long long n, hipStream_t s);
+// per-store step launchers (lbm_step.h), dispatched by launch_step / launch_batch_step
+template <typename S>
+hipError_t launch_step_store(bool odd, int bc, const StepArgs& a, hipStream_t s);
+template <typename S>
+hipError_t launch_batch_store(bool odd, const StepArgs& a0, const StepArgs* table, const int* tile_inst, int ntiles,
+                              hipStream_t s);
+
 hipError_t launch_wall_utau(const double* U, int n, double y1, double nu, double kappa, double bconst, double tol,
                             int maxit, double* utau, int* iters, hipStream_t s);
 

@@ -67,6 +67,25 @@ def test_create_validates_arguments(L):
         lib.lbm_destroy(h)
 
 
+def test_brick_layout_parameter(L):
+    """Rows per brick: bricks of 8 rows when every block holds one row, the
+    plain layout (one brick of ny rows) when a block holds several."""
+    lib = L.lib()
+    v = C.c_double()
+    for (nx, ny), want in (((512, 128), 8), ((512, 5), 5), ((32, 16), 16)):
+        h = C.c_void_p()
+        assert lib.lbm_create(C.byref(L.Grid(nx, ny, 4)), 0.6, 0.1, 0.41, 5.5, 0.0, C.byref(h)) == 0
+        try:
+            assert lib.lbm_get_param(h, L.LBM_P_BRICK, C.byref(v)) == 0 and v.value == want, (nx, ny)
+            assert lib.lbm_set_param(h, L.LBM_P_BRICK, 3) == 0
+            assert lib.lbm_get_param(h, L.LBM_P_BRICK, C.byref(v)) == 0
+            assert v.value == (3 if want != ny or nx >= 256 else ny)
+            assert lib.lbm_set_param(h, L.LBM_P_BRICK, -1) == L.LBM_E_ARG
+            assert lib.lbm_set_param(h, L.LBM_P_BRICK, 2.5) == L.LBM_E_ARG
+        finally:
+            lib.lbm_destroy(h)
+
+
 def test_status_strings(L):
     lib = L.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):

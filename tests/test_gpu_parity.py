@@ -126,12 +126,13 @@ def test_initial_state(P, orc, store):
 
 
 def test_device_newton_matches_spalding(P, orc):
-    """The kernel's FP64 Newton solve: Spalding residual <= 1e-10 and u_tau equal
-    to the oracle's to 1e-13 relative."""
+    """The kernel's FP64 Newton solve (started from an FP32 estimate, where the
+    oracle starts from the viscous guess): Spalding residual <= 1e-10 and u_tau
+    equal to the oracle's to 1e-13 relative; few FP64 steps at any R."""
     U = np.geomspace(1e-7, 0.2, 200)
     for y1, nu in ((1.0, 2.04e-5), (1.0, 1e-3), (0.5, 1e-4)):
         ut, it = P.device_wall_utau(U, y1, nu)
-        assert np.all(ut > 0) and np.all(it >= 1) and np.all(it < 100)
+        assert np.all(ut > 0) and np.all(it >= 1) and np.all(it <= 6)
         for Ui, ui in zip(U, ut):
             yp, up = y1 * ui / nu, Ui / ui
             assert abs(orc.spalding_yplus(up) - yp) <= 1e-10 * yp
@@ -139,7 +140,9 @@ def test_device_newton_matches_spalding(P, orc):
             assert abs(ui - ref) <= 1e-13 * ref
     ut, it = P.device_wall_utau(np.array([0.0, 1.0]), 1.0, 1e-5)
     assert ut[0] == 0.0 and it[0] == 0
-    assert ut[1] == -1.0 and it[1] == 100   # beyond the cap: reported, not returned
+    assert ut[1] > 0.0 and it[1] <= 6        # R = 1e5: the FP32 start leaves a few FP64 steps
+    ut, it = P.device_wall_utau(np.array([0.0, 1e-2]), 1.0, 1e-5, maxit=1)
+    assert ut[1] == -1.0 and it[1] == 1      # beyond the cap: reported, not returned
 
 
 @pytest.mark.parametrize("bc", BCS)
