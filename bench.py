@@ -86,7 +86,7 @@ def run_store(P, W, name, store, steps, warmup):
     nx, ny, nz = p["grid"]
     n = nx * ny * nz
     ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
-                   tiles=W.LAUNCH_TILES[store], graph_steps=0)
+                   tiles=W.launch_tiles(name, store), graph_steps=0)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     total_ms, odd_ms, even_ms = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
     status, first_bad = ch.sync()
@@ -229,7 +229,7 @@ def bench_single(P, W, args, copy_gbs):
     hd = per_store[head]
     config = {"workload": "%s: %s" % (args.workload, wl["desc"]), "grid": [nx, ny, nz], "store": head,
               "boundary": "wfb", "re_tau": wl["re_tau"], "tau0": p["tau0"], "fx": p["fx"],
-              "launch": list(W.LAUNCH_TILES[head]), "parallelism": "single GPU"}
+              "launch": list(W.launch_tiles(args.workload, head)), "parallelism": "single GPU"}
     return hd, per_store, config, roofline(hd, head, n, args.workload), "f32" if head != "f64" else "f64"
 
 

@@ -78,6 +78,11 @@ extern "C" {
                                * when every block of both step kernels holds a single row, otherwise the
                                * plain order (brick = ny).  Fixed once the state is initialised; reading it
                                * gives the height in use.  Results do not depend on it. */
+#define LBM_P_ODD_ROWS 15     /* odd-step kernel: 0 = blocks of rows or row segments exchanging through LDS;
+                               * 1 = (default) one wavefront per row walking it in 64-lane segments, for FP16/BF16
+                               * stores whose rows are longer than an odd-step block; 2 = walk rows whenever nx is a
+                               * multiple of 64 cells
+                               * per thread.  Results do not depend on it (statistics sums up to summation order). */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -220,7 +225,8 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const 
 void lbm_batch_destroy(lbm_batch* batch);
 /* Keys LBM_P_STORE (before binding), LBM_P_TILE_ODD, LBM_P_TILE_EVEN,
  * LBM_P_VECTOR (0 = the widest group every instance allows), LBM_P_XCD_REMAP,
- * LBM_P_GRAPH_STEPS, and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT /
+ * LBM_P_GRAPH_STEPS, LBM_P_ODD_ROWS (walks rows only if every instance's rows
+ * qualify), and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT /
  * LBM_P_BRICK (before initialisation) applied to every instance.  Block
  * sizes and cells per thread that an initialised instance's layout cannot
  * run with give LBM_E_STATE. */

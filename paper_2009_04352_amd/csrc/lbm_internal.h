@@ -68,6 +68,8 @@ struct StepArgs {
     int nbricks;          // bricks (the last one may hold fewer groups)
     int bg_last;          // row groups of the last brick
     FastDiv fd_ntx, fd_brick_tiles, fd_bgroups, fd_bg_last, fd_tpr;  // tile and thread decomposition
+    int nseg;             // odd step by rows: each wavefront walks one row in nseg segments of 64 vw
+                          // cells (tile_x / 64 rows per block); 0: the tile kernel
     int tile_x;           // threads per block
     int vw;               // cells per thread (1, 2 or 4): a group of vw * sizeof(store) <= 8 bytes
     int ntx;              // x segments per row (1: a block holds whole rows)
@@ -111,6 +113,8 @@ struct ObsArgs {
 // launchers (lbm_kernels.hip); each returns the launch status
 int step_vector_width(int store, int nx);
 void step_geometry(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a);
+bool rows_ok(int nx, int vw);
+void step_geometry_rows(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a);
 bool brick_ok(int ny, int brick, int rpb);
 hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, int n, const StepArgs* dev_table,
                              const int* dev_tile_inst, int ntiles, int xcd_remap, hipStream_t s);

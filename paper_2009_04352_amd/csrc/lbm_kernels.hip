@@ -53,6 +53,32 @@ void step_geometry(int nx, int ny, int nz, int tile_x, int vw, int brick, StepAr
     a.fd_bgroups = make_fastdiv(a.bgroups);
     a.fd_bg_last = make_fastdiv(a.bg_last);
     a.fd_tpr = make_fastdiv(a.ntx == 1 ? tpr_full : tile_x);
+    a.nseg = 0;
+}
+
+// The odd step by rows needs rows of whole 64-lane segments.
+bool rows_ok(int nx, int vw) { return nx % (64 * vw) == 0; }
+
+// Geometry of the odd step by rows: a tile is tile_x / 64 consecutive rows in
+// memory order, one per wavefront; the decomposition of a memory row into
+// (brick, z, row in brick) uses the fields of single-row tiles.
+void step_geometry_rows(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a)
+{
+    step_geometry(nx, ny, nz, tile_x, vw, brick, a);   // for vw and the common fields
+    a.ntx = 1;
+    a.rpb = 1;
+    a.nyt = ny;
+    a.bgroups = brick >= ny ? ny : brick;
+    a.nbricks = (ny + a.bgroups - 1) / a.bgroups;
+    a.bg_last = ny - (a.nbricks - 1) * a.bgroups;
+    a.fd_ntx = make_fastdiv(1);
+    a.fd_brick_tiles = make_fastdiv(a.bgroups * nz);
+    a.fd_bgroups = make_fastdiv(a.bgroups);
+    a.fd_bg_last = make_fastdiv(a.bg_last);
+    a.fd_tpr = make_fastdiv(tile_x);
+    const int waves = tile_x / 64;
+    a.ntiles = (int)(((long long)ny * nz + waves - 1) / waves);
+    a.nseg = nx / (64 * vw);
 }
 
 static bool step_args_ok(int store, const StepArgs& a)
@@ -62,8 +88,14 @@ static bool step_args_ok(int store, const StepArgs& a)
     // the thread part of an address is (row in tile * nx + x) * bytes < 32 bits
     if ((long long)a.nx * a.ny * store_bytes(store) > 0xffffffffll) return false;
     StepArgs g = a;
-    step_geometry(a.nx, a.ny, a.nz, a.tile_x, a.vw, a.brick, g);
-    if (!brick_ok(a.ny, a.brick, g.rpb)) return false;
+    if (a.nseg > 0) {
+        if (!rows_ok(a.nx, a.vw)) return false;
+        step_geometry_rows(a.nx, a.ny, a.nz, a.tile_x, a.vw, a.brick, g);
+        if (a.brick < 1 || a.brick > a.ny || g.nseg != a.nseg) return false;
+    } else {
+        step_geometry(a.nx, a.ny, a.nz, a.tile_x, a.vw, a.brick, g);
+        if (!brick_ok(a.ny, a.brick, g.rpb)) return false;
+    }
     // the decomposition must be the one step_geometry derives (the batched
     // launch reads it from the device table)
     auto same = [](const FastDiv& x, const FastDiv& y) { return x.m == y.m && x.s == y.s; };
@@ -94,7 +126,9 @@ hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, in
     int total = 0;
     for (int i = 0; i < n; ++i) {
         if (!step_args_ok(store, host_table[i]) || host_table[i].tile_begin != total) return hipErrorInvalidValue;
-        if (host_table[i].tile_x != host_table[0].tile_x || host_table[i].vw != host_table[0].vw) return hipErrorInvalidValue;
+        if (host_table[i].tile_x != host_table[0].tile_x || host_table[i].vw != host_table[0].vw ||
+            (host_table[i].nseg > 0) != (host_table[0].nseg > 0))
+            return hipErrorInvalidValue;
         total += host_table[i].ntiles;
     }
     if (total != ntiles) return hipErrorInvalidValue;

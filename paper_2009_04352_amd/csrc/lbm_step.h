@@ -22,6 +22,8 @@
 // read of slot opp(mirror a) at c - e_a^par is the slot the same cell writes
 // its outgoing mirror(b) population to, b = opp(a).
 #pragma once
+#include <type_traits>
+
 #include "lbm_device.h"
 
 namespace lbmwf {
@@ -70,6 +72,67 @@ __device__ __forceinline__ u32x2 halo_as_first(const typename S::T* p)
     else return Ln::as_first(Ln::load_elem(p));
 }
 
+// a3-a6 for the V cells of a group in place: decode, wall-function bounce
+// (wall_wfb: the cells are wall-adjacent and the boundary is WFB), moments,
+// Smagorinsky, BGK with the body force, encode.  Accumulates the sampled
+// velocity sums, the largest Newton iteration count and the failure flags.
+template <typename S, int V, bool MAYBE_WFB, bool STATS>
+__device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p, bool wall_wfb, bool top,
+                                              double (&sm)[7], int& iters, bool& bad, bool& newton_fail)
+{
+    using R = typename S::R;
+    using Ln = Lane<S, V>;
+    constexpr bool PAIRS = (sizeof(typename S::T) == 2) && (V >= 2);
+    auto cell = [&](int k, R (&f)[kQ]) {
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            f[a] = Ln::get(w[a], k);
+        });
+        // a3: wall-function bounce at wall-adjacent cells
+        if constexpr (MAYBE_WFB) {
+            if (wall_wfb) {
+                int it = 0;
+                bool fail = false;
+                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, it,
+                               fail);
+                iters = max(iters, it);
+                newton_fail = newton_fail || fail;
+            }
+        }
+        // a4-a6: moments, Smagorinsky, BGK + body force
+        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
+        bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
+        if constexpr (STATS) {
+            const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
+            sm[0] += ux; sm[1] += uy; sm[2] += uz;
+            sm[3] += ux * ux; sm[4] += uy * uy; sm[5] += uz * uz; sm[6] += ux * uy;
+        }
+    };
+    if constexpr (PAIRS) {
+        // 2-byte stores: two cells are encoded by one packed conversion
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+            R f0[kQ], f1[kQ];
+            cell(k, f0);
+            cell(k + 1, f1);
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                Ln::set_pair(w[a], k, f0[a], f1[a]);
+            });
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            R f[kQ];
+            cell(k, f);
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                Ln::set(w[a], k, f[a]);
+            });
+        }
+    }
+}
+
 // Boundary of a launch: fixed at compile time for a single channel, read
 // from the instance table for batched launches (instances differ).
 constexpr int kBCRuntime = 3;
@@ -95,8 +158,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
     using T = typename S::T;
     using R = typename S::R;
     using Ln = Lane<S, V>;
-    constexpr bool PAIRS = (sizeof(T) == 2) && (V >= 2);
-    extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x]
+    extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x], then halo[kNX]
 
     int tile;
     StepArgs p;
@@ -202,6 +264,25 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
         for_each_dir([&](auto A) { w[decltype(A)::value] = u32x2{0u, 0u}; });
     }
     if constexpr (ODD) {
+        // A partial segment's two edge threads fetch the one element beyond
+        // the segment together with the group loads (so that its latency is
+        // not paid after the barrier) and leave it in LDS: halo[xslot(a)].
+        u32x2* halo = xbuf + kNX * nthr;
+        if (!whole && L.active && (tr == 0 || tr == nact - 1)) {
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
+                if constexpr (ex != 0) {
+                    const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+                    const bool shifted = !from_wall || (MAYBE_SPEC && spec && is_tangential(a));
+                    char* src = from_wall ? base(opp(mirror_y(a)), 0, -ez) : base(opp(a), -ey, -ez);
+                    if (shifted && ex == 1 && tr == 0)
+                        halo[xslot(a)] = halo_as_last<S, V>(at(src, xoff(L.wrapx(L.x0 - 1))));
+                    if (shifted && ex == -1 && tr == nact - 1)
+                        halo[xslot(a)] = halo_as_first<S, V>(at(src, xoff(L.wrapx(L.x0 + V))));
+                }
+            });
+        }
         // the x-shifted groups hold cells x0 .. x0 + V - 1 of the source row; shift by -e_x
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
@@ -221,17 +302,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
                             u32x2 nb;
                             if (tr > 0) nb = xb[t - 1];
                             else if (whole) nb = xb[tb + nact - 1];
-                            else nb = halo_as_last<S, V>(at(from_wall ? base(opp(mirror_y(a)), 0, -ez)
-                                                                      : base(opp(a), -ey, -ez),
-                                                            xoff(L.wrapx(L.x0 - 1))));
+                            else nb = halo[xslot(a)];
                             w[a] = join_left<S, V>(w[a], nb);
                         } else {                  // needs the element at x0 + V
                             u32x2 nb;
                             if (tr < nact - 1) nb = xb[t + 1];
                             else if (whole) nb = xb[tb];
-                            else nb = halo_as_first<S, V>(at(from_wall ? base(opp(mirror_y(a)), 0, -ez)
-                                                                       : base(opp(a), -ey, -ez),
-                                                             xoff(L.wrapx(L.x0 + V))));
+                            else nb = halo[xslot(a)];
                             w[a] = join_right<S, V>(w[a], nb);
                         }
                     }
@@ -243,55 +320,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
     double sm[7] = {0, 0, 0, 0, 0, 0, 0};
     int iters = 0;
     bool bad = false, newton_fail = false;
-    // a3-a6 for cell k of the group: decode, wall function, collision
-    auto cell = [&](int k, R (&f)[kQ]) {
-        for_each_dir([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            f[a] = Ln::get(w[a], k);
-        });
-        // a3: wall-function bounce at wall-adjacent cells
-        if constexpr (MAYBE_WFB) {
-            if (wfb && (bot || top) && L.active) {
-                int it = 0;
-                bool fail = false;
-                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, it,
-                               fail);
-                iters = max(iters, it);
-                newton_fail = newton_fail || fail;
-            }
-        }
-        // a4-a6: moments, Smagorinsky, BGK + body force
-        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
-        bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
-        if constexpr (STATS) {
-            const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
-            sm[0] += ux; sm[1] += uy; sm[2] += uz;
-            sm[3] += ux * ux; sm[4] += uy * uy; sm[5] += uz * uz; sm[6] += ux * uy;
-        }
-    };
-    if constexpr (PAIRS) {
-        // 2-byte stores: two cells are encoded by one packed conversion
-#pragma unroll
-        for (int k = 0; k < V; k += 2) {
-            R f0[kQ], f1[kQ];
-            cell(k, f0);
-            cell(k + 1, f1);
-            for_each_dir([&](auto A) {
-                constexpr int a = decltype(A)::value;
-                Ln::set_pair(w[a], k, f0[a], f1[a]);
-            });
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            R f[kQ];
-            cell(k, f);
-            for_each_dir([&](auto A) {
-                constexpr int a = decltype(A)::value;
-                Ln::set(w[a], k, f[a]);
-            });
-        }
-    }
+    collide_group<S, V, MAYBE_WFB, STATS>(w, p, wfb && (bot || top) && L.active, top, sm, iters, bad, newton_fail);
     if (L.active && (bad || newton_fail)) {
         atomicOr(&p.flags->status, (bad ? 1 : 0) | (newton_fail ? 2 : 0));
         atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
@@ -375,11 +404,336 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
     if (tile == 0 && t == 0) p.flags->cnt[ODD ? 0 : 1] = p.flags->cnt[ODD ? 1 : 0] + 1;
 }
 
+// Edge elements of a group for the odd step by rows: one element's bits
+// (V >= 2) or, for one-element groups, the group itself.
+template <typename S, int V>
+struct Edge {
+    using Ln = Lane<S, V>;
+    using E = std::conditional_t<V == 1, u32x2, unsigned int>;
+    __device__ __forceinline__ static E last(u32x2 g)
+    {
+        if constexpr (V == 1) return g;
+        else return Ln::last(g);
+    }
+    __device__ __forceinline__ static E first(u32x2 g)
+    {
+        if constexpr (V == 1) return g;
+        else return Ln::first(g);
+    }
+    // [e, g0 .. g(V-2)] and [g1 .. g(V-1), e]
+    __device__ __forceinline__ static u32x2 join_left(u32x2 g, E e)
+    {
+        if constexpr (V == 1) return e;
+        else return Ln::shift_in_left(g, e);
+    }
+    __device__ __forceinline__ static u32x2 join_right(u32x2 g, E e)
+    {
+        if constexpr (V == 1) return e;
+        else return Ln::shift_in_right(g, e);
+    }
+    __device__ __forceinline__ static E up(E e)  // lane i gets lane i - 1's value (lane 0 its own)
+    {
+        if constexpr (V == 1) return u32x2{(unsigned)__shfl_up((int)e.x, 1, 64), (unsigned)__shfl_up((int)e.y, 1, 64)};
+        else return (unsigned)__shfl_up((int)e, 1, 64);
+    }
+    __device__ __forceinline__ static E down(E e)  // lane i gets lane i + 1's value (lane 63 its own)
+    {
+        if constexpr (V == 1)
+            return u32x2{(unsigned)__shfl_down((int)e.x, 1, 64), (unsigned)__shfl_down((int)e.y, 1, 64)};
+        else return (unsigned)__shfl_down((int)e, 1, 64);
+    }
+    __device__ __forceinline__ static E lane_value(E e, int l)  // lane l's value, wave-uniform
+    {
+        if constexpr (V == 1)
+            return u32x2{(unsigned)__builtin_amdgcn_readlane((int)e.x, l), (unsigned)__builtin_amdgcn_readlane((int)e.y, l)};
+        else return (unsigned)__builtin_amdgcn_readlane((int)e, l);
+    }
+    __device__ __forceinline__ static u32x2 lane_group(u32x2 g, int l)
+    {
+        return u32x2{(unsigned)__builtin_amdgcn_readlane((int)g.x, l), (unsigned)__builtin_amdgcn_readlane((int)g.y, l)};
+    }
+    __device__ __forceinline__ static E uniform(E e)  // a value every lane holds alike, as a scalar
+    {
+        if constexpr (V == 1)
+            return u32x2{(unsigned)__builtin_amdgcn_readfirstlane((int)e.x), (unsigned)__builtin_amdgcn_readfirstlane((int)e.y)};
+        else return (unsigned)__builtin_amdgcn_readfirstlane((int)e);
+    }
+    // the element at p (every lane loads the same address)
+    __device__ __forceinline__ static E load_at(const typename S::T* p)
+    {
+        if constexpr (V == 1) return Ln::template load<false>(p);
+        else return Ln::load_elem(p);
+    }
+};
+
+// The odd step by rows, for rows of whole 64-lane segments.  Each wavefront
+// owns one row (a block holds blockDim.x / 64 consecutive rows in memory
+// order) and walks it in nseg segments of 64 V cells.  The x-shift of the
+// streamwise directions moves one element across lanes by a shuffle; across
+// segments, and around the periodic row, the edge elements are carried in
+// scalar registers:
+//   gather, e_x = +1: lane 0 takes the previous segment's last element (for
+//     the first segment: the row's last element, loaded at the start);
+//   gather, e_x = -1: lane 63 takes the next segment's first element, loaded
+//     with the segment (for the last segment: the row's first element, kept
+//     from the first segment);
+//   store, e_x = +1: the first segment's first group waits for the row's last
+//     post-collision element and is written after the walk;
+//   store, e_x = -1: each segment's last group waits for the next segment's
+//     first post-collision element (the last one for the row's first).
+// Every element a cell reads is read before any cell writes it: an AA cell
+// reads exactly the slots it writes, and carried elements are taken from the
+// loads of their own segment.  No LDS, no barrier, and no memory line is
+// written in parts by two wavefronts.
+template <typename S, int V, int BCT, bool STATS>
+__global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepArgs* __restrict__ table,
+                                                        const int* __restrict__ tile_inst, int ntiles_all)
+{
+    constexpr bool BATCH = (BCT == kBCRuntime);
+    using T = typename S::T;
+    using Ln = Lane<S, V>;
+    using Ed = Edge<S, V>;
+    using E = typename Ed::E;
+    constexpr bool MAYBE_WFB = BATCH || BCT == kWFB;
+    constexpr bool MAYBE_SPEC = BATCH || BCT != kBB;
+
+    int tile;
+    StepArgs p;
+    if constexpr (BATCH) {
+        const int gt = tile_of_block(blockIdx.x, ntiles_all, p0.xcd_remap);
+        p = table[tile_inst[gt]];
+        tile = gt - p.tile_begin;
+    } else {
+        p = p0;
+        tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
+    }
+    const bool spec = BATCH ? (p.bc != kBB) : (BCT != kBB);
+    const bool wfb = BATCH ? (p.bc == kWFB) : (BCT == kWFB);
+    if (tile == 0 && threadIdx.x == 0) p.flags->cnt[0] = p.flags->cnt[1] + 1;
+
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int row = tile * ((int)blockDim.x >> 6) + wave;   // memory-order row of this wavefront
+    if (row >= p.ny * p.nz) return;
+    // memory row -> (brick, z, row in brick) -> (y, z)
+    const int yb = fdiv(row, p.fd_brick_tiles);
+    const int rem = row - yb * p.bgroups * p.nz;
+    const bool last_brick = (yb == p.nbricks - 1);
+    const int bk = last_brick ? p.bg_last : p.bgroups;         // rows of this brick
+    const int z = last_brick ? fdiv(rem, p.fd_bg_last) : fdiv(rem, p.fd_bgroups);
+    const int yi0 = rem - z * bk;
+    const int y = yb * p.brick + yi0;
+    const bool bot = (y == 0), top = (y == p.ny - 1);
+    const int zm = (z == 0) ? p.nz - 1 : z - 1;
+    const int zp = (z == p.nz - 1) ? 0 : z + 1;
+    const bool plain = (p.brick >= p.ny);
+    const int bkn = min(p.brick, p.ny - (yb + 1) * p.brick);
+    auto row_of = [&](int dy, int zz) -> long long {
+        const int yi = yi0 + dy;
+        const long long in_brick = (long long)yb * p.brick * p.nz + (long long)zz * bk + yi;
+        const long long prev = ((long long)(yb - 1) * p.nz + zz) * p.brick + (p.brick - 1);
+        const long long next = (long long)(yb + 1) * p.brick * p.nz + (long long)zz * bkn;
+        const long long bricked = yi < 0 ? prev : (yi >= bk ? next : in_brick);
+        return plain ? (long long)zz * p.ny + (y + dy) : bricked;
+    };
+    long long row_nx[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+            row_nx[dy + 1][dz + 1] = row_of(dy, dz < 0 ? zm : (dz > 0 ? zp : z)) * p.nx;
+    const long long N = p.n;
+    // The row starts are recomputed in every segment from hbits, which the
+    // empty asm statement makes opaque to the compiler: kept live across the
+    // walk, 38 of them would not fit in scalar registers.
+    typedef __attribute__((address_space(1))) char gchar;   // global memory, so that loads stay global
+    unsigned long long hbits = (unsigned long long)p.h;
+    auto base = [&](int s, int dy, int dz) -> char* {
+        gchar* g = (gchar*)hbits;
+        return (char*)(g + ((long long)s * N + row_nx[dy + 1][dz + 1]) * (long long)sizeof(T));
+    };
+    auto at = [&](char* b, unsigned off) -> T* { return (T*)(b + off); };
+    // the source row of direction a (its x-shift applies unless it is bounced back unshifted)
+    auto src_of = [&](auto A) -> char* {
+        constexpr int a = decltype(A)::value;
+        constexpr int ey = kEy[a], ez = kEz[a];
+        const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+        if (from_wall) return (MAYBE_SPEC && spec && is_tangential(a)) ? base(opp(mirror_y(a)), 0, -ez) : base(a, 0, 0);
+        return base(opp(a), -ey, -ez);
+    };
+    auto shifted_in = [&](auto A) -> bool {
+        constexpr int a = decltype(A)::value;
+        constexpr int ey = kEy[a];
+        const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+        return kEx[a] != 0 && (!from_wall || (MAYBE_SPEC && spec && is_tangential(a)));
+    };
+    // the destination row of direction a and whether its x-shift applies
+    auto dst_of = [&](auto A) -> char* {
+        constexpr int a = decltype(A)::value;
+        constexpr int ey = kEy[a], ez = kEz[a];
+        const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+        const bool mirrored = to_wall && MAYBE_SPEC && spec && is_tangential(a);
+        if (to_wall && !mirrored) return base(opp(a), 0, 0);  // bounce-back into the cell's own slot
+        return mirrored ? base(mirror_y(a), 0, ez) : base(a, ey, ez);
+    };
+    auto shifted_out = [&](auto A) -> bool {
+        constexpr int a = decltype(A)::value;
+        constexpr int ey = kEy[a];
+        const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+        const bool mirrored = to_wall && MAYBE_SPEC && spec && is_tangential(a);
+        return kEx[a] != 0 && (!to_wall || mirrored);
+    };
+
+    const int nseg = p.nseg;
+    const unsigned sbytes = (unsigned)sizeof(T);
+    E gcar[kNX], gwrap[kNX], scar[kNX], swrap[kNX];
+    // groups waiting for an element of another segment, per wavefront: [0]
+    // e_x = +1, written by lane 0 (first segment), [1] e_x = -1, written by
+    // lane 63 and read by lane 0 one segment later (same wavefront, so the
+    // LDS accesses stay in program order)
+    __shared__ u32x2 dfr[kMaxBlock / 64][2][kNX];
+    // the row's last element for the first segment's e_x = +1 gather
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        if constexpr (kEx[a] == 1) {
+            if (shifted_in(A)) gcar[xslot(a)] = Ed::uniform(Ed::load_at(at(src_of(A), (unsigned)(p.nx - 1) * sbytes)));
+        }
+    });
+
+    double sm[7] = {0, 0, 0, 0, 0, 0, 0};
+    int iters = 0;
+    bool bad = false, newton_fail = false;
+    for (int k = 0; k < nseg; ++k) {
+        asm volatile("" : "+s"(hbits));
+        const unsigned off = (unsigned)((k * 64 + lane) * V) * sbytes;
+        const bool more = (k + 1 < nseg);
+        // a1/a2: gather with wall reflections
+        u32x2 w[kQ];
+        E ahead[kNX] = {};
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            w[a] = Ln::template load<true>(at(src_of(A), off));
+            if constexpr (kEx[a] == -1) {  // the next segment's first element (every lane loads it alike)
+                if (more && shifted_in(A))
+                    ahead[xslot(a)] = Ed::load_at(at(src_of(A), (unsigned)((k + 1) * 64 * V) * sbytes));
+            }
+        });
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (kEx[a] != 0) {
+                if (shifted_in(A)) {
+                    constexpr int j = xslot(a);
+                    if constexpr (kEx[a] == 1) {      // needs the element at x0 - 1
+                        const E mine = Ed::last(w[a]);
+                        E nb = Ed::up(mine);
+                        if (lane == 0) nb = gcar[j];
+                        gcar[j] = Ed::lane_value(mine, 63);
+                        w[a] = Ed::join_left(w[a], nb);
+                    } else {                          // needs the element at x0 + V
+                        const E mine = Ed::first(w[a]);
+                        if (k == 0) gwrap[j] = Ed::lane_value(mine, 0);
+                        E nb = Ed::down(mine);
+                        if (lane == 63) nb = more ? Ed::uniform(ahead[j]) : gwrap[j];
+                        w[a] = Ed::join_right(w[a], nb);
+                    }
+                }
+            }
+        });
+        // a3-a6
+        collide_group<S, V, MAYBE_WFB, STATS>(w, p, wfb && (bot || top), top, sm, iters, bad, newton_fail);
+        // a7: store with wall reflections
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            char* dst = dst_of(A);
+            if constexpr (kEx[a] == 0) {
+                Ln::template store<true>(at(dst, off), w[a]);
+            } else {
+                if (!shifted_out(A)) {
+                    Ln::template store<true>(at(dst, off), w[a]);
+                } else {
+                    constexpr int j = xslot(a);
+                    if constexpr (kEx[a] == 1) {      // the group at x0 starts with x0 - 1's value
+                        const E mine = Ed::last(w[a]);
+                        E pv = Ed::up(mine);
+                        if (lane == 0) pv = scar[j];
+                        if (k == 0 && lane == 0) dfr[wave][0][j] = w[a];
+                        scar[j] = Ed::lane_value(mine, 63);
+                        if (k > 0 || lane != 0) Ln::template store<true>(at(dst, off), Ed::join_left(w[a], pv));
+                    } else {                          // the group at x0 ends with x0 + V's value
+                        const E mine = Ed::first(w[a]);
+                        const E pv = Ed::down(mine);
+                        const E first0 = Ed::lane_value(mine, 0);
+                        if (k == 0) swrap[j] = first0;
+                        else if (lane == 0)           // the previous segment's last group, now complete
+                            Ln::template store<true>(at(dst, off - 64u * V * sbytes + (unsigned)(63 * V) * sbytes),
+                                                     Ed::join_right(dfr[wave][1][j], first0));
+                        if (lane == 63) dfr[wave][1][j] = w[a];
+                        if (lane != 63) Ln::template store<true>(at(dst, off), Ed::join_right(w[a], pv));
+                    }
+                }
+            }
+        });
+    }
+    // the groups that waited for the other end of the periodic row
+    if (lane == 0) {
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (kEx[a] != 0) {
+                if (shifted_out(A)) {
+                    constexpr int j = xslot(a);
+                    char* dst = dst_of(A);
+                    if constexpr (kEx[a] == 1)
+                        Ln::template store<true>(at(dst, 0u), Ed::join_left(dfr[wave][0][j], scar[j]));
+                    else
+                        Ln::template store<true>(at(dst, (unsigned)(p.nx - V) * sbytes),
+                                                 Ed::join_right(dfr[wave][1][j], swrap[j]));
+                }
+            }
+        });
+    }
+    if (bad || newton_fail) {
+        atomicOr(&p.flags->status, (bad ? 1 : 0) | (newton_fail ? 2 : 0));
+        atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[1]);
+    }
+    if constexpr (MAYBE_WFB) {
+        const int mx = wave_max(iters);
+        if (lane == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
+    }
+    // a8: plane statistics: the row's sums (fixed-order wave reduction)
+    if constexpr (STATS) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const double v = wave_sum(sm[q]);
+            if (lane == 0) p.partials[((long long)y + (long long)p.ny * z) * 7 + q] = v;
+        }
+    }
+}
+
+template <typename S, int V>
+static hipError_t launch_odd_rows(int bc, const StepArgs& a, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
+#define LBM_ROWS(BCT)                                                                                          \
+    do {                                                                                                       \
+        if (a.partials)                                                                                        \
+            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, true>), grid, block, 0, s, a, nullptr, nullptr, 0);      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, false>), grid, block, 0, s, a, nullptr, nullptr, 0);     \
+    } while (0)
+    if (bc == kBB) LBM_ROWS(kBB);
+    else if (bc == kWFB) LBM_ROWS(kWFB);
+    else LBM_ROWS(kFreeSlip);
+#undef LBM_ROWS
+    return hipGetLastError();
+}
+
 template <typename S, int V, bool ODD>
 static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
+    if constexpr (ODD)
+        if (a.nseg > 0) return launch_odd_rows<S, V>(bc, a, s);
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
-    const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
+    const size_t lds = ODD ? (size_t)kNX * (a.tile_x + 1) * sizeof(u32x2) : 0;
 #define LBM_STEP(BCT)                                                                                        \
     do {                                                                                                     \
         if (a.partials)                                                                                      \
@@ -399,8 +753,10 @@ static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* t
                                  hipStream_t s)
 {
     const dim3 grid((unsigned)ntiles), block((unsigned)a0.tile_x);
-    const size_t lds = odd ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
-    if (odd)
+    const size_t lds = odd ? (size_t)kNX * (a0.tile_x + 1) * sizeof(u32x2) : 0;
+    if (odd && a0.nseg > 0)
+        hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false>), grid, block, 0, s, a0, table, tile_inst, ntiles);
+    else if (odd)
         hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);
     else
         hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);

@@ -178,3 +178,73 @@ def test_layout_rejects_incompatible_blocks(P, orc):
     ch.set_param(5, 128)          # row segments are fine
     ch.step(2)
     assert ch.sync()[0] == 0
+
+
+ROWS_CASES = [  # grid, store, tiles (odd, even, cells per thread), boundary, rows per brick
+    ((256, 7, 5), "f16", (128, 128, 4), "wfb", 0),      # one 64-lane segment per row
+    ((512, 6, 4), "bf16", (64, 128, 4), "wfb", 3),      # two segments, bricks of 3 rows
+    ((512, 9, 3), "f32", (128, 256, 2), "freeslip", 0),  # four segments
+    ((192, 5, 4), "f64", (256, 64, 1), "bb", 2),        # three segments, blocks of 4 rows
+    ((128, 6, 7), "f16", (64, 64, 2), "wfb", 128),      # plain layout
+]
+
+
+@pytest.mark.parametrize("grid,store,tiles,bc,brick", ROWS_CASES)
+def test_odd_step_by_rows_equals_blocks(P, orc, grid, store, tiles, bc, brick):
+    """The odd step walking rows (one wavefront per row, edge elements carried
+    across segments and around the periodic row) gives bit for bit the state,
+    moments and wall records of the block kernel with its LDS exchange;
+    statistics agree up to their summation order."""
+    h0 = _state(orc, grid, store, 21)
+    out = []
+    for mode in (0, 2):
+        ch = P.Channel(*grid, 0.51, cs=0.1, fx=2e-6, store=store, bc=bc, tiles=tiles, brick=brick,
+                       stats_every=1, graph_steps=0)
+        ch.set_param(15, mode)
+        ch.set_state(h0)
+        ch.step(7)
+        assert ch.sync()[0] == 0
+        out.append((ch.get_state(), ch.moments(), ch.wall_shear(), ch.stats_sums()[0]))
+        ch.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, b in zip(out[0][1], out[1][1]):
+        assert np.array_equal(a, b)
+    for a, b in zip(out[0][2], out[1][2]):
+        assert np.array_equal(a, b)
+    np.testing.assert_allclose(out[1][3], out[0][3], rtol=1e-12, atol=1e-14)
+
+
+def test_odd_step_by_rows_matches_oracle(P, orc):
+    """Two FP64 steps walking rows of three segments against the oracle."""
+    from gpu_common import one_step_tol, oracle_for
+    w = weights(orc)
+    grid = (192, 6, 3)
+    h0 = _state(orc, grid, "f64", 22)
+    ch = P.Channel(*grid, 0.52, cs=0.1, fx=1e-6, store="f64", bc="wfb", tiles=(128, 128, 1))
+    ch.set_param(15, 2)
+    ch.set_state(h0)
+    ch.step(2)
+    o = oracle_for(orc, grid, 0.52, 0.1, 1e-6, "wfb")
+    o.set_state(h0 + w)
+    assert o.step(2) == 0
+    want = o.state() - w
+    assert np.all(np.abs(ch.get_state() - want) <= 4 * one_step_tol("f64", want, w))
+
+
+def test_batch_odd_step_by_rows(P):
+    """A batch whose rows all qualify walks rows in its odd step and still
+    equals each channel stepped alone."""
+    specs = [dict(nx=128, ny=6, nz=3, tau=0.51, cs=0.1, fx=1e-6, bc="wfb"),
+             dict(nx=256, ny=5, nz=4, tau=0.52, cs=0.1, fx=2e-6, bc="bb")]
+    b = P.Batch(specs, store="f32", tiles=(64, 128, 2), graph_steps=0)
+    b._set(15, 2)
+    b.init_spalding([1e-2, 2e-2], 0.05, seeds=[3, 4])
+    b.step(5)
+    assert b.sync()[0] == 0
+    for i, s in enumerate(specs):
+        ch = P.Channel(s["nx"], s["ny"], s["nz"], s["tau"], cs=s["cs"], fx=s["fx"], store="f32", bc=s["bc"],
+                       tiles=(64, 128, 2), graph_steps=0)
+        ch.set_param(15, 0)
+        ch.init_spalding([1e-2, 2e-2][i], 0.05, 3 + i)
+        ch.step(5)
+        assert np.array_equal(b.instance(i).get_state(), ch.get_state()), i

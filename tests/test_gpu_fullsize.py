@@ -1,5 +1,6 @@
-"""Parity at the benchmark's full size (512 x 128 x 256 channel, 16.8M cells)
-in the launch configuration the benchmark times: sampled cells after one step
+"""Parity at the benchmark's full sizes (512 x 128 x 256 channel, 16.8M cells;
+2048 x 512 x 1024 channel, 1.07G cells) in the launch configuration the
+benchmark times: sampled cells after one step
 against the oracle evaluated cell by cell from the analytic initial state, and
 conservation properties that hold at any size."""
 import numpy as np
@@ -19,22 +20,36 @@ def P():
     return P
 
 
-def _channel(P, store, named=False):
+def _channel(P, store, named=False, workload="c3"):
     from paper_2009_04352_amd import workloads as W
-    p = W.params("c3", named_tau=named)
+    p = W.params(workload, named_tau=named)
     ch = P.Channel(*p["grid"], p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
-                   tiles=W.LAUNCH_TILES[store])
+                   tiles=W.launch_tiles(workload, store))
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     return ch, p
 
 
-@pytest.mark.parametrize("store", ("f64", "f32", "f16", "bf16"))
-def test_c3_one_step_sampled(P, orc, store):
+def _release(ch):
+    import torch
+    ch.close()
+    del ch
+    torch.cuda.empty_cache()
+
+
+# the benchmark's workloads and stores: the 512 x 128 x 256 channel in all four
+# formats, the 2048 x 512 x 1024 channel (1.07 G cells) in FP16 and FP32 and
+# its FP64 reference
+FULL = [("c3", "f64"), ("c3", "f32"), ("c3", "f16"), ("c3", "bf16"), ("c5", "f16"), ("c5", "f32"), ("c5", "f64")]
+
+
+@pytest.mark.parametrize("workload,store", FULL)
+def test_one_step_sampled(P, orc, workload, store):
     """Tolerance: the initial rounding to the store (half an ulp of each input
     population, carried through one collision with relaxation factor below 2
     into at most 19 terms) plus one ulp of the output and the arithmetic bound."""
     from paper_2009_04352_amd import workloads as W
-    ch, p = _channel(P, store)
+    print("full-size sampled step: %s %s" % (workload, store), flush=True)
+    ch, p = _channel(P, store, workload=workload)
     cells = W.sample_cells(p["grid"], 3000, seed=1)
     nx, ny, nz = p["grid"]
     op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB)
@@ -51,6 +66,7 @@ def test_c3_one_step_sampled(P, orc, store):
     tol = ulp(store, want) + 4.0 * ulp(store, hmax) + MATH_EPS[store] + 8.0 * np.spacing(1.0 / 3.0)
     assert np.all(np.abs(got - want) <= tol), np.abs(got - want).max()
     assert ch.sync()[0] == 0
+    _release(ch)
 
 
 def test_c3_fp64_conservation(P):
@@ -75,3 +91,4 @@ def test_c3_fp64_conservation(P):
     m1, _ = totals()
     assert abs(m1 - m0) <= 1e-12 * m0
     assert ch.sync()[0] == 0
+    _release(ch)
