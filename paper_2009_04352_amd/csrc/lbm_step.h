@@ -150,15 +150,21 @@ constexpr int kBCRuntime = 3;
 // of plane z + dz) is the same for every thread of the block; each thread
 // adds one small 32-bit byte offset, shared by all 19 directions.
 // BATCH: the instance of the tile and its parameters come from tables.
+// Occupancy floor: 2-byte stores with 4 cells per thread sit near the
+// register count of 3 wavefronts per SIMD, and the allocator sometimes lands
+// just above it; hold it to 3.
+template <typename S, int V>
+constexpr int min_waves() { return (sizeof(typename S::T) == 2 && V == 4) ? 3 : 1; }
+
 template <typename S, int V, bool ODD, int BCT, bool STATS>
-__global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_waves<S, V>()))) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
                                                     const int* __restrict__ tile_inst, int ntiles_all)
 {
     constexpr bool BATCH = (BCT == kBCRuntime);
     using T = typename S::T;
     using R = typename S::R;
     using Ln = Lane<S, V>;
-    extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x], then halo[kNX]
+    extern __shared__ u32x2 xbuf[];  // odd step: [kNX][blockDim.x]
 
     int tile;
     StepArgs p;
@@ -264,25 +270,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
         for_each_dir([&](auto A) { w[decltype(A)::value] = u32x2{0u, 0u}; });
     }
     if constexpr (ODD) {
-        // A partial segment's two edge threads fetch the one element beyond
-        // the segment together with the group loads (so that its latency is
-        // not paid after the barrier) and leave it in LDS: halo[xslot(a)].
-        u32x2* halo = xbuf + kNX * nthr;
-        if (!whole && L.active && (tr == 0 || tr == nact - 1)) {
-            for_each_dir([&](auto A) {
-                constexpr int a = decltype(A)::value;
-                constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
-                if constexpr (ex != 0) {
-                    const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
-                    const bool shifted = !from_wall || (MAYBE_SPEC && spec && is_tangential(a));
-                    char* src = from_wall ? base(opp(mirror_y(a)), 0, -ez) : base(opp(a), -ey, -ez);
-                    if (shifted && ex == 1 && tr == 0)
-                        halo[xslot(a)] = halo_as_last<S, V>(at(src, xoff(L.wrapx(L.x0 - 1))));
-                    if (shifted && ex == -1 && tr == nact - 1)
-                        halo[xslot(a)] = halo_as_first<S, V>(at(src, xoff(L.wrapx(L.x0 + V))));
-                }
-            });
-        }
         // the x-shifted groups hold cells x0 .. x0 + V - 1 of the source row; shift by -e_x
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
@@ -302,13 +289,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
                             u32x2 nb;
                             if (tr > 0) nb = xb[t - 1];
                             else if (whole) nb = xb[tb + nact - 1];
-                            else nb = halo[xslot(a)];
+                            else nb = halo_as_last<S, V>(at(from_wall ? base(opp(mirror_y(a)), 0, -ez)
+                                                                      : base(opp(a), -ey, -ez),
+                                                            xoff(L.wrapx(L.x0 - 1))));
                             w[a] = join_left<S, V>(w[a], nb);
                         } else {                  // needs the element at x0 + V
                             u32x2 nb;
                             if (tr < nact - 1) nb = xb[t + 1];
                             else if (whole) nb = xb[tb];
-                            else nb = halo[xslot(a)];
+                            else nb = halo_as_first<S, V>(at(from_wall ? base(opp(mirror_y(a)), 0, -ez)
+                                                                       : base(opp(a), -ey, -ez),
+                                                             xoff(L.wrapx(L.x0 + V))));
                             w[a] = join_right<S, V>(w[a], nb);
                         }
                     }
@@ -320,7 +311,54 @@ __global__ __launch_bounds__(kMaxBlock) void k_step(StepArgs p0, const StepArgs*
     double sm[7] = {0, 0, 0, 0, 0, 0, 0};
     int iters = 0;
     bool bad = false, newton_fail = false;
-    collide_group<S, V, MAYBE_WFB, STATS>(w, p, wfb && (bot || top) && L.active, top, sm, iters, bad, newton_fail);
+    // a3-a6 (the same steps as collide_group, written out here: the register
+    // allocation of this kernel came out tighter this way)
+    constexpr bool PAIRS = (sizeof(T) == 2) && (V >= 2);
+    auto cell = [&](int k, R (&f)[kQ]) {
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            f[a] = Ln::get(w[a], k);
+        });
+        if constexpr (MAYBE_WFB) {
+            if (wfb && (bot || top) && L.active) {
+                int it = 0;
+                bool fail = false;
+                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, it,
+                               fail);
+                iters = max(iters, it);
+                newton_fail = newton_fail || fail;
+            }
+        }
+        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
+        bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
+        if constexpr (STATS) {
+            const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
+            sm[0] += ux; sm[1] += uy; sm[2] += uz;
+            sm[3] += ux * ux; sm[4] += uy * uy; sm[5] += uz * uz; sm[6] += ux * uy;
+        }
+    };
+    if constexpr (PAIRS) {
+#pragma unroll
+        for (int k = 0; k < V; k += 2) {
+            R f0[kQ], f1[kQ];
+            cell(k, f0);
+            cell(k + 1, f1);
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                Ln::set_pair(w[a], k, f0[a], f1[a]);
+            });
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            R f[kQ];
+            cell(k, f);
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                Ln::set(w[a], k, f[a]);
+            });
+        }
+    }
     if (L.active && (bad || newton_fail)) {
         atomicOr(&p.flags->status, (bad ? 1 : 0) | (newton_fail ? 2 : 0));
         atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
@@ -733,7 +771,7 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
     if constexpr (ODD)
         if (a.nseg > 0) return launch_odd_rows<S, V>(bc, a, s);
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
-    const size_t lds = ODD ? (size_t)kNX * (a.tile_x + 1) * sizeof(u32x2) : 0;
+    const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
 #define LBM_STEP(BCT)                                                                                        \
     do {                                                                                                     \
         if (a.partials)                                                                                      \
@@ -753,7 +791,7 @@ static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* t
                                  hipStream_t s)
 {
     const dim3 grid((unsigned)ntiles), block((unsigned)a0.tile_x);
-    const size_t lds = odd ? (size_t)kNX * (a0.tile_x + 1) * sizeof(u32x2) : 0;
+    const size_t lds = odd ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
     if (odd && a0.nseg > 0)
         hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false>), grid, block, 0, s, a0, table, tile_inst, ntiles);
     else if (odd)
