@@ -83,6 +83,12 @@ extern "C" {
                                * stores whose rows are longer than an odd-step block; 2 = walk rows whenever nx is a
                                * multiple of 64 cells
                                * per thread.  Results do not depend on it (statistics sums up to summation order). */
+#define LBM_P_SPREAD 16       /* launch order: c in [5, 16] = chunks of 2^c tiles cycle through the bricks of the
+                               * layout, so the wall rows (first and last brick; their Newton solves cost more)
+                               * are spread over the whole launch; 0 = tiles in memory order; -1 (default) = 7
+                               * for 2-byte stores, 0 otherwise.  Applies when every brick is whole and holds a
+                               * whole number of chunks; reads back the value in use.  Results do not depend
+                               * on it. */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -225,7 +231,7 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const 
 void lbm_batch_destroy(lbm_batch* batch);
 /* Keys LBM_P_STORE (before binding), LBM_P_TILE_ODD, LBM_P_TILE_EVEN,
  * LBM_P_VECTOR (0 = the widest group every instance allows), LBM_P_XCD_REMAP,
- * LBM_P_GRAPH_STEPS, LBM_P_ODD_ROWS (walks rows only if every instance's rows
+ * LBM_P_GRAPH_STEPS, LBM_P_SPREAD, LBM_P_ODD_ROWS (walks rows only if every instance's rows
  * qualify), and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT /
  * LBM_P_BRICK (before initialisation) applied to every instance.  Block
  * sizes and cells per thread that an initialised instance's layout cannot

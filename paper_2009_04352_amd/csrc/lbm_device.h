@@ -47,6 +47,24 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap)
     return ((((j >> c) << 3) + k) << c) + (j & ((1 << c) - 1));
 }
 
+// Tile at launch position u when the bricks are spread over the launch (see
+// set_spread on the host): position u is tile i of chunk G = u >> spread;
+// round q = G / nbricks of chunks takes chunk q of brick (G + q) mod nbricks
+// (rotated) or G mod nbricks.  A bijection on the tiles; identity when
+// spread < 0.
+__device__ __forceinline__ int spread_tile(int u, const StepArgs& p)
+{
+    if (p.spread < 0) return u;
+    const int G = u >> p.spread, i = u & ((1 << p.spread) - 1);
+    const int q = fdiv(G, p.fd_nbricks);
+    int g = G - q * p.nbricks;
+    if (p.spread_rot) {
+        g += q - fdiv(q, p.fd_nbricks) * p.nbricks;   // (G + q) mod nbricks
+        if (g >= p.nbricks) g -= p.nbricks;
+    }
+    return g * p.tiles_per_brick + (q << p.spread) + i;
+}
+
 // splitmix64 (Steele, Lea & Flood 2014): output k of the generator seeded
 // with `seed`.
 __device__ __forceinline__ unsigned long long splitmix64_at(unsigned long long seed, unsigned long long k)
@@ -64,77 +82,123 @@ __device__ __forceinline__ double uniform01(unsigned long long seed, unsigned lo
 
 // ------------------------------------------------------ wall function (FP64)
 
-// Start value for the wall-function Newton solve, in FP32: the log law
+// Friction velocities from Spalding's law (Eq. 16-17) for NC wall cells at
+// once.  In p = u+ = U / u_tau with R = y1 U / nu the law reads
+// H(p) = p Sp(p) - R = 0.  H is increasing and convex for p > 0, so Newton's
+// method converges from any positive start (after at most one step it is
+// right of the root and then decreases monotonically); it stops when
+// |p_{k+1} - p_k| <= tol p_{k+1}.
+//
+// The FP64 iteration starts from an FP32 estimate: the log law
 // u+ = ln(y+) / kappa + B with y+ = R / p, iterated as a fixed point (it
 // contracts for p > 1 / kappa), taken when it is below the viscous guess
-// sqrt(R); then a few FP32 Newton steps on H below.  Only the start of the
-// FP64 iteration depends on it.
-__device__ __forceinline__ double wall_newton_start(double R, double kappa, double bconst, double ekb)
+// sqrt(R); then FP32 Newton steps on H until the change is below 1e-6.  Only
+// the start of the FP64 iteration depends on it.
+//
+// The NC solves run side by side (independent dependency chains for the
+// scheduler); each cell keeps its own stopping step, so every cell gets the
+// value a solve of its own would give.  Cells with U = 0 get u_tau = 0.
+// `iters` is the largest FP64 step count of the live cells, `fail` is set if
+// any live cell reached maxit without meeting the stop.
+template <int NC>
+__device__ __forceinline__ void wall_utau_n(const double (&U)[NC], double y1, double nu, double kappa, double bconst,
+                                            double ekb, double tol, int maxit, double (&ut)[NC], int& iters,
+                                            bool& fail)
 {
-    const float Rf = (float)R, kf = (float)kappa, ekf = (float)ekb;
-    float p = sqrtf(Rf);
-    float pl = p;
+    double R[NC], p[NC];
+    bool live[NC], run[NC];
+    int cnt[NC];
+    const float kf = (float)kappa, ekf = (float)ekb;
+    float pf[NC], Rf[NC];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) pl = __logf(Rf / pl) / kf + (float)bconst;
-    if (pl > 1.0f && pl < p) p = pl;
-    for (int i = 0; i < 6; ++i) {
-        const float k = kf * p, ek = __expf(k), k2 = 0.5f * k * k;
-        const float br = ek - 1.0f - k - k2;
-        const float sp = p + ekf * (br - k2 * k * (1.0f / 3.0f));
-        const float dsp = 1.0f + kf * ekf * br;
-        const float pn = p - (p * sp - Rf) / (sp + p * dsp);
-        if (!(pn > 0.0f) || !(pn < INFINITY)) break;
-        const bool done = fabsf(pn - p) <= 1e-6f * pn;
-        p = pn;
-        if (done) break;
+    for (int c = 0; c < NC; ++c) {
+        live[c] = U[c] > 0.0;
+        R[c] = live[c] ? y1 * U[c] / nu : 1.0;
+        Rf[c] = (float)R[c];
+        pf[c] = sqrtf(Rf[c]);
+        float pl = pf[c];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) pl = __logf(Rf[c] / pl) / kf + (float)bconst;
+        if (pl > 1.0f && pl < pf[c]) pf[c] = pl;
+        run[c] = true;
     }
-    return (p > 0.0f && p < INFINITY) ? (double)p : sqrt(R);
+    for (int i = 0; i < 6; ++i) {
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const float q = pf[c];
+            const float k = kf * q, ek = __expf(k), k2 = 0.5f * k * k;
+            const float br = ek - 1.0f - k - k2;
+            const float sp = q + ekf * (br - k2 * k * (1.0f / 3.0f));
+            const float dsp = 1.0f + kf * ekf * br;
+            const float pn = q - (q * sp - Rf[c]) / (sp + q * dsp);
+            if (run[c]) {
+                if (!(pn > 0.0f) || !(pn < INFINITY)) {
+                    run[c] = false;
+                } else {
+                    run[c] = !(fabsf(pn - q) <= 1e-6f * pn);
+                    pf[c] = pn;
+                }
+            }
+            any = any || run[c];
+        }
+        if (!any) break;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        p[c] = (pf[c] > 0.0f && pf[c] < INFINITY) ? (double)pf[c] : sqrt(R[c]);
+        run[c] = live[c];
+        cnt[c] = 0;
+    }
+    for (int it = 1; it <= maxit; ++it) {
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double q = p[c];
+            const double k = kappa * q;
+            const double ek = exp(k);
+            const double k2 = 0.5 * k * k;
+            const double br = ek - 1.0 - k - k2;              // e^k - 1 - k - k^2/2
+            const double sp = q + ekb * (br - k2 * k * (1.0 / 3.0));
+            const double dsp = 1.0 + kappa * ekb * br;
+            const double pn = q - (q * sp - R[c]) / (sp + q * dsp);
+            if (run[c]) {
+                cnt[c] = it;
+                run[c] = !(fabs(pn - q) <= tol * pn);
+                p[c] = pn;
+            }
+            any = any || run[c];
+        }
+        if (!any) break;
+    }
+    iters = 0;
+    fail = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        iters = max(iters, cnt[c]);
+        fail = fail || run[c];
+        ut[c] = live[c] ? U[c] / p[c] : 0.0;
+    }
 }
 
-// Friction velocity from Spalding's law (Eq. 16-17).  In p = u+ = U / u_tau
-// with R = y1 U / nu the law reads H(p) = p Sp(p) - R = 0.  H is increasing
-// and convex for p > 0, so Newton's method converges from any positive start
-// (after at most one step it is right of the root and then decreases
-// monotonically); it stops when |p_{k+1} - p_k| <= tol p_{k+1}.  The FP64
-// iteration starts from wall_newton_start; `iters` counts FP64 steps.
+// One cell (U > 0) of the above: the device Newton probe uses it.
 __device__ __forceinline__ double wall_utau(double U, double y1, double nu, double kappa, double bconst, double ekb,
                                             double tol, int maxit, int& iters, bool& fail)
 {
-    const double R = y1 * U / nu;
-    double p = wall_newton_start(R, kappa, bconst, ekb);
-    iters = 0;
-    fail = true;
-    for (int it = 1; it <= maxit; ++it) {
-        const double k = kappa * p;
-        const double ek = exp(k);
-        const double k2 = 0.5 * k * k;
-        const double br = ek - 1.0 - k - k2;              // e^k - 1 - k - k^2/2
-        const double sp = p + ekb * (br - k2 * k * (1.0 / 3.0));
-        const double dsp = 1.0 + kappa * ekb * br;
-        const double pn = p - (p * sp - R) / (sp + p * dsp);
-        iters = it;
-        if (fabs(pn - p) <= tol * pn) {
-            p = pn;
-            fail = false;
-            break;
-        }
-        p = pn;
-    }
-    return U / p;
+    const double u[1] = {U};
+    double ut[1];
+    wall_utau_n<1>(u, y1, nu, kappa, bconst, ekb, tol, maxit, ut, iters, fail);
+    return ut[0];
 }
 
 struct WallRecord {
     double taux, tauz, utau, U;
 };
 
-// WFB correction of the gathered (free-slip) populations of one wall cell:
-// tau_w from the wall function, split along the wall-parallel velocity
-// (Eq. 15) and added as +-tau/2 to the four reflected diagonal populations
-// (Eq. 13-14 with dt = dy = 1).  Top wall: the bottom rule mirrored in y.
+// Density and wall-parallel velocity of the gathered (free-slip) populations
+// of a wall cell, with the half-force shift; returns |v_par| in FP64.
 template <typename R>
-__device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double fx, double y1, double nu0,
-                                                  double kappa, double bconst, double ekb, double tol, int maxit,
-                                                  int& iters, bool& fail)
+__device__ __forceinline__ double wall_velocity(const R (&f)[kQ], R fx, R& rho, R& vx, R& vz)
 {
     R drho = R(0), jx = R(0), jz = R(0);
     for_each_dir([&](auto A) {
@@ -145,21 +209,33 @@ __device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double f
         if constexpr (kEz[a] == 1) jz += f[a];
         if constexpr (kEz[a] == -1) jz -= f[a];
     });
-    const R rho = R(1) + drho;
-    const double vx = (double)((jx + R(0.5) * (R)fx) / rho);
-    const double vz = (double)(jz / rho);
-    const double U = sqrt(vx * vx + vz * vz);
+    rho = R(1) + drho;
+    vx = (jx + R(0.5) * fx) / rho;
+    vz = jz / rho;
+    const double dx = (double)vx, dz = (double)vz;
+    return sqrt(dx * dx + dz * dz);
+}
+
+// Wall stress from the friction velocity: tau_w = rho u_tau^2 split against
+// the wall-parallel velocity (Eq. 15, 17); zero when U = 0.
+__device__ __forceinline__ WallRecord wall_record(double rho, double vx, double vz, double U, double ut)
+{
     WallRecord rec{0.0, 0.0, 0.0, U};
-    iters = 0;
-    fail = false;
     if (U > 0.0) {
-        const double ut = wall_utau(U, y1, nu0, kappa, bconst, ekb, tol, maxit, iters, fail);
-        const double tauw = (double)rho * ut * ut;
+        const double tauw = rho * ut * ut;
         rec.taux = -(vx / U) * tauw;
         rec.tauz = -(vz / U) * tauw;
         rec.utau = ut;
     }
-    const R hx = (R)(0.5 * rec.taux), hz = (R)(0.5 * rec.tauz);
+    return rec;
+}
+
+// The bounce correction: +-tau/2 on the four reflected diagonal populations
+// (Eq. 13-14 with dt = dy = 1), hx = tau_x / 2 and hz = tau_z / 2.  Top wall:
+// the bottom rule mirrored in y.
+template <typename R>
+__device__ __forceinline__ void wfb_apply(R (&f)[kQ], bool top, R hx, R hz)
+{
     if (!top) {
         f[7] += hx;
         f[14] -= hx;
@@ -171,6 +247,22 @@ __device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double f
         f[mirror_y(11)] += hz;
         f[mirror_y(17)] -= hz;
     }
+}
+
+// WFB correction of the gathered (free-slip) populations of one wall cell:
+// tau_w from the wall function, split along the wall-parallel velocity and
+// applied as the bounce correction.
+template <typename R>
+__device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double fx, double y1, double nu0,
+                                                  double kappa, double bconst, double ekb, double tol, int maxit,
+                                                  int& iters, bool& fail)
+{
+    R rho, vx, vz;
+    const double U[1] = {wall_velocity<R>(f, (R)fx, rho, vx, vz)};
+    double ut[1];
+    wall_utau_n<1>(U, y1, nu0, kappa, bconst, ekb, tol, maxit, ut, iters, fail);
+    const WallRecord rec = wall_record((double)rho, (double)vx, (double)vz, U[0], ut[0]);
+    wfb_apply<R>(f, top, (R)(0.5 * rec.taux), (R)(0.5 * rec.tauz));
     return rec;
 }
 

@@ -59,6 +59,10 @@ __host__ __device__ inline int fdiv(int n, FastDiv f) { return (int)(((unsigned 
 // launch).  A block processes one tile: rpb whole x-rows of one z-plane, or
 // one segment of tile_x * vw cells of a single x-row.  Tiles are numbered in
 // memory order: x segment, row group within a brick, z, brick.
+// Blocks go round-robin to the 8 XCDs; with the XCD remap each XCD takes
+// chunks of 2^kXcdChunkLog2 consecutive tiles in turn.
+constexpr int kXcdChunkLog2 = 5;
+
 struct StepArgs {
     void* h;              // populations h_a = f_a - w_a, bricked layout (row_index)
     long long n;          // cells
@@ -68,6 +72,10 @@ struct StepArgs {
     int nbricks;          // bricks (the last one may hold fewer groups)
     int bg_last;          // row groups of the last brick
     FastDiv fd_ntx, fd_brick_tiles, fd_bgroups, fd_bg_last, fd_tpr;  // tile and thread decomposition
+    int spread;           // launch order: log2 of the tile chunks that cycle over the bricks (-1: memory order)
+    int spread_rot;       // rotate the brick of each round of chunks by the round (brick count shares a factor with 8)
+    int tiles_per_brick;  // tiles of one brick (every brick whole when spread >= 0)
+    FastDiv fd_nbricks;
     int nseg;             // odd step by rows: each wavefront walks one row in nseg segments of 64 vw
                           // cells (tile_x / 64 rows per block); 0: the tile kernel
     int tile_x;           // threads per block
@@ -115,6 +123,7 @@ int step_vector_width(int store, int nx);
 void step_geometry(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a);
 bool rows_ok(int nx, int vw);
 void step_geometry_rows(int nx, int ny, int nz, int tile_x, int vw, int brick, StepArgs& a);
+void set_spread(StepArgs& a, int log2);
 bool brick_ok(int ny, int brick, int rpb);
 hipError_t launch_batch_step(int store, bool odd, const StepArgs* host_table, int n, const StepArgs* dev_table,
                              const int* dev_tile_inst, int ntiles, int xcd_remap, hipStream_t s);

@@ -54,6 +54,7 @@ void step_geometry(int nx, int ny, int nz, int tile_x, int vw, int brick, StepAr
     a.fd_bg_last = make_fastdiv(a.bg_last);
     a.fd_tpr = make_fastdiv(a.ntx == 1 ? tpr_full : tile_x);
     a.nseg = 0;
+    set_spread(a, 0);
 }
 
 // The odd step by rows needs rows of whole 64-lane segments.
@@ -79,6 +80,29 @@ void step_geometry_rows(int nx, int ny, int nz, int tile_x, int vw, int brick, S
     const int waves = tile_x / 64;
     a.ntiles = (int)(((long long)ny * nz + waves - 1) / waves);
     a.nseg = nx / (64 * vw);
+    set_spread(a, 0);
+}
+
+// Launch order that spreads the bricks over time: chunks of 2^log2 tiles
+// cycle through the bricks (round q of chunks takes chunk q of every brick),
+// so the wall rows, which live in the first and last brick and cost more
+// than the others (the wall-function Newton solve), are mixed into the whole
+// launch instead of its first and last 1/nbricks.  log2 <= 0, a single
+// brick, a short last brick or bricks that are not a whole number of chunks
+// keep the memory order.  Chunks smaller than a round of XCD chunks (8 of
+// 2^kXcdChunkLog2 tiles, one per XCD) would give each XCD the same few
+// bricks when the brick count is even; rotating round q's bricks by q
+// avoids that.
+void set_spread(StepArgs& a, int log2)
+{
+    const long long brick_tiles = (a.nseg > 0) ? (long long)a.bgroups * a.nz : (long long)a.ntx * a.bgroups * a.nz;
+    const int waves = (a.nseg > 0) ? a.tile_x / 64 : 1;   // rows per tile of the odd step by rows
+    a.tiles_per_brick = (int)(brick_tiles / waves);
+    a.fd_nbricks = make_fastdiv(a.nbricks);
+    const bool ok = log2 > 0 && log2 < 30 && a.nbricks > 1 && a.bg_last == a.bgroups && brick_tiles % waves == 0 &&
+                    a.tiles_per_brick % (1 << log2) == 0;
+    a.spread = ok ? log2 : -1;
+    a.spread_rot = (a.nbricks % 2 == 0 && log2 < kXcdChunkLog2 + 3) ? 1 : 0;
 }
 
 static bool step_args_ok(int store, const StepArgs& a)
@@ -96,13 +120,16 @@ static bool step_args_ok(int store, const StepArgs& a)
         step_geometry(a.nx, a.ny, a.nz, a.tile_x, a.vw, a.brick, g);
         if (!brick_ok(a.ny, a.brick, g.rpb)) return false;
     }
+    set_spread(g, a.spread);
     // the decomposition must be the one step_geometry derives (the batched
     // launch reads it from the device table)
     auto same = [](const FastDiv& x, const FastDiv& y) { return x.m == y.m && x.s == y.s; };
     return g.ntx == a.ntx && g.rpb == a.rpb && g.nyt == a.nyt && g.ntiles == a.ntiles && g.bgroups == a.bgroups &&
            g.nbricks == a.nbricks && g.bg_last == a.bg_last && same(g.fd_ntx, a.fd_ntx) &&
            same(g.fd_brick_tiles, a.fd_brick_tiles) && same(g.fd_bgroups, a.fd_bgroups) &&
-           same(g.fd_bg_last, a.fd_bg_last) && same(g.fd_tpr, a.fd_tpr);
+           same(g.fd_bg_last, a.fd_bg_last) && same(g.fd_tpr, a.fd_tpr) && g.spread == a.spread &&
+           (a.spread < 0 || (a.spread_rot == g.spread_rot && a.tiles_per_brick == g.tiles_per_brick &&
+                             same(g.fd_nbricks, a.fd_nbricks)));
 }
 
 hipError_t launch_step(int store, bool odd, int bc, const StepArgs& a, hipStream_t s)

@@ -72,6 +72,37 @@ __device__ __forceinline__ u32x2 halo_as_first(const typename S::T* p)
     else return Ln::as_first(Ln::load_elem(p));
 }
 
+// a3 for the V cells of a wall-row group: decode, the gathered wall-parallel
+// velocity of each cell, one joint Newton solve for the V friction
+// velocities, and the half stresses hx = tau_x / 2, hz = tau_z / 2 that the
+// bounce correction adds.  Wall rows are whole rows, so the branch that calls
+// this is uniform over the wavefront.
+template <typename S, int V>
+__device__ __forceinline__ void wall_group(const u32x2 (&w)[kQ], const StepArgs& p, typename S::R (&hx)[V],
+                                           typename S::R (&hz)[V], int& iters, bool& fail)
+{
+    using R = typename S::R;
+    using Ln = Lane<S, V>;
+    R rho[V], vx[V], vz[V];
+    double U[V], ut[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        R f[kQ];
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            f[a] = Ln::get(w[a], k);
+        });
+        U[k] = wall_velocity<R>(f, (R)p.fx, rho[k], vx[k], vz[k]);
+    }
+    wall_utau_n<V>(U, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, ut, iters, fail);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        const WallRecord rec = wall_record((double)rho[k], (double)vx[k], (double)vz[k], U[k], ut[k]);
+        hx[k] = (R)(0.5 * rec.taux);
+        hz[k] = (R)(0.5 * rec.tauz);
+    }
+}
+
 // a3-a6 for the V cells of a group in place: decode, wall-function bounce
 // (wall_wfb: the cells are wall-adjacent and the boundary is WFB), moments,
 // Smagorinsky, BGK with the body force, encode.  Accumulates the sampled
@@ -83,21 +114,24 @@ __device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p,
     using R = typename S::R;
     using Ln = Lane<S, V>;
     constexpr bool PAIRS = (sizeof(typename S::T) == 2) && (V >= 2);
+    // a3: wall-function bounce at wall-adjacent cells
+    R whx[V], whz[V];
+    if constexpr (MAYBE_WFB) {
+        if (wall_wfb) {
+            int it = 0;
+            bool fail = false;
+            wall_group<S, V>(w, p, whx, whz, it, fail);
+            iters = max(iters, it);
+            newton_fail = newton_fail || fail;
+        }
+    }
     auto cell = [&](int k, R (&f)[kQ]) {
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             f[a] = Ln::get(w[a], k);
         });
-        // a3: wall-function bounce at wall-adjacent cells
         if constexpr (MAYBE_WFB) {
-            if (wall_wfb) {
-                int it = 0;
-                bool fail = false;
-                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, it,
-                               fail);
-                iters = max(iters, it);
-                newton_fail = newton_fail || fail;
-            }
+            if (wall_wfb) wfb_apply<R>(f, top, whx[k], whz[k]);
         }
         // a4-a6: moments, Smagorinsky, BGK + body force
         const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
@@ -176,6 +210,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         p = p0;
         tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
     }
+    tile = spread_tile(tile, p);
     const bool spec = BATCH ? (p.bc != kBB) : (BCT != kBB);
     const bool wfb = BATCH ? (p.bc == kWFB) : (BCT == kWFB);
     constexpr bool MAYBE_WFB = BATCH || BCT == kWFB;
@@ -314,20 +349,18 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     // a3-a6 (the same steps as collide_group, written out here: the register
     // allocation of this kernel came out tighter this way)
     constexpr bool PAIRS = (sizeof(T) == 2) && (V >= 2);
+    const bool wall_wfb = MAYBE_WFB && wfb && (bot || top) && L.active;
+    R whx[V], whz[V];
+    if constexpr (MAYBE_WFB) {
+        if (wall_wfb) wall_group<S, V>(w, p, whx, whz, iters, newton_fail);
+    }
     auto cell = [&](int k, R (&f)[kQ]) {
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             f[a] = Ln::get(w[a], k);
         });
         if constexpr (MAYBE_WFB) {
-            if (wfb && (bot || top) && L.active) {
-                int it = 0;
-                bool fail = false;
-                wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, it,
-                               fail);
-                iters = max(iters, it);
-                newton_fail = newton_fail || fail;
-            }
+            if (wall_wfb) wfb_apply<R>(f, top, whx[k], whz[k]);
         }
         const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
         bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
@@ -545,6 +578,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
         p = p0;
         tile = tile_of_block(blockIdx.x, p.ntiles, p.xcd_remap);
     }
+    tile = spread_tile(tile, p);
     const bool spec = BATCH ? (p.bc != kBB) : (BCT != kBB);
     const bool wfb = BATCH ? (p.bc == kWFB) : (BCT == kWFB);
     if (tile == 0 && threadIdx.x == 0) p.flags->cnt[0] = p.flags->cnt[1] + 1;

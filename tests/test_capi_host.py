@@ -86,6 +86,28 @@ def test_brick_layout_parameter(L):
             lib.lbm_destroy(h)
 
 
+def test_spread_parameter(L):
+    """Brick spreading: chunks of 128 tiles for 2-byte stores and memory order
+    otherwise by default; 0 or a chunk log2 in [5, 16]; reads back."""
+    lib = L.lib()
+    v = C.c_double()
+    for store, want in ((L.LBM_STORE_F16, 7), (L.LBM_STORE_F64, 0)):
+        h = C.c_void_p()
+        assert lib.lbm_create(C.byref(L.Grid(512, 128, 8)), 0.6, 0.1, 0.41, 5.5, 0.0, C.byref(h)) == 0
+        try:
+            assert lib.lbm_set_param(h, L.LBM_P_STORE, store) == 0
+            assert lib.lbm_get_param(h, L.LBM_P_SPREAD, C.byref(v)) == 0 and v.value == want
+            for ok in (0, 5, 8, 16):
+                assert lib.lbm_set_param(h, L.LBM_P_SPREAD, ok) == 0
+                assert lib.lbm_get_param(h, L.LBM_P_SPREAD, C.byref(v)) == 0 and v.value == ok
+            for bad in (1, 4, 17, -2, 5.5):
+                assert lib.lbm_set_param(h, L.LBM_P_SPREAD, bad) == L.LBM_E_ARG
+            assert lib.lbm_set_param(h, L.LBM_P_SPREAD, -1) == 0
+            assert lib.lbm_get_param(h, L.LBM_P_SPREAD, C.byref(v)) == 0 and v.value == want
+        finally:
+            lib.lbm_destroy(h)
+
+
 def test_status_strings(L):
     lib = L.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):

@@ -180,6 +180,41 @@ def test_layout_rejects_incompatible_blocks(P, orc):
     assert ch.sync()[0] == 0
 
 
+SPREAD_CASES = [  # grid, store, tiles, odd step by rows, rows per brick: every brick whole, 32k tiles each
+    ((256, 24, 32), "f16", (64, 64, 4), 0, 8),      # 3 bricks (no rotation), one row per block
+    ((256, 32, 32), "bf16", (64, 64, 4), 2, 8),     # 4 bricks (rotated rounds), odd step by rows
+    ((512, 32, 16), "f64", (256, 256, 1), 0, 8),    # two segments per row
+    ((256, 48, 16), "f32", (128, 128, 2), 0, 4),    # 12 bricks of 4 rows
+]
+
+
+@pytest.mark.parametrize("grid,store,tiles,rows,brick", SPREAD_CASES)
+def test_brick_spread_launch_order(P, orc, grid, store, tiles, rows, brick):
+    """Spreading the bricks over the launch (chunks of 32, 128 or 256 tiles) only
+    reorders the blocks: states, moments, wall records and statistics agree
+    bit for bit with memory order."""
+    h0 = _state(orc, grid, store, 23)
+    out = []
+    for spread in (0, 5, 7, 8):
+        ch = P.Channel(*grid, 0.51, cs=0.1, fx=2e-6, store=store, bc="wfb", tiles=tiles, brick=brick,
+                       stats_every=1, graph_steps=0)
+        ch.set_param(15, rows)
+        ch.set_param(16, spread)
+        assert ch.get_param(16) == spread
+        ch.set_state(h0)
+        ch.step(7)
+        assert ch.sync()[0] == 0
+        out.append((ch.get_state(), ch.moments(), ch.wall_shear(), ch.stats_sums()[0]))
+        ch.close()
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0])
+        for a, b in zip(out[0][1], o[1]):
+            assert np.array_equal(a, b)
+        for a, b in zip(out[0][2], o[2]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(out[0][3], o[3])
+
+
 ROWS_CASES = [  # grid, store, tiles (odd, even, cells per thread), boundary, rows per brick
     ((256, 7, 5), "f16", (128, 128, 4), "wfb", 0),      # one 64-lane segment per row
     ((512, 6, 4), "bf16", (64, 128, 4), "wfb", 3),      # two segments, bricks of 3 rows
