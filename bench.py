@@ -91,7 +91,8 @@ def run_store(P, W, name, store, steps, warmup):
     total_ms, odd_ms, even_ms = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
     status, first_bad = ch.sync()
     out = dict(ms_per_step=total_ms / steps, mlups=n * steps / (total_ms * 1e-3) / 1e6,
-               odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status), first_bad_step=int(first_bad))
+               odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status), first_bad_step=int(first_bad),
+               odd_by_rows=int(ch.get_param(17)))
     acc = None
     if status == 0:
         cells = W.sample_cells(p["grid"], 200000, seed=7)
@@ -182,7 +183,9 @@ def roofline(per, kernel_key, n_cells, workload):
     traffic = measured_traffic(workload, kernel_key, kern)
     return dict(bound="hbm", achieved=per["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=per["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
-                kernel=("k_step odd (pull/push with wall reflections)" if kern == "odd" else "k_step even (local)"),
+                kernel=(("k_odd_rows odd (one wavefront per row; pull/push with wall reflections)"
+                         if per.get("odd_by_rows") else "k_step odd (pull/push with wall reflections)")
+                        if kern == "odd" else "k_step even (local)"),
                 kernel_ms=per[kern + "_kernel_ms"], algorithmic_bytes_per_launch=per["bytes_per_cell"] * n_cells)
 
 
@@ -192,7 +195,7 @@ def store_record(r, s, n, copy_gbs):
     gbs = bytes_cell * n / (r[kern + "_kernel_ms"] * 1e-3) / 1e9
     d = dict(mlups=r["mlups"], ms_per_step=r["ms_per_step"], bytes_per_cell=bytes_cell,
              odd_kernel_ms=r["odd_kernel_ms"], even_kernel_ms=r["even_kernel_ms"], dominant_kernel=kern,
-             kernel_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS,
+             kernel_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS, odd_by_rows=r.get("odd_by_rows", 0),
              step_gbs=bytes_cell * n / (r["ms_per_step"] * 1e-3) / 1e9, status=r["status"])
     if copy_gbs:
         d["copy_frac"] = gbs / copy_gbs
@@ -281,7 +284,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the channel step runs on a single MI355X here; "
-              "multi-GPU slab decomposition is not part of this build (--gpus %d refused)" % args.gpus,
+              "the multi-GPU slab decomposition is not implemented (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

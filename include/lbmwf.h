@@ -89,6 +89,8 @@ extern "C" {
                                * for 2-byte stores, 0 otherwise.  Applies when every brick is whole and holds a
                                * whole number of chunks; reads back the value in use.  Results do not depend
                                * on it. */
+#define LBM_P_ODD_BY_ROWS 17  /* read only: 1 if the odd step currently walks rows (k_odd_rows), 0 if it runs
+                               * the block kernel, as decided by LBM_P_ODD_ROWS, the store, nx and the blocks */
 
 typedef struct lbm_ctx lbm_ctx;
 

@@ -539,6 +539,7 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
         case LBM_P_BRICK: *v = brick_rows(c); break;
         case LBM_P_ODD_ROWS: *v = c->odd_rows; break;
         case LBM_P_SPREAD: *v = spread_log2(c); break;
+        case LBM_P_ODD_BY_ROWS: *v = odd_by_rows(c, c->odd_rows) ? 1.0 : 0.0; break;
         case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
         case LBM_P_BC: *v = c->bc; break;
         case LBM_P_TAU0: *v = c->tau0; break;

@@ -108,6 +108,28 @@ def test_spread_parameter(L):
             lib.lbm_destroy(h)
 
 
+def test_odd_kernel_choice_reads_back(L):
+    """LBM_P_ODD_BY_ROWS reports the odd kernel the settings select: rows are
+    walked for 2-byte stores whose rows are longer than an odd-step block
+    (mode 1), always where nx allows (mode 2), never in mode 0; read only."""
+    lib = L.lib()
+    v = C.c_double()
+    cases = [  # nx, store, odd block, mode, walks rows
+        (2048, L.LBM_STORE_F16, 128, 1, 1), (512, L.LBM_STORE_F16, 128, 1, 0), (2048, L.LBM_STORE_F64, 256, 1, 0),
+        (2048, L.LBM_STORE_F64, 256, 2, 1), (2048, L.LBM_STORE_F16, 128, 0, 0), (96, L.LBM_STORE_F16, 64, 2, 0)]
+    for nx, store, tile, mode, want in cases:
+        h = C.c_void_p()
+        assert lib.lbm_create(C.byref(L.Grid(nx, 16, 4)), 0.6, 0.1, 0.41, 5.5, 0.0, C.byref(h)) == 0
+        try:
+            assert lib.lbm_set_param(h, L.LBM_P_STORE, store) == 0
+            assert lib.lbm_set_param(h, L.LBM_P_TILE_ODD, tile) == 0
+            assert lib.lbm_set_param(h, L.LBM_P_ODD_ROWS, mode) == 0
+            assert lib.lbm_get_param(h, L.LBM_P_ODD_BY_ROWS, C.byref(v)) == 0 and v.value == want, (nx, store, mode)
+            assert lib.lbm_set_param(h, L.LBM_P_ODD_BY_ROWS, 1) == L.LBM_E_ARG
+        finally:
+            lib.lbm_destroy(h)
+
+
 def test_status_strings(L):
     lib = L.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):
