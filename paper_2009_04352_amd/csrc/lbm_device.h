@@ -92,12 +92,13 @@ __device__ __forceinline__ double uniform01(unsigned long long seed, unsigned lo
 // The FP64 iteration starts from an FP32 estimate: the log law
 // u+ = ln(y+) / kappa + B with y+ = R / p, iterated as a fixed point (it
 // contracts for p > 1 / kappa), taken when it is below the viscous guess
-// sqrt(R); then FP32 Newton steps on H until the change is below 1e-6.  Only
-// the start of the FP64 iteration depends on it.
+// sqrt(R); then FP32 Newton steps on H until the change is below 1e-6, with
+// the hardware reciprocal in place of divisions.  Only the start of the
+// FP64 iteration depends on it, and through it only the iteration count.
 //
-// The NC solves run side by side (independent dependency chains for the
-// scheduler); each cell keeps its own stopping step, so every cell gets the
-// value a solve of its own would give.  Cells with U = 0 get u_tau = 0.
+// The NC solves run side by side (independent dependency chains); each cell
+// keeps its own stopping step, so every cell gets the value a solve of its
+// own would give.  Cells with U = 0 get u_tau = 0.
 // `iters` is the largest FP64 step count of the live cells, `fail` is set if
 // any live cell reached maxit without meeting the stop.
 template <int NC>
@@ -108,7 +109,7 @@ __device__ __forceinline__ void wall_utau_n(const double (&U)[NC], double y1, do
     double R[NC], p[NC];
     bool live[NC], run[NC];
     int cnt[NC];
-    const float kf = (float)kappa, ekf = (float)ekb;
+    const float kf = (float)kappa, ekf = (float)ekb, ikf = 1.0f / kf;
     float pf[NC], Rf[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -118,7 +119,7 @@ __device__ __forceinline__ void wall_utau_n(const double (&U)[NC], double y1, do
         pf[c] = sqrtf(Rf[c]);
         float pl = pf[c];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) pl = __logf(Rf[c] / pl) / kf + (float)bconst;
+        for (int i = 0; i < 3; ++i) pl = fmaf(__logf(Rf[c] * __builtin_amdgcn_rcpf(pl)), ikf, (float)bconst);
         if (pl > 1.0f && pl < pf[c]) pf[c] = pl;
         run[c] = true;
     }
@@ -131,7 +132,7 @@ __device__ __forceinline__ void wall_utau_n(const double (&U)[NC], double y1, do
             const float br = ek - 1.0f - k - k2;
             const float sp = q + ekf * (br - k2 * k * (1.0f / 3.0f));
             const float dsp = 1.0f + kf * ekf * br;
-            const float pn = q - (q * sp - Rf[c]) / (sp + q * dsp);
+            const float pn = q - (q * sp - Rf[c]) * __builtin_amdgcn_rcpf(sp + q * dsp);
             if (run[c]) {
                 if (!(pn > 0.0f) || !(pn < INFINITY)) {
                     run[c] = false;

@@ -73,9 +73,9 @@ __device__ __forceinline__ u32x2 halo_as_first(const typename S::T* p)
 }
 
 // a3 for the V cells of a wall-row group: decode, the gathered wall-parallel
-// velocity of each cell, one joint Newton solve for the V friction
-// velocities, and the half stresses hx = tau_x / 2, hz = tau_z / 2 that the
-// bounce correction adds.  Wall rows are whole rows, so the branch that calls
+// velocity of each cell, the Newton solve for each friction velocity, and
+// the half stresses hx = tau_x / 2, hz = tau_z / 2 that the bounce
+// correction adds.  Wall rows are whole rows, so the branch that calls
 // this is uniform over the wavefront.
 template <typename S, int V>
 __device__ __forceinline__ void wall_group(const u32x2 (&w)[kQ], const StepArgs& p, typename S::R (&hx)[V],
@@ -94,7 +94,32 @@ __device__ __forceinline__ void wall_group(const u32x2 (&w)[kQ], const StepArgs&
         });
         U[k] = wall_velocity<R>(f, (R)p.fx, rho[k], vx[k], vz[k]);
     }
-    wall_utau_n<V>(U, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, ut, iters, fail);
+    // With 4 cells per thread: one solve per cell, in a loop kept rolled, so
+    // that the solve's code appears once (unrolled over the 4 cells, or two
+    // at a time, the odd step ran 2-5 % slower on MI355X).  With 1 or 2
+    // cells the solves run side by side (rolled, the 2-cell kernels need
+    // more registers).
+    if constexpr (V < 4) {
+        wall_utau_n<V>(U, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, ut, iters, fail);
+    } else {
+        iters = 0;
+        fail = false;
+#pragma unroll 1
+        for (int k = 0; k < V; ++k) {
+            double u1[1] = {U[0]}, t1[1];
+#pragma unroll
+            for (int j = 1; j < V; ++j)
+                if (k == j) u1[0] = U[j];
+            int it;
+            bool fl;
+            wall_utau_n<1>(u1, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, t1, it, fl);
+            iters = max(iters, it);
+            fail = fail || fl;
+#pragma unroll
+            for (int j = 0; j < V; ++j)
+                if (k == j) ut[j] = t1[0];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         const WallRecord rec = wall_record((double)rho[k], (double)vx[k], (double)vz[k], U[k], ut[k]);
