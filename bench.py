@@ -8,9 +8,12 @@ Workloads (synthetic inputs generated on the device, see workloads.py):
   c5            2048 x 512 x 1024 channel (1.07B cells), same physics;
   c4            64 independent channels in one launch per step (FP32 store).
 One step is one launch of the fused kernel over every cell (odd and even AA
-kernels alternate).  Timing: W untimed warm-up steps, then K steps bracketed
-by synchronisation, a HIP event recorded on the library's stream after every
-launch (per-kernel durations for the roofline).  Prints one JSON line.
+kernels alternate).  Timing: W untimed warm-up steps (default 200: in a
+fresh process the first ~100 odd steps of the 2-byte stores run up to 30 %
+slower, on MI355X, than the steady state a long run sees), then K steps
+bracketed by synchronisation, a HIP event recorded on the library's stream
+after every launch (per-kernel durations for the roofline).  Prints one
+JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c4|c5]
                 [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
@@ -276,7 +279,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5"))
     ap.add_argument("--stores", default="f64,f32,f16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
