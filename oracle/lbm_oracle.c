@@ -40,7 +40,16 @@
  *   - collision is single-relaxation-time (BGK); the Smagorinsky closure is
  *     tau_e = (tau0 + sqrt(tau0^2 + 18 Cs^2 Q / rho)) / 2 with
  *     Q = sqrt(2 Pi:Pi), Pi the non-equilibrium second moment;
- *   - F_a is the Guo et al. (2002) force term with u = (sum e f + F/2)/rho.
+ *   - F_a is the Guo et al. (2002) force term with u = (sum e f + F/2)/rho;
+ *   - MRT (optional, the paper's collision, Sec. 3.1 [40]): the moment basis
+ *     of d'Humieres et al. (2002) for D3Q19, equilibrium moments taken as the
+ *     moments of the same second-order equilibrium (so equal rates give BGK),
+ *     the stress moments relaxed at 1/tau_e, the others at given rates, the
+ *     force term added as (I - S/2) M F in moment space;
+ *   - van Driest damping (optional, Sec. 3.1 [42]): Cs (1 - exp(-y+/A+)) with
+ *     y+ = d u_tau,ref / nu0, d = min(y, ny - 1 - y) + y1 (the distance used
+ *     for the first layer) and u_tau,ref the given friction velocity, or
+ *     sqrt(|Fx| ny / 2) from the force balance when none is given.
  *
  * Arithmetic is IEEE FP64 throughout, summation order a = 0..18, built
  * with -ffp-contract=off.  Populations are stored as full f (not f - w).
@@ -88,6 +97,7 @@ static void tables_init(void)
 }
 
 enum { ORC_BB = 0, ORC_WFB = 1, ORC_FREESLIP = 2 };
+enum { ORC_BGK = 0, ORC_MRT = 1 };
 enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_NONFINITE = -5, ORC_E_NEWTON = -6 };
 
 typedef struct {
@@ -101,6 +111,13 @@ typedef struct {
     double newton_tol;   /* relative step that ends Newton */
     int32_t newton_maxit;
     int32_t stats_every; /* sample statistics on steps t with t % every == 0; 0 = off */
+    int32_t collision;   /* ORC_BGK or ORC_MRT */
+    double s_e, s_eps;   /* MRT rates of the energy and energy-square moments */
+    double s_q;          /* MRT rate of the heat-flux moments */
+    double s_pi;         /* MRT rate of the fourth-order normal-stress moments */
+    double s_m;          /* MRT rate of the third-order m moments */
+    double vd_aplus;     /* van Driest A+; <= 0: no damping */
+    double vd_utau;      /* friction velocity for the damping's y+; <= 0: sqrt(|Fx| ny / 2) */
 } orc_params;
 
 typedef struct {
@@ -250,10 +267,15 @@ int orc_wfb_cell(const orc_params* p, int wall, double f[Q], double rec[4], int3
     return ORC_OK;
 }
 
-/* BGK + Smagorinsky + body force on gathered (and WFB-corrected) f.
- * out receives the post-collision populations; taue_out (may be NULL) the
- * effective relaxation time. */
-void orc_collide_cell(const orc_params* p, const double f[Q], double out[Q], double* taue_out)
+static double cs_at(const orc_params* p, int y);
+static double mrate(const orc_params* p, int k, double omega);
+static double mrow(int k, int a);
+
+/* Collision + Smagorinsky + body force on gathered (and WFB-corrected) f of
+ * a cell in row y (y < 0: no van Driest damping).  BGK, or MRT in the
+ * moment basis.  out receives the post-collision populations; taue_out
+ * (may be NULL) the effective relaxation time. */
+void orc_collide_cell_at(const orc_params* p, int y, const double f[Q], double out[Q], double* taue_out)
 {
     tables_init();
     double rho, u[3], fe[Q];
@@ -267,16 +289,116 @@ void orc_collide_cell(const orc_params* p, const double f[Q], double out[Q], dou
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) pp += pi[i][j] * pi[i][j];
     double qn = sqrt(2.0 * pp);
-    double taue = 0.5 * (p->tau0 + sqrt(p->tau0 * p->tau0 + 18.0 * p->cs * p->cs * qn / rho));
+    double cs = cs_at(p, y);
+    double taue = 0.5 * (p->tau0 + sqrt(p->tau0 * p->tau0 + 18.0 * cs * cs * qn / rho));
     double fvec[3] = {p->fx, 0.0, 0.0};
+    double force[Q];
     for (int a = 0; a < Q; ++a) {
         double eu = E[a][0] * u[0] + E[a][1] * u[1] + E[a][2] * u[2];
         double ef = E[a][0] * fvec[0] + E[a][1] * fvec[1] + E[a][2] * fvec[2];
         double emuf = (E[a][0] - u[0]) * fvec[0] + (E[a][1] - u[1]) * fvec[1] + (E[a][2] - u[2]) * fvec[2];
-        double force = (1.0 - 1.0 / (2.0 * taue)) * W[a] * (3.0 * emuf + 9.0 * eu * ef);
-        out[a] = f[a] - (f[a] - fe[a]) / taue + force;
+        force[a] = W[a] * (3.0 * emuf + 9.0 * eu * ef);
+    }
+    if (p->collision == ORC_MRT) {
+        /* m* = m - S (m - m_eq) + (I - S/2) M F, then f* = M^-1 m* with
+         * M^-1 = M^T diag(1 / |row k|^2) (the rows are orthogonal) */
+        double mstar[Q];
+        for (int k = 0; k < Q; ++k) {
+            double m = 0.0, meq = 0.0, mf = 0.0;
+            for (int a = 0; a < Q; ++a) {
+                double c = mrow(k, a);
+                m += c * f[a];
+                meq += c * fe[a];
+                mf += c * force[a];
+            }
+            double sk = mrate(p, k, 1.0 / taue);
+            mstar[k] = m - sk * (m - meq) + (1.0 - 0.5 * sk) * mf;
+        }
+        for (int a = 0; a < Q; ++a) {
+            double v = 0.0;
+            for (int k = 0; k < Q; ++k) {
+                double n2 = 0.0;
+                for (int b = 0; b < Q; ++b) n2 += mrow(k, b) * mrow(k, b);
+                v += mrow(k, a) * mstar[k] / n2;
+            }
+            out[a] = v;
+        }
+    } else {
+        for (int a = 0; a < Q; ++a)
+            out[a] = f[a] - (f[a] - fe[a]) / taue + (1.0 - 1.0 / (2.0 * taue)) * force[a];
     }
     if (taue_out) *taue_out = taue;
+}
+
+void orc_collide_cell(const orc_params* p, const double f[Q], double out[Q], double* taue_out)
+{
+    orc_collide_cell_at(p, -1, f, out, taue_out);
+}
+
+/* ------------------------------------------------------------------ MRT */
+
+/* Row k of the D3Q19 moment basis of d'Humieres et al. (2002) at velocity e:
+ * the polynomials 1, e2 = |e|^2, energy and energy square, momentum and heat
+ * flux, the normal and off-diagonal stresses with their fourth-order
+ * partners, and the three third-order m moments, orthogonal over the 19
+ * velocities. */
+static double mrow(int k, int a)
+{
+    const double ex = E[a][0], ey = E[a][1], ez = E[a][2];
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    switch (k) {
+        case 0: return 1.0;                                            /* rho */
+        case 1: return 19.0 * e2 - 30.0;                               /* e */
+        case 2: return (21.0 * e2 * e2 - 53.0 * e2 + 24.0) / 2.0;      /* epsilon */
+        case 3: return ex;                                             /* j_x */
+        case 4: return (5.0 * e2 - 9.0) * ex;                          /* q_x */
+        case 5: return ey;                                             /* j_y */
+        case 6: return (5.0 * e2 - 9.0) * ey;                          /* q_y */
+        case 7: return ez;                                             /* j_z */
+        case 8: return (5.0 * e2 - 9.0) * ez;                          /* q_z */
+        case 9: return 3.0 * ex * ex - e2;                             /* 3 p_xx */
+        case 10: return (3.0 * e2 - 5.0) * (3.0 * ex * ex - e2);       /* 3 pi_xx */
+        case 11: return ey * ey - ez * ez;                             /* p_ww */
+        case 12: return (3.0 * e2 - 5.0) * (ey * ey - ez * ez);        /* pi_ww */
+        case 13: return ex * ey;                                       /* p_xy */
+        case 14: return ey * ez;                                       /* p_yz */
+        case 15: return ex * ez;                                       /* p_xz */
+        case 16: return (ey * ey - ez * ez) * ex;                      /* m_x */
+        case 17: return (ez * ez - ex * ex) * ey;                      /* m_y */
+        default: return (ex * ex - ey * ey) * ez;                      /* m_z */
+    }
+}
+
+void orc_mrt_basis(double* m)
+{
+    tables_init();
+    for (int k = 0; k < Q; ++k)
+        for (int a = 0; a < Q; ++a) m[k * Q + a] = mrow(k, a);
+}
+
+/* Relaxation rate of moment k: the stress moments (and the conserved ones,
+ * whose rate does not matter) at omega = 1/tau_e, the others at theirs. */
+static double mrate(const orc_params* p, int k, double omega)
+{
+    switch (k) {
+        case 1: return p->s_e;
+        case 2: return p->s_eps;
+        case 4: case 6: case 8: return p->s_q;
+        case 10: case 12: return p->s_pi;
+        case 16: case 17: case 18: return p->s_m;
+        default: return omega;
+    }
+}
+
+/* Smagorinsky constant at row y with the van Driest damping. */
+static double cs_at(const orc_params* p, int y)
+{
+    if (!(p->vd_aplus > 0.0) || y < 0) return p->cs;
+    int dy = y < p->ny - 1 - y ? y : p->ny - 1 - y;
+    double d = (double)dy + p->y1;
+    double ut = p->vd_utau > 0.0 ? p->vd_utau : sqrt(fabs(p->fx) * p->ny / 2.0);
+    double nu0 = (p->tau0 - 0.5) / 3.0;
+    return p->cs * (1.0 - exp(-(d * ut / nu0) / p->vd_aplus));
 }
 
 /* ------------------------------------------------------------ gathering */
@@ -388,6 +510,13 @@ static int params_ok(const orc_params* p)
     if (!isfinite(p->tau0) || !isfinite(p->cs) || !isfinite(p->kappa) || !isfinite(p->bconst)) return 0;
     if (!isfinite(p->fx) || !(p->y1 > 0.0) || !(p->newton_tol > 0.0) || p->newton_maxit < 1) return 0;
     if (p->bc < 0 || p->bc > 2 || p->stats_every < 0) return 0;
+    if (p->collision != ORC_BGK && p->collision != ORC_MRT) return 0;
+    if (p->collision == ORC_MRT) {
+        const double r[5] = {p->s_e, p->s_eps, p->s_q, p->s_pi, p->s_m};
+        for (int i = 0; i < 5; ++i)
+            if (!(r[i] > 0.0 && r[i] < 2.0)) return 0;
+    }
+    if (!isfinite(p->vd_aplus) || !isfinite(p->vd_utau)) return 0;
     return 1;
 }
 
@@ -479,7 +608,7 @@ static int cell_update(const src_t* s, int x, int y, int z, double out[Q], doubl
     moments(f, s->p->fx, &rho, u);
     if (mom) { mom[0] = rho; mom[1] = u[0]; mom[2] = u[1]; mom[3] = u[2]; }
     if (!(rho > 0.0) || !isfinite(rho)) return ORC_E_NONFINITE;
-    orc_collide_cell(s->p, f, out, NULL);
+    orc_collide_cell_at(s->p, y, f, out, NULL);
     return ORC_OK;
 }
 

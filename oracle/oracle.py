@@ -13,6 +13,11 @@ from . import build as _build
 
 Q = 19
 BB, WFB, FREESLIP = 0, 1, 2
+BGK, MRT = 0, 1
+# MRT rates of the non-hydrodynamic moments suggested by d'Humieres et al.
+# (2002) for D3Q19: energy, energy square, heat flux, fourth-order normal
+# stresses, third-order m moments
+MRT_RATES = dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.4, s_m=1.98)
 OK, E_ARG, E_NONFINITE, E_NEWTON = 0, -1, -5, -6
 
 
@@ -22,7 +27,9 @@ class Params(C.Structure):
         ("tau0", C.c_double), ("cs", C.c_double), ("kappa", C.c_double),
         ("bconst", C.c_double), ("fx", C.c_double), ("y1", C.c_double),
         ("newton_tol", C.c_double), ("newton_maxit", C.c_int32),
-        ("stats_every", C.c_int32),
+        ("stats_every", C.c_int32), ("collision", C.c_int32),
+        ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("s_pi", C.c_double),
+        ("s_m", C.c_double), ("vd_aplus", C.c_double), ("vd_utau", C.c_double),
     ]
 
 
@@ -54,6 +61,8 @@ def lib():
         L.orc_wfb_cell.restype = C.c_int
         L.orc_wfb_cell.argtypes = [PP, C.c_int, dp, dp, C.POINTER(C.c_int32)]
         L.orc_collide_cell.argtypes = [PP, dp, dp, C.POINTER(C.c_double)]
+        L.orc_collide_cell_at.argtypes = [PP, C.c_int, dp, dp, C.POINTER(C.c_double)]
+        L.orc_mrt_basis.argtypes = [dp]
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [PP]
         L.orc_destroy.argtypes = [C.c_void_p]
@@ -95,9 +104,12 @@ def tables():
 
 
 def make_params(nx, ny, nz, tau0, cs=0.1, kappa=0.41, bconst=5.5, fx=0.0, bc=WFB,
-                y1=1.0, newton_tol=1e-14, newton_maxit=100, stats_every=0):
+                y1=1.0, newton_tol=1e-14, newton_maxit=100, stats_every=0, collision=BGK,
+                rates=None, vd_aplus=0.0, vd_utau=0.0):
+    r = dict(MRT_RATES, **(rates or {}))
     return Params(nx, ny, nz, bc, tau0, cs, kappa, bconst, fx, y1, newton_tol,
-                  newton_maxit, stats_every)
+                  newton_maxit, stats_every, collision, r["s_e"], r["s_eps"], r["s_q"], r["s_pi"],
+                  r["s_m"], vd_aplus, vd_utau)
 
 
 def spalding_yplus(uplus, kappa=0.41, b=5.5):
@@ -129,11 +141,23 @@ def wfb_cell(params, wall, f):
     return f, rec, st, it.value
 
 
-def collide_cell(params, f):
+def collide_cell(params, f, y=None):
+    """Collision of one cell (row y for the van Driest damping; None: undamped)."""
     out = np.zeros(19)
     taue = C.c_double(0.0)
-    lib().orc_collide_cell(C.byref(params), np.ascontiguousarray(f, dtype=np.float64), out, C.byref(taue))
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if y is None:
+        lib().orc_collide_cell(C.byref(params), f, out, C.byref(taue))
+    else:
+        lib().orc_collide_cell_at(C.byref(params), int(y), f, out, C.byref(taue))
     return out, taue.value
+
+
+def mrt_basis():
+    """The moment basis rows [19 moments, 19 velocities] as the oracle holds them."""
+    m = np.zeros(19 * 19)
+    lib().orc_mrt_basis(m)
+    return m.reshape(19, 19)
 
 
 def rule_m(ny, re_tau, ma, kappa=0.41, b=5.5, y1=1.0):

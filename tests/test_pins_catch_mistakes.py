@@ -11,8 +11,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
-PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_spalding.py", "tests/test_oracle_wfb.py",
-             "tests/test_oracle_flows.py", "tests/test_oracle_paper_numbers.py", "tests/test_oracle_initial_state.py"]
+# fast pins first: the run stops at the first failure
+PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_mrt.py", "tests/test_oracle_spalding.py",
+             "tests/test_oracle_wfb.py", "tests/test_oracle_paper_numbers.py", "tests/test_oracle_initial_state.py",
+             "tests/test_oracle_flows.py", "tests/test_oracle_mrt_flows.py"]
 
 # name: (text in lbm_oracle.c, planted replacement)
 MISTAKES = {
@@ -20,9 +22,9 @@ MISTAKES = {
     "equilibrium (e.u)^2 coefficient": ("4.5 * eu * eu", "4.0 * eu * eu"),
     "equilibrium u.u sign": ("- 1.5 * uu", "+ 1.5 * uu"),
     "full force in the velocity": ("j[0] += 0.5 * fx;", "j[0] += 1.0 * fx;"),
-    "Guo prefactor dropped": ("(1.0 - 1.0 / (2.0 * taue)) * W[a]", "W[a]"),
+    "Guo prefactor dropped": ("+ (1.0 - 1.0 / (2.0 * taue)) * force[a];", "+ force[a];"),
     "Guo second-order term": ("9.0 * eu * ef", "3.0 * eu * ef"),
-    "Smagorinsky constant 18 -> 9": ("18.0 * p->cs * p->cs", "9.0 * p->cs * p->cs"),
+    "Smagorinsky constant 18 -> 9": ("18.0 * cs * cs", "9.0 * cs * cs"),
     "Smagorinsky Q without the 2": ("sqrt(2.0 * pp)", "sqrt(pp)"),
     "wall stress sign": ("taux = -(vx / U) * tauw;", "taux = (vx / U) * tauw;"),
     "wall stress without rho": ("double tauw = rho * utau * utau;", "double tauw = utau * utau;"),
@@ -35,10 +37,16 @@ MISTAKES = {
     "streaming from the wrong side": ("int sx = wrap(x - E[a][0], p->nx);", "int sx = wrap(x + E[a][0], p->nx);"),
     "bounce-back set of the free-slip wall": ("(E[a][0] == 0 && E[a][2] == 0)", "(E[a][0] == 0)"),
     "statistics u_x u_z for u_x u_y": ("r[6] += mom[1] * mom[2];", "r[6] += mom[1] * mom[3];"),
-    "initial profile distance without y1": ("double d = (double)dy + p->y1;", "double d = (double)dy;"),
+    "initial profile distance without y1": ("double d = (double)dy + p->y1;\n        prof[y]", "double d = (double)dy;\n        prof[y]"),
+    "MRT energy row": ("case 1: return 19.0 * e2 - 30.0;", "case 1: return 19.0 * e2 - 31.0;"),
+    "MRT heat flux relaxed at the m rate": ("case 4: case 6: case 8: return p->s_q;", "case 4: case 6: case 8: return p->s_m;"),
+    "MRT stress relaxed at the pi rate": ("case 10: case 12: return p->s_pi;", "case 9: case 10: case 12: return p->s_pi;"),
+    "MRT force without the half rate": ("(1.0 - 0.5 * sk) * mf", "(1.0 - sk) * mf"),
+    "MRT inverse without the row norm": ("v += mrow(k, a) * mstar[k] / n2;", "v += mrow(k, a) * mstar[k] / 19.0;"),
+    "van Driest exponent without A+": ("exp(-(d * ut / nu0) / p->vd_aplus)", "exp(-(d * ut / nu0))"),
+    "van Driest damping inverted": ("return p->cs * (1.0 - exp(", "return p->cs * (exp("),
     "one noise draw for all components": ("3u * c + (uint64_t)i", "3u * c"),
-    "relaxation multiplied by tau": ("out[a] = f[a] - (f[a] - fe[a]) / taue + force;",
-                                     "out[a] = f[a] - (f[a] - fe[a]) * taue + force;"),
+    "relaxation multiplied by tau": ("out[a] = f[a] - (f[a] - fe[a]) / taue +", "out[a] = f[a] - (f[a] - fe[a]) * taue +"),
     "nu0 without the 1/3": ("double nu0 = (p->tau0 - 0.5) / 3.0;\n        utau", "double nu0 = (p->tau0 - 0.5);\n        utau"),
     "wall velocity without the half force": ("    jx += 0.5 * p->fx;\n    double vx", "    double vx"),
     "statistics sample count": ("o->stats[8 * y + 7] += (double)p->nx * p->nz;", "o->stats[8 * y + 7] += (double)p->nx;"),
