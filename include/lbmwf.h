@@ -91,6 +91,21 @@ extern "C" {
                                * on it. */
 #define LBM_P_ODD_BY_ROWS 17  /* read only: 1 if the odd step currently walks rows (k_odd_rows), 0 if it runs
                                * the block kernel, as decided by LBM_P_ODD_ROWS, the store, nx and the blocks */
+#define LBM_P_COLLISION 18    /* 0 = BGK (default); 1 = MRT, the paper's collision (Sec. 3.1, after d'Humieres
+                               * et al. 2002): the D3Q19 moment basis of that paper, equilibrium moments of the
+                               * same second-order equilibrium (equal rates give BGK), the viscous stresses
+                               * relaxed at 1/tau_e (Smagorinsky), the non-hydrodynamic moments at the rates
+                               * below, the body force added as (I - S/2) M F in moment space */
+#define LBM_P_MRT_S_E 19      /* MRT rate of the energy moment, in (0, 2); default 1.19 */
+#define LBM_P_MRT_S_EPS 20    /* ... of the energy-square moment; default 1.4 */
+#define LBM_P_MRT_S_Q 21      /* ... of the three heat-flux moments; default 1.2 */
+#define LBM_P_MRT_S_PI 22     /* ... of the two fourth-order normal-stress moments; default 1.4 */
+#define LBM_P_MRT_S_M 23      /* ... of the three third-order moments; default 1.98 */
+#define LBM_P_VD_APLUS 24     /* van Driest damping of the Smagorinsky constant (Sec. 3.1): Cs (1 - exp(-y+/A+))
+                               * with y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1; A+ >= 0, 0 = no damping
+                               * (default); the paper's reference uses 26 */
+#define LBM_P_VD_UTAU 25      /* friction velocity u_tau of that y+, >= 0; 0 (default) = sqrt(|Fx| ny / 2), the
+                               * force-balance value of the channel */
 
 typedef struct lbm_ctx lbm_ctx;
 

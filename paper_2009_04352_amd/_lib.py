@@ -15,7 +15,10 @@ LBM_BB, LBM_WFB, LBM_FREESLIP = 0, 1, 2
 LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2, 3
 (LBM_P_Y1, LBM_P_NEWTON_TOL, LBM_P_NEWTON_MAXIT, LBM_P_STATS_EVERY, LBM_P_STORE, LBM_P_TILE_ODD,
  LBM_P_TILE_EVEN, LBM_P_XCD_REMAP, LBM_P_GRAPH_STEPS, LBM_P_BC, LBM_P_TAU0, LBM_P_FX, LBM_P_CS,
- LBM_P_VECTOR, LBM_P_BRICK, LBM_P_ODD_ROWS, LBM_P_SPREAD, LBM_P_ODD_BY_ROWS) = range(18)
+ LBM_P_VECTOR, LBM_P_BRICK, LBM_P_ODD_ROWS, LBM_P_SPREAD, LBM_P_ODD_BY_ROWS, LBM_P_COLLISION,
+ LBM_P_MRT_S_E, LBM_P_MRT_S_EPS, LBM_P_MRT_S_Q, LBM_P_MRT_S_PI, LBM_P_MRT_S_M, LBM_P_VD_APLUS,
+ LBM_P_VD_UTAU) = range(26)
+LBM_BGK, LBM_MRT = 0, 1
 
 # every symbol the header declares, with (restype, argtypes)
 _dp = C.POINTER(C.c_double)

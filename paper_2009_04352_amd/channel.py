@@ -13,6 +13,21 @@ STORES = {"f64": L.LBM_STORE_F64, "f32": L.LBM_STORE_F32, "f16": L.LBM_STORE_F16
 BOUNDARIES = {"bb": L.LBM_BB, "wfb": L.LBM_WFB, "freeslip": L.LBM_FREESLIP}
 
 
+MRT_KEYS = {"s_e": L.LBM_P_MRT_S_E, "s_eps": L.LBM_P_MRT_S_EPS, "s_q": L.LBM_P_MRT_S_Q,
+            "s_pi": L.LBM_P_MRT_S_PI, "s_m": L.LBM_P_MRT_S_M}
+
+
+def set_collision(setter, collision="bgk", mrt_rates=None, van_driest=0.0, van_driest_utau=0.0):
+    """Collision operator ("bgk" or "mrt"), MRT rates by name (s_e, s_eps,
+    s_q, s_pi, s_m; others keep their defaults) and the van Driest A+ (0: off)
+    with the friction velocity of its y+ (0: from the force balance)."""
+    setter(L.LBM_P_COLLISION, {"bgk": L.LBM_BGK, "mrt": L.LBM_MRT}[collision])
+    for k, v in (mrt_rates or {}).items():
+        setter(MRT_KEYS[k], v)
+    setter(L.LBM_P_VD_APLUS, van_driest)
+    setter(L.LBM_P_VD_UTAU, van_driest_utau)
+
+
 def spalding_uplus(yplus, kappa=0.41, B=5.5):
     """u+ of Spalding's law at y+ (host inversion in the library)."""
     out = C.c_double(0.0)
@@ -53,7 +68,7 @@ class Channel:
 
     def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
                  device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False,
-                 vector=0, brick=0):
+                 vector=0, brick=0, collision="bgk", mrt_rates=None, van_driest=0.0, van_driest_utau=0.0):
         import torch
         self.lib = L.lib()
         self.shape = (nz, ny, nx)
@@ -78,6 +93,7 @@ class Channel:
             self._set(L.LBM_P_VECTOR, vector)
         if brick:
             self._set(L.LBM_P_BRICK, brick)
+        set_collision(self._set, collision, mrt_rates, van_driest, van_driest_utau)
         nbytes = C.c_size_t(0)
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value
@@ -222,7 +238,8 @@ class Batch:
     cs, fx, bc."""
 
     def __init__(self, specs, kappa=0.41, B=5.5, store="f32", device="cuda", stream=None, tiles=None,
-                 graph_steps=None, vector=0, brick=0):
+                 graph_steps=None, vector=0, brick=0, collision="bgk", mrt_rates=None, van_driest=0.0,
+                 van_driest_utau=0.0):
         import torch
         self.lib = L.lib()
         n = len(specs)
@@ -250,6 +267,7 @@ class Batch:
             self._set(L.LBM_P_VECTOR, vector)
         if brick:
             self._set(L.LBM_P_BRICK, brick)
+        set_collision(self._set, collision, mrt_rates, van_driest, van_driest_utau)
         nbytes = C.c_size_t(0)
         L.check_batch(self.lib.lbm_batch_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value

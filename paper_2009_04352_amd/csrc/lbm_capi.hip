@@ -48,6 +48,10 @@ struct lbm_ctx {
     int brick_req = 0;           // rows per brick of the population layout requested; 0 = automatic
     int brick = 0;               // rows per brick in use; fixed while the state is initialised
     int odd_rows = 1;            // odd step by rows: 0 never, 1 when rows are longer than a block, 2 whenever possible
+    int coll = kBGK;             // collision: kBGK or kMRT
+    double mrt_s[5] = {1.19, 1.4, 1.2, 1.4, 1.98};  // MRT rates (d'Humieres et al. 2002): e, epsilon, q, pi, m
+    double vd_aplus = 0.0;       // van Driest A+; 0 = no damping
+    double vd_utau = 0.0;        // friction velocity of the damping's y+; 0 = sqrt(|Fx| ny / 2)
     int spread = -1;             // launch order: log2 of the tile chunks that cycle through the bricks; 0 = memory
                                  // order; -1 = by store format (spread_log2)
 
@@ -63,6 +67,9 @@ struct lbm_ctx {
     double* dpart = nullptr;     // [max tiles][7]
     size_t part_cap = 0;         // tiles
     double* dtmp = nullptr;      // relayout scratch, [2 nx nz][5]
+    double* dcs2 = nullptr;      // [ny] 18 Cs^2 with the van Driest damping
+    std::vector<double> hcs2;    // its host copy
+    bool cs2_dirty = true;
 
     bool initialized = false;
     long long steps = 0;
@@ -199,6 +206,9 @@ StepArgs step_args(const lbm_ctx* c, bool odd, int rows_mode)
     a.newton_maxit = c->newton_maxit;
     a.tau0 = c->tau0;
     a.cs2_18 = 18.0 * c->cs * c->cs;
+    a.cs2_row = (c->vd_aplus > 0.0) ? c->dcs2 : nullptr;
+    a.coll = c->coll;
+    for (int i = 0; i < 5; ++i) a.mrt_s[i] = c->mrt_s[i];
     a.fx = c->fx;
     a.y1 = c->y1;
     a.nu0 = (c->tau0 - 0.5) / 3.0;
@@ -431,6 +441,7 @@ void lbm_destroy(lbm_ctx* c)
     if (c->dprof) (void)hipFree(c->dprof);
     if (c->dpart) (void)hipFree(c->dpart);
     if (c->dtmp) (void)hipFree(c->dtmp);
+    if (c->dcs2) (void)hipFree(c->dcs2);
     delete c;
 }
 
@@ -516,9 +527,30 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
             if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "Cs must be >= 0");
             c->cs = v;
             break;
+        case LBM_P_COLLISION:
+            if (v != kBGK && v != kMRT) return fail(c, LBM_E_ARG, "collision is 0 (BGK) or 1 (MRT)");
+            c->coll = (int)v;
+            break;
+        case LBM_P_MRT_S_E:
+        case LBM_P_MRT_S_EPS:
+        case LBM_P_MRT_S_Q:
+        case LBM_P_MRT_S_PI:
+        case LBM_P_MRT_S_M:
+            if (!(v > 0.0 && v < 2.0)) return fail(c, LBM_E_ARG, "MRT rates must lie in (0, 2)");
+            c->mrt_s[key - LBM_P_MRT_S_E] = v;
+            break;
+        case LBM_P_VD_APLUS:
+            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest A+ must be >= 0");
+            c->vd_aplus = v;
+            break;
+        case LBM_P_VD_UTAU:
+            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest friction velocity must be >= 0");
+            c->vd_utau = v;
+            break;
         default:
             return fail(c, LBM_E_ARG, "unknown or read-only parameter key");
     }
+    c->cs2_dirty = true;
     drop_graphs(c);
     return LBM_OK;
 }
@@ -540,6 +572,14 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
         case LBM_P_ODD_ROWS: *v = c->odd_rows; break;
         case LBM_P_SPREAD: *v = spread_log2(c); break;
         case LBM_P_ODD_BY_ROWS: *v = odd_by_rows(c, c->odd_rows) ? 1.0 : 0.0; break;
+        case LBM_P_COLLISION: *v = c->coll; break;
+        case LBM_P_MRT_S_E:
+        case LBM_P_MRT_S_EPS:
+        case LBM_P_MRT_S_Q:
+        case LBM_P_MRT_S_PI:
+        case LBM_P_MRT_S_M: *v = c->mrt_s[key - LBM_P_MRT_S_E]; break;
+        case LBM_P_VD_APLUS: *v = c->vd_aplus; break;
+        case LBM_P_VD_UTAU: *v = c->vd_utau; break;
         case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
         case LBM_P_BC: *v = c->bc; break;
         case LBM_P_TAU0: *v = c->tau0; break;
@@ -575,7 +615,9 @@ int lbm_bind_storage(lbm_ctx* c, void* ptr, size_t bytes)
         LBM_HIP(c, hipMalloc((void**)&c->dflags, sizeof(DevFlags)));
         LBM_HIP(c, hipMalloc((void**)&c->dacc, (size_t)c->ny * 8 * sizeof(double)));
         LBM_HIP(c, hipMalloc((void**)&c->dprof, (size_t)c->ny * sizeof(double)));
+        LBM_HIP(c, hipMalloc((void**)&c->dcs2, (size_t)c->ny * sizeof(double)));
         LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
+        c->cs2_dirty = true;
     }
     drop_graphs(c);
     c->h = ptr;
@@ -734,6 +776,28 @@ int lbm_get_state_cells(lbm_ctx* c, int64_t n, const int64_t* cells, double* out
     return get_state_impl(c, n, cells, out);
 }
 
+// The per-row Smagorinsky factor 18 Cs^2 (1 - exp(-y+/A+))^2 with
+// y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1 (the first-layer distance
+// rule) and u_tau the given friction velocity or sqrt(|Fx| ny / 2) from the
+// force balance; uploaded in stream order when a parameter changed.
+int refresh_damping(lbm_ctx* c, hipStream_t s)
+{
+    if (!(c->vd_aplus > 0.0) || !c->cs2_dirty) return LBM_OK;
+    const double nu0 = (c->tau0 - 0.5) / 3.0;
+    const double ut = c->vd_utau > 0.0 ? c->vd_utau : std::sqrt(std::fabs(c->fx) * c->ny / 2.0);
+    LBM_HIP(c, hipStreamSynchronize(s));   // no step still reads the old table
+    c->hcs2.resize((size_t)c->ny);
+    for (int y = 0; y < c->ny; ++y) {
+        const int dy = std::min(y, c->ny - 1 - y);
+        const double d = (double)dy + c->y1;
+        const double ce = c->cs * (1.0 - std::exp(-(d * ut / nu0) / c->vd_aplus));
+        c->hcs2[(size_t)y] = 18.0 * ce * ce;
+    }
+    LBM_HIP(c, hipMemcpyAsync(c->dcs2, c->hcs2.data(), (size_t)c->ny * sizeof(double), hipMemcpyHostToDevice, s));
+    c->cs2_dirty = false;
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx* c, int64_t n)
 {
     int st = check_ready(c);
@@ -744,6 +808,7 @@ int lbm_step(lbm_ctx* c, int64_t n)
     DeviceGuard dg(c->dev);
     if ((st = fix_layout(c)) != LBM_OK) return st;
     if ((st = ensure_partials(c)) != LBM_OK) return st;
+    if ((st = refresh_damping(c, c->stream)) != LBM_OK) return st;
     long long left = n;
     while (left > 0) {
         if (c->graph_steps > 0 && left >= c->graph_steps) {
@@ -1336,6 +1401,14 @@ int lbm_batch_set_param(lbm_batch* b, int key, double v)
         case LBM_P_Y1:
         case LBM_P_NEWTON_TOL:
         case LBM_P_NEWTON_MAXIT:
+        case LBM_P_COLLISION:
+        case LBM_P_MRT_S_E:
+        case LBM_P_MRT_S_EPS:
+        case LBM_P_MRT_S_Q:
+        case LBM_P_MRT_S_PI:
+        case LBM_P_MRT_S_M:
+        case LBM_P_VD_APLUS:
+        case LBM_P_VD_UTAU:
             for (lbm_ctx* c : b->inst) {
                 c->batch_member = false;
                 int st = lbm_set_param(c, key, v);
@@ -1426,6 +1499,8 @@ int lbm_batch_step(lbm_batch* b, int64_t n)
     DeviceGuard dg(b->dev);
     int st = batch_tables(b);
     if (st != LBM_OK) return st;
+    for (lbm_ctx* c : b->inst)
+        if ((st = refresh_damping(c, b->stream)) != LBM_OK) return bfail(b, st, c->err);
     long long left = n;
     while (left > 0) {
         if (b->graph_steps > 0 && left >= b->graph_steps) {

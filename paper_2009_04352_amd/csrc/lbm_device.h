@@ -267,6 +267,60 @@ __device__ __forceinline__ WallRecord wfb_correct(R (&f)[kQ], bool top, double f
     return rec;
 }
 
+// ---------------------------------------------- MRT basis (Sec. 3.1, [40])
+
+// Moment m_k of velocity a in the D3Q19 basis of d'Humieres et al. (2002):
+// polynomials of e that are orthogonal over the 19 velocities.  Rows 0, 3,
+// 5, 7 are density and momentum; 9, 11, 13-15 the viscous stresses; the
+// others (energy 1, energy square 2, heat flux 4, 6, 8, fourth-order
+// normal stresses 10, 12, third-order 16-18) are not hydrodynamic and relax
+// at rates of their own.
+constexpr int mrt_row(int k, int a)
+{
+    const int ex = kEx[a], ey = kEy[a], ez = kEz[a], e2 = ex * ex + ey * ey + ez * ez;
+    switch (k) {
+        case 0: return 1;
+        case 1: return 19 * e2 - 30;
+        case 2: return (21 * e2 * e2 - 53 * e2 + 24) / 2;   // even: 24, -8, 1 for |e|^2 = 0, 1, 2
+        case 3: return ex;
+        case 4: return (5 * e2 - 9) * ex;
+        case 5: return ey;
+        case 6: return (5 * e2 - 9) * ey;
+        case 7: return ez;
+        case 8: return (5 * e2 - 9) * ez;
+        case 9: return 3 * ex * ex - e2;
+        case 10: return (3 * e2 - 5) * (3 * ex * ex - e2);
+        case 11: return ey * ey - ez * ez;
+        case 12: return (3 * e2 - 5) * (ey * ey - ez * ez);
+        case 13: return ex * ey;
+        case 14: return ey * ez;
+        case 15: return ex * ez;
+        case 16: return (ey * ey - ez * ez) * ex;
+        case 17: return (ez * ez - ex * ex) * ey;
+        default: return (ex * ex - ey * ey) * ez;
+    }
+}
+
+constexpr int mrt_norm(int k)
+{
+    int n = 0;
+    for (int a = 0; a < kQ; ++a) n += mrt_row(k, a) * mrt_row(k, a);
+    return n;
+}
+
+static_assert(mrt_norm(1) == 2394 && mrt_norm(2) == 252 && mrt_norm(10) == 72 && mrt_norm(16) == 8, "basis norms");
+
+// The non-hydrodynamic moments and the rate (index into MrtRates::s) each
+// relaxes at: energy, energy square, heat flux, fourth-order normal
+// stresses, third-order moments.
+constexpr int kMrtNH[10] = {1, 2, 4, 6, 8, 10, 12, 16, 17, 18};
+constexpr int kMrtRate[10] = {0, 1, 2, 2, 2, 3, 3, 4, 4, 4};
+
+template <typename R>
+struct MrtRates {
+    R s[5];   // energy, energy square, heat flux, fourth-order normal stress, third-order
+};
+
 // ------------------------------------------------- collision (Sec. 3.1, Eq. 1)
 
 // The library is compiled without automatic contraction, so that every
@@ -306,8 +360,15 @@ static_assert(kEx[17] == 0 && kEy[17] == 1 && kEz[17] == -1, "pair 17");
 // and an odd part 3 w rho e.u, and the force term into -3 u_x + 9 e_x e.u and
 // 3 e_x (per unit force along x); both halves of the update are then
 // polynomials in e.u whose coefficients depend only on the weight class.
-template <typename R>
-__device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx)
+//
+// MRT (the paper's collision, [40]): the BGK result plus, for each
+// non-hydrodynamic moment k, M^-1 of (omega - s_k) (n_k + F_k / 2), where
+// n = M (f - f_eq) and F = M (force term): the difference between relaxing
+// that moment at s_k (with the force added as (I - S/2) M F) and at omega.
+// The stress moments relax at omega = 1/tau_e in both, density and
+// momentum are conserved (their rates do not enter).
+template <typename R, bool MRT = false>
+__device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx, const MrtRates<R>* mr = nullptr)
 {
     R s[kQ], d[kQ];  // indexed by the odd member of each pair
     R drho = f[0];
@@ -345,6 +406,44 @@ __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx
     const R usq = R(1.5) * fmad(ux, ux, fmad(uy, uy, uz * uz));
     const R m3ux = R(-3) * ux;
     const R t0 = fmad(rho, -usq, drho);          // drho - rho * 1.5 u.u
+
+    // MRT: x_k = n_k + F_k / 2 of the non-hydrodynamic moments, from the
+    // pre-collision pairs.  Per pair (a, opp a) of the weight class w the
+    // sum and difference of g = f - f_eq + F / 2 are
+    //   s - w (2 t0 + 9 rho (e.u)^2 + 3 u_x Fx - 9 e_x (e.u) Fx),
+    //   d - 3 w (2 rho e.u - e_x Fx),
+    // and the rest population's is f0 - w0 (t0 + 1.5 u_x Fx).
+    R xk[10] = {};
+    if constexpr (MRT) {
+        const R g0 = f[0] - weight<R>(0) * fmad(R(1.5) * ux, fx, t0);
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (a == 0) {
+#pragma unroll
+                for (int i = 0; i < 10; ++i)
+                    if (kMrtNH[i] == 1 || kMrtNH[i] == 2 || kMrtNH[i] == 10 || kMrtNH[i] == 12)
+                        xk[i] = R(mrt_row(kMrtNH[i], 0)) * g0;
+            } else if constexpr (a % 2 == 1) {
+                constexpr R w = weight<R>(a);
+                R eu = R(0);
+                if constexpr (kEx[a] == 1) eu = ux;
+                if constexpr (kEy[a] == 1) eu = (kEx[a] != 0) ? eu + uy : uy;
+                if constexpr (kEy[a] == -1) eu = eu - uy;
+                if constexpr (kEz[a] == 1) eu = (kEx[a] != 0 || kEy[a] != 0) ? eu + uz : uz;
+                if constexpr (kEz[a] == -1) eu = eu - uz;
+                const R ex_fx = (kEx[a] != 0) ? fx : R(0);
+                const R gs = s[a] - w * fmad(R(9) * rho * eu, eu, fmad(R(3) * ux, fx, fmad(R(-9) * eu, ex_fx, R(2) * t0)));
+                const R gd = d[a] - (R(3) * w) * fmad(R(2) * rho, eu, -ex_fx);
+#pragma unroll
+                for (int i = 0; i < 10; ++i) {
+                    const int k = kMrtNH[i];
+                    const int c = mrt_row(k, a);
+                    const bool even = (k == 1 || k == 2 || k == 10 || k == 12);
+                    if (c != 0) xk[i] = fmad(R(c), even ? gs : gd, xk[i]);
+                }
+            }
+        });
+    }
 
     {   // rest population: e = 0
         constexpr R w = weight<R>(0);
@@ -388,6 +487,37 @@ __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx
             f[a + 1] = S - D;
         }
     });
+    if constexpr (MRT) {
+        // c_k = (omega - s_k) x_k / |row k|^2, added back through M^T
+        R ck[10];
+#pragma unroll
+        for (int i = 0; i < 10; ++i)
+            ck[i] = (om - mr->s[kMrtRate[i]]) * xk[i] * R(1.0 / (double)mrt_norm(kMrtNH[i]));
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (a == 0) {
+                R v = R(0);
+#pragma unroll
+                for (int i = 0; i < 10; ++i)
+                    if (mrt_row(kMrtNH[i], 0) != 0) v = fmad(R(mrt_row(kMrtNH[i], 0)), ck[i], v);
+                f[0] += v;
+            } else if constexpr (a % 2 == 1) {
+                R ev = R(0), od = R(0);
+#pragma unroll
+                for (int i = 0; i < 10; ++i) {
+                    const int k = kMrtNH[i];
+                    const int c = mrt_row(k, a);
+                    const bool even = (k == 1 || k == 2 || k == 10 || k == 12);
+                    if (c != 0) {
+                        if (even) ev = fmad(R(c), ck[i], ev);
+                        else od = fmad(R(c), ck[i], od);
+                    }
+                }
+                f[a] += ev + od;
+                f[a + 1] += ev - od;
+            }
+        });
+    }
     return Moments<R>{rho, ux, uy, uz};
 }
 

@@ -59,6 +59,8 @@ __host__ __device__ inline int fdiv(int n, FastDiv f) { return (int)(((unsigned 
 // launch).  A block processes one tile: rpb whole x-rows of one z-plane, or
 // one segment of tile_x * vw cells of a single x-row.  Tiles are numbered in
 // memory order: x segment, row group within a brick, z, brick.
+enum { kBGK = 0, kMRT = 1 };
+
 // Blocks go round-robin to the 8 XCDs; with the XCD remap each XCD takes
 // chunks of 2^kXcdChunkLog2 consecutive tiles in turn.
 constexpr int kXcdChunkLog2 = 5;
@@ -90,6 +92,9 @@ struct StepArgs {
     int newton_maxit;
     double tau0;          // molecular relaxation time
     double cs2_18;        // 18 Cs^2 (Smagorinsky closure)
+    const double* cs2_row;// 18 Cs^2 per row y with the van Driest damping; nullptr: cs2_18 in every row
+    int coll;             // collision: kBGK or kMRT
+    double mrt_s[5];      // MRT rates: energy, energy square, heat flux, fourth-order normal stress, third order
     double fx;            // body force density along x
     double y1;            // wall distance of the first layer used in y+
     double nu0;           // molecular viscosity (tau0 - 1/2) / 3

@@ -132,13 +132,18 @@ __device__ __forceinline__ void wall_group(const u32x2 (&w)[kQ], const StepArgs&
 // (wall_wfb: the cells are wall-adjacent and the boundary is WFB), moments,
 // Smagorinsky, BGK with the body force, encode.  Accumulates the sampled
 // velocity sums, the largest Newton iteration count and the failure flags.
-template <typename S, int V, bool MAYBE_WFB, bool STATS>
-__device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p, bool wall_wfb, bool top,
-                                              double (&sm)[7], int& iters, bool& bad, bool& newton_fail)
+template <typename S, int V, bool MAYBE_WFB, bool STATS, bool MRT>
+__device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p, typename S::R cs2, bool wall_wfb,
+                                              bool top, double (&sm)[7], int& iters, bool& bad, bool& newton_fail)
 {
     using R = typename S::R;
     using Ln = Lane<S, V>;
     constexpr bool PAIRS = (sizeof(typename S::T) == 2) && (V >= 2);
+    MrtRates<R> mr;
+    if constexpr (MRT) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) mr.s[i] = (R)p.mrt_s[i];
+    }
     // a3: wall-function bounce at wall-adjacent cells
     R whx[V], whz[V];
     if constexpr (MAYBE_WFB) {
@@ -158,8 +163,8 @@ __device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p,
         if constexpr (MAYBE_WFB) {
             if (wall_wfb) wfb_apply<R>(f, top, whx[k], whz[k]);
         }
-        // a4-a6: moments, Smagorinsky, BGK + body force
-        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
+        // a4-a6: moments, Smagorinsky, BGK (or MRT) + body force
+        const Moments<R> m = collide<R, MRT>(f, (R)p.tau0, cs2, (R)p.fx, &mr);
         bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
         if constexpr (STATS) {
             const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
@@ -215,7 +220,7 @@ constexpr int kBCRuntime = 3;
 template <typename S, int V>
 constexpr int min_waves() { return (sizeof(typename S::T) == 2 && V == 4) ? 3 : 1; }
 
-template <typename S, int V, bool ODD, int BCT, bool STATS>
+template <typename S, int V, bool ODD, int BCT, bool STATS, bool MRT>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_waves<S, V>()))) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
                                                     const int* __restrict__ tile_inst, int ntiles_all)
 {
@@ -375,6 +380,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     // allocation of this kernel came out tighter this way)
     constexpr bool PAIRS = (sizeof(T) == 2) && (V >= 2);
     const bool wall_wfb = MAYBE_WFB && wfb && (bot || top) && L.active;
+    MrtRates<R> mr;
+    if constexpr (MRT) {
+#pragma unroll
+        for (int i = 0; i < 5; ++i) mr.s[i] = (R)p.mrt_s[i];
+    }
     R whx[V], whz[V];
     if constexpr (MAYBE_WFB) {
         if (wall_wfb) wall_group<S, V>(w, p, whx, whz, iters, newton_fail);
@@ -387,7 +397,9 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         if constexpr (MAYBE_WFB) {
             if (wall_wfb) wfb_apply<R>(f, top, whx[k], whz[k]);
         }
-        const Moments<R> m = collide<R>(f, (R)p.tau0, (R)p.cs2_18, (R)p.fx);
+        // Smagorinsky factor of this row (van Driest damping)
+        const R cs2 = (R)((p.cs2_row && L.active) ? p.cs2_row[y] : p.cs2_18);
+        const Moments<R> m = collide<R, MRT>(f, (R)p.tau0, cs2, (R)p.fx, &mr);
         bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
         if constexpr (STATS) {
             const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
@@ -581,7 +593,7 @@ struct Edge {
 // reads exactly the slots it writes, and carried elements are taken from the
 // loads of their own segment.  No LDS, no barrier, and no memory line is
 // written in parts by two wavefronts.
-template <typename S, int V, int BCT, bool STATS>
+template <typename S, int V, int BCT, bool STATS, bool MRT>
 __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepArgs* __restrict__ table,
                                                         const int* __restrict__ tile_inst, int ntiles_all)
 {
@@ -621,6 +633,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
     const int yi0 = rem - z * bk;
     const int y = yb * p.brick + yi0;
     const bool bot = (y == 0), top = (y == p.ny - 1);
+    const typename S::R cs2 = (typename S::R)(p.cs2_row ? p.cs2_row[y] : p.cs2_18);  // van Driest damping
     const int zm = (z == 0) ? p.nz - 1 : z - 1;
     const int zp = (z == p.nz - 1) ? 0 : z + 1;
     const bool plain = (p.brick >= p.ny);
@@ -737,7 +750,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
             }
         });
         // a3-a6
-        collide_group<S, V, MAYBE_WFB, STATS>(w, p, wfb && (bot || top), top, sm, iters, bad, newton_fail);
+        collide_group<S, V, MAYBE_WFB, STATS, MRT>(w, p, cs2, wfb && (bot || top), top, sm, iters, bad, newton_fail);
         // a7: store with wall reflections
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
@@ -806,16 +819,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
     }
 }
 
-template <typename S, int V>
+template <typename S, int V, bool MRT>
 static hipError_t launch_odd_rows(int bc, const StepArgs& a, hipStream_t s)
 {
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
 #define LBM_ROWS(BCT)                                                                                          \
     do {                                                                                                       \
         if (a.partials)                                                                                        \
-            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, true>), grid, block, 0, s, a, nullptr, nullptr, 0);      \
+            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, true, MRT>), grid, block, 0, s, a, nullptr, nullptr, 0); \
         else                                                                                                   \
-            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, false>), grid, block, 0, s, a, nullptr, nullptr, 0);     \
+            hipLaunchKernelGGL((k_odd_rows<S, V, BCT, false, MRT>), grid, block, 0, s, a, nullptr, nullptr, 0);\
     } while (0)
     if (bc == kBB) LBM_ROWS(kBB);
     else if (bc == kWFB) LBM_ROWS(kWFB);
@@ -824,19 +837,19 @@ static hipError_t launch_odd_rows(int bc, const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename S, int V, bool ODD>
+template <typename S, int V, bool ODD, bool MRT>
 static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
     if constexpr (ODD)
-        if (a.nseg > 0) return launch_odd_rows<S, V>(bc, a, s);
+        if (a.nseg > 0) return launch_odd_rows<S, V, MRT>(bc, a, s);
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
     const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
-#define LBM_STEP(BCT)                                                                                        \
-    do {                                                                                                     \
-        if (a.partials)                                                                                      \
-            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, true>), grid, block, lds, s, a, nullptr, nullptr, 0);  \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false>), grid, block, lds, s, a, nullptr, nullptr, 0); \
+#define LBM_STEP(BCT)                                                                                              \
+    do {                                                                                                           \
+        if (a.partials)                                                                                            \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, true, MRT>), grid, block, lds, s, a, nullptr, nullptr, 0);  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false, MRT>), grid, block, lds, s, a, nullptr, nullptr, 0); \
     } while (0)
     if (bc == kBB) LBM_STEP(kBB);
     else if (bc == kWFB) LBM_STEP(kWFB);
@@ -845,18 +858,20 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename S, int V>
+template <typename S, int V, bool MRT>
 static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* table, const int* tile_inst, int ntiles,
                                  hipStream_t s)
 {
     const dim3 grid((unsigned)ntiles), block((unsigned)a0.tile_x);
     const size_t lds = odd ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
     if (odd && a0.nseg > 0)
-        hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false>), grid, block, 0, s, a0, table, tile_inst, ntiles);
+        hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false, MRT>), grid, block, 0, s, a0, table, tile_inst, ntiles);
     else if (odd)
-        hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);
+        hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false, MRT>), grid, block, lds, s, a0, table, tile_inst,
+                           ntiles);
     else
-        hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false>), grid, block, lds, s, a0, table, tile_inst, ntiles);
+        hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false, MRT>), grid, block, lds, s, a0, table, tile_inst,
+                           ntiles);
     return hipGetLastError();
 }
 
@@ -880,7 +895,9 @@ hipError_t launch_step_store(bool odd, int bc, const StepArgs& a, hipStream_t s)
 {
     return with_width<S>(a.vw, [&](auto Vc) {
         constexpr int V = decltype(Vc)::value;
-        return odd ? launch_step_bc<S, V, true>(bc, a, s) : launch_step_bc<S, V, false>(bc, a, s);
+        if (a.coll == kMRT)
+            return odd ? launch_step_bc<S, V, true, true>(bc, a, s) : launch_step_bc<S, V, false, true>(bc, a, s);
+        return odd ? launch_step_bc<S, V, true, false>(bc, a, s) : launch_step_bc<S, V, false, false>(bc, a, s);
     });
 }
 
@@ -889,7 +906,8 @@ hipError_t launch_batch_store(bool odd, const StepArgs& a0, const StepArgs* tabl
                               hipStream_t s)
 {
     return with_width<S>(a0.vw, [&](auto Vc) {
-        return launch_batch_v<S, decltype(Vc)::value>(odd, a0, table, tile_inst, ntiles, s);
+        if (a0.coll == kMRT) return launch_batch_v<S, decltype(Vc)::value, true>(odd, a0, table, tile_inst, ntiles, s);
+        return launch_batch_v<S, decltype(Vc)::value, false>(odd, a0, table, tile_inst, ntiles, s);
     });
 }
 

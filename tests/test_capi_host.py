@@ -130,6 +130,33 @@ def test_odd_kernel_choice_reads_back(L):
             lib.lbm_destroy(h)
 
 
+def test_collision_and_damping_parameters(L):
+    """Collision 0/1, MRT rates in (0, 2) with the defaults of d'Humieres et
+    al. (2002), van Driest A+ and friction velocity >= 0; all read back."""
+    lib = L.lib()
+    v = C.c_double()
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(L.Grid(64, 16, 4)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(h)) == 0
+    try:
+        get = lambda k: (lib.lbm_get_param(h, k, C.byref(v)), v.value)[1]
+        assert get(L.LBM_P_COLLISION) == L.LBM_BGK
+        keys = (L.LBM_P_MRT_S_E, L.LBM_P_MRT_S_EPS, L.LBM_P_MRT_S_Q, L.LBM_P_MRT_S_PI, L.LBM_P_MRT_S_M)
+        assert [get(k) for k in keys] == [1.19, 1.4, 1.2, 1.4, 1.98]
+        assert get(L.LBM_P_VD_APLUS) == 0.0 and get(L.LBM_P_VD_UTAU) == 0.0
+        assert lib.lbm_set_param(h, L.LBM_P_COLLISION, L.LBM_MRT) == 0 and get(L.LBM_P_COLLISION) == L.LBM_MRT
+        assert lib.lbm_set_param(h, L.LBM_P_COLLISION, 2) == L.LBM_E_ARG
+        for k in keys:
+            assert lib.lbm_set_param(h, k, 1.5) == 0 and get(k) == 1.5
+            for bad in (0.0, 2.0, -1.0):
+                assert lib.lbm_set_param(h, k, bad) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_VD_APLUS, 26.0) == 0 and get(L.LBM_P_VD_APLUS) == 26.0
+        assert lib.lbm_set_param(h, L.LBM_P_VD_UTAU, 1e-3) == 0 and get(L.LBM_P_VD_UTAU) == 1e-3
+        assert lib.lbm_set_param(h, L.LBM_P_VD_APLUS, -1.0) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_VD_UTAU, -1.0) == L.LBM_E_ARG
+    finally:
+        lib.lbm_destroy(h)
+
+
 def test_status_strings(L):
     lib = L.lib()
     for code in (0, -1, -2, -3, -4, -5, -6):
