@@ -17,6 +17,9 @@ JSON line.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c4|c5]
                 [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
+                [--collision bgk|mrt] [--van-driest A+]
+The headline line is the BGK step (the default); --collision mrt with
+--van-driest 26 measures the paper's LES collision on the same workload.
 """
 import argparse
 import hashlib
@@ -82,14 +85,18 @@ def timed_steps(torch, stepper, stream, steps, warmup, first_step):
     return total, odd, even
 
 
-def run_store(P, W, name, store, steps, warmup):
+def collision_kw(args):
+    return dict(collision=args.collision, van_driest=args.van_driest)
+
+
+def run_store(P, W, name, store, steps, warmup, coll):
     import numpy as np
     import torch
     p = W.params(name)
     nx, ny, nz = p["grid"]
     n = nx * ny * nz
     ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
-                   tiles=W.launch_tiles(name, store), graph_steps=0)
+                   tiles=W.launch_tiles(name, store, coll["collision"]), graph_steps=0, **coll)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     total_ms, odd_ms, even_ms = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
     status, first_bad = ch.sync()
@@ -137,16 +144,17 @@ def copy_probe_gbs(P, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(W, name, budget_s=20.0):
+def cpu_baseline(W, name, coll, budget_s=20.0):
     """The FP64 CPU oracle on this host's cores: a bounded sample of the same
     workload (the same grid from the same initial state, a few steps)."""
     from oracle import oracle as O
+    okw = dict(collision=O.MRT if coll["collision"] == "mrt" else O.BGK, vd_aplus=coll["van_driest"])
     if name == "c4":
         ens = W.ensemble()
         o_list = []
         for e in ens:
             o = O.Oracle(O.make_params(e["nx"], e["ny"], e["nz"], e["tau"], cs=e["cs"], fx=e["fx"],
-                                       bc=O.WFB if e["bc"] == "wfb" else O.BB))
+                                       bc=O.WFB if e["bc"] == "wfb" else O.BB, **okw))
             o.init_spalding(e["u_tau"], 0.05, e["seed"])
             o_list.append(o)
         cells = sum(e["nx"] * e["ny"] * e["nz"] for e in ens)
@@ -166,7 +174,7 @@ def cpu_baseline(W, name, budget_s=20.0):
         if nx * ny * nz > FULL_FIELD_LIMIT:   # a z-slab of the large channel fits the host
             nz = 16
         cells = nx * ny * nz
-        o = O.Oracle(O.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=O.WFB))
+        o = O.Oracle(O.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=O.WFB, **okw))
         o.init_spalding(p["u_tau"], p["noise"], p["seed"])
         t0 = time.perf_counter()
         o.step(1)
@@ -181,9 +189,10 @@ def cpu_baseline(W, name, budget_s=20.0):
     return dict(value=cells * k / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle", sample=sample)
 
 
-def roofline(per, kernel_key, n_cells, workload):
+def roofline(per, kernel_key, n_cells, workload, collision="bgk"):
     kern = per["dominant_kernel"]
-    traffic = measured_traffic(workload, kernel_key, kern)
+    # the committed counter summaries were taken with the BGK kernels
+    traffic = measured_traffic(workload, kernel_key, kern) if collision == "bgk" else None
     return dict(bound="hbm", achieved=per["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=per["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
                 kernel=(("k_odd_rows odd (one wavefront per row; pull/push with wall reflections)"
@@ -215,7 +224,7 @@ def bench_single(P, W, args, copy_gbs):
     n = nx * ny * nz
     res, acc = {}, {}
     for s in stores:
-        r, a, p = run_store(P, W, args.workload, s, args.steps, args.warmup)
+        r, a, p = run_store(P, W, args.workload, s, args.steps, args.warmup, collision_kw(args))
         print("[bench] %s: %.1f MLUPS, odd %.4f ms, even %.4f ms, status %d"
               % (s, r["mlups"], r["odd_kernel_ms"], r["even_kernel_ms"], r["status"]), file=sys.stderr, flush=True)
         res[s], acc[s] = r, a
@@ -235,8 +244,10 @@ def bench_single(P, W, args, copy_gbs):
     hd = per_store[head]
     config = {"workload": "%s: %s" % (args.workload, wl["desc"]), "grid": [nx, ny, nz], "store": head,
               "boundary": "wfb", "re_tau": wl["re_tau"], "tau0": p["tau0"], "fx": p["fx"],
-              "launch": list(W.launch_tiles(args.workload, head)), "parallelism": "single GPU"}
-    return hd, per_store, config, roofline(hd, head, n, args.workload), "f32" if head != "f64" else "f64"
+              "launch": list(W.launch_tiles(args.workload, head, args.collision)), "collision": args.collision,
+              "van_driest_aplus": args.van_driest, "parallelism": "single GPU"}
+    roof = roofline(hd, head, n, args.workload, args.collision)
+    return hd, per_store, config, roof, "f32" if head != "f64" else "f64"
 
 
 def bench_ensemble(P, W, args, copy_gbs):
@@ -244,7 +255,7 @@ def bench_ensemble(P, W, args, copy_gbs):
     ens = W.ensemble(W.ENSEMBLE["n"])
     store = W.ENSEMBLE["store"]
     n = sum(e["nx"] * e["ny"] * e["nz"] for e in ens)
-    b = P.Batch(ens, store=store, graph_steps=0)
+    b = P.Batch(ens, store=store, graph_steps=0, **collision_kw(args))
     tiles = b.autotune(steps=6)
     b.init_spalding([e["u_tau"] for e in ens], 0.05, seeds=[e["seed"] for e in ens])
     total_ms, odd_ms, even_ms = timed_steps(torch, b.step, b.stream, args.steps, args.warmup, 1)
@@ -252,7 +263,7 @@ def bench_ensemble(P, W, args, copy_gbs):
     r = dict(ms_per_step=total_ms / args.steps, mlups=n * args.steps / (total_ms * 1e-3) / 1e6,
              odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status))
     # the same work through captured graphs, the production path
-    b2 = P.Batch(ens, store=store, tiles=tiles, graph_steps=50)
+    b2 = P.Batch(ens, store=store, tiles=tiles, graph_steps=50, **collision_kw(args))
     b2.init_spalding([e["u_tau"] for e in ens], 0.05, seeds=[e["seed"] for e in ens])
     b2.step(100)
     torch.cuda.synchronize()
@@ -272,7 +283,8 @@ def bench_ensemble(P, W, args, copy_gbs):
               "launch": list(tiles), "parallelism": "single GPU"}
     b.close()
     b2.close()
-    return d, {store: d}, config, roofline(d, store, n, "c4"), "f32"
+    config.update(collision=args.collision, van_driest_aplus=args.van_driest)
+    return d, {store: d}, config, roofline(d, store, n, "c4", args.collision), "f32"
 
 
 def main():
@@ -284,6 +296,9 @@ def main():
     ap.add_argument("--stores", default="f64,f32,f16,bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--collision", default="bgk", choices=("bgk", "mrt"),
+                    help="collision operator (mrt: the paper's LES collision)")
+    ap.add_argument("--van-driest", type=float, default=0.0, help="van Driest A+ (0: no damping)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the channel step runs on a single MI355X here; "
@@ -321,7 +336,7 @@ def main():
         "kernel_source": kernel_source_hash(),
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(W, args.workload)
+        line["cpu_baseline"] = cpu_baseline(W, args.workload, collision_kw(args))
     print(json.dumps(line), flush=True)
 
 

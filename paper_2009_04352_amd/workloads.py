@@ -98,9 +98,14 @@ LAUNCH_TILES = {
     "c3": {"f64": (512, 512, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
     "c5": {"f64": (256, 256, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
 }
+# With the MRT collision the FP64 odd step of the 512-cell rows runs faster in
+# 256-thread row segments (its registers allow fewer resident wavefronts).
+LAUNCH_TILES_MRT = {"c3": {"f64": (256, 512, 1)}}
 
 
-def launch_tiles(workload, store):
+def launch_tiles(workload, store, collision="bgk"):
+    if collision == "mrt" and store in LAUNCH_TILES_MRT.get(workload, {}):
+        return LAUNCH_TILES_MRT[workload][store]
     return LAUNCH_TILES.get(workload, LAUNCH_TILES["c3"])[store]
 
 
