@@ -192,6 +192,17 @@ int lbm_moments_cells(lbm_ctx* ctx, int64_t n, const int64_t* cells, double* out
  * Free-slip: zeros and U.  Synchronises. */
 int lbm_wall_shear(lbm_ctx* ctx, double* tau_x, double* tau_z, double* u_tau, double* U);
 
+/* Distribution of the first-layer y+ over the wall cells (Fig. 7: the PDF of
+ * y1+ normalised by its mean and standard deviation), computed on the device
+ * from the current wall records: y+ = y1 u_tau / nu0 with nu0 = (tau0 - 1/2)/3.
+ * mean_std[2] receives the mean and the population standard deviation of y+
+ * (FP64, fixed summation order); counts[nbins + 2] the number of wall cells
+ * whose z = (y+ - mean) / std falls below lo (counts[0]), in bin k of
+ * [lo + k w, lo + (k + 1) w), w = (hi - lo) / nbins (counts[k + 1]), or at or
+ * above hi (counts[nbins + 1]).  Host arrays, caller-owned; 1 <= nbins <= 2^20,
+ * lo < hi, else LBM_E_ARG.  Synchronises. */
+int lbm_wall_yplus_pdf(lbm_ctx* ctx, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std);
+
 /* Plane statistics (Sec. 3.1 time and plane averages, Fig. 6 moments),
  * accumulated in FP64 on sampled steps from the velocity each sampled step
  * computes.  lbm_stats_sums: out[y][8] = sums of ux, uy, uz, ux^2, uy^2, uz^2,

@@ -200,6 +200,16 @@ class Channel:
         self._chk(self.lib.lbm_wall_shear(self._h, *[L.dptr(o) for o in outs]))
         return tuple(o.reshape(2, self.nz, self.nx) for o in outs)
 
+    def wall_yplus_pdf(self, nbins=40, lo=-4.0, hi=4.0):
+        """Distribution of the first-layer y+ normalised by its mean and standard
+        deviation (Fig. 7): returns (counts[nbins + 2] with under- and overflow
+        bins first and last, bin edges, mean, std)."""
+        counts = np.zeros(nbins + 2, dtype=np.int64)
+        ms = np.zeros(2)
+        self._chk(self.lib.lbm_wall_yplus_pdf(self._h, nbins, lo, hi, counts.ctypes.data_as(C.c_void_p),
+                                              L.dptr(ms)))
+        return counts, np.linspace(lo, hi, nbins + 1), ms[0], ms[1]
+
     def stats_reset(self):
         self._chk(self.lib.lbm_stats_reset(self._h))
 

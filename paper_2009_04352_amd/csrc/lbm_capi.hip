@@ -961,6 +961,53 @@ int lbm_wall_shear(lbm_ctx* c, double* tx, double* tz, double* ut, double* U)
     return LBM_OK;
 }
 
+int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std)
+{
+    if (!c || !counts || !mean_std) return fail(c, LBM_E_ARG, "null argument");
+    if (nbins < 1 || nbins > (1 << 20) || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+        return fail(c, LBM_E_ARG, "need 1 <= nbins <= 2^20 and finite lo < hi");
+    int st = check_ready(c);
+    if (st != LBM_OK) return st;
+    DeviceGuard dg(c->dev);
+    if ((st = fix_layout(c)) != LBM_OK) return st;
+    if ((st = sync_check(c)) != LBM_OK) return st;
+    const long long m = 2ll * c->nx * c->nz;
+    double* rec = nullptr;
+    double* ms = nullptr;
+    unsigned long long* dcnt = nullptr;
+    hipError_t e = hipMalloc((void**)&rec, (size_t)m * 4 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&ms, 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&dcnt, (size_t)(nbins + 2) * sizeof(unsigned long long));
+    std::vector<unsigned long long> hc((size_t)nbins + 2);
+    double hms[2] = {0.0, 0.0};
+    if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)(nbins + 2) * sizeof(unsigned long long), c->stream);
+    if (e == hipSuccess) {
+        ObsArgs a = obs_args(c);
+        a.mode = 1;
+        a.cells = nullptr;
+        a.first = 0;
+        a.count = m;
+        a.out = rec;
+        a.iters = nullptr;
+        e = launch_observe(c->store, a, c->stream);
+    }
+    const double nu0 = (c->tau0 - 0.5) / 3.0;
+    if (e == hipSuccess)
+        e = launch_yplus_pdf(rec, m, c->y1, nu0, ms, lo, (double)nbins / (hi - lo), nbins, dcnt, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hms, ms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hc.data(), dcnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (rec) (void)hipFree(rec);
+    if (ms) (void)hipFree(ms);
+    if (dcnt) (void)hipFree(dcnt);
+    if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("wall y+ distribution: ") + hipGetErrorString(e));
+    for (size_t i = 0; i < hc.size(); ++i) counts[i] = (int64_t)hc[i];
+    mean_std[0] = hms[0];
+    mean_std[1] = hms[1];
+    return LBM_OK;
+}
+
 int lbm_stats_reset(lbm_ctx* c)
 {
     if (!c) return fail(nullptr, LBM_E_ARG, "null context");

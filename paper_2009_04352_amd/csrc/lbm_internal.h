@@ -143,6 +143,8 @@ hipError_t launch_get_state(int store, const void* h, long long n, int nx, int n
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
                             hipStream_t s);
 hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s);
+hipError_t launch_yplus_pdf(const double* rec, long long m, double y1, double nu0, double* ms, double lo, double scale,
+                            int nbins, unsigned long long* counts, hipStream_t s);
 hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int brick, int from_spec,
                            int to_spec, double* tmp, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);

@@ -556,6 +556,70 @@ hipError_t launch_codec(int store, const float* in, float* out, long long n, hip
     return dispatch_store<CodecK>(store, blocks_for(n, 256), dim3(256), s, in, out, n);
 }
 
+// First-layer y+ of the wall records (Fig. 7): y+ = y1 u_tau / nu0 per wall
+// cell.  k_yplus_moments: one block forms the mean and then the mean square
+// deviation in FP64 in a fixed order (thread t takes records t, t + 256, ...;
+// then a tree over the threads) and writes the mean and the population
+// standard deviation.  k_yplus_hist counts
+// z = (y+ - mean) / std into nbins bins of width (hi - lo) / nbins from lo,
+// with an underflow bin first and an overflow bin last.
+__global__ __launch_bounds__(256) void k_yplus_moments(const double* __restrict__ rec, long long m, double y1,
+                                                       double nu0, double* __restrict__ ms)
+{
+    __shared__ double sh[256];
+    const int t = (int)threadIdx.x;
+    // two passes: the mean, then the mean square deviation from it
+    double mean = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double a = 0.0;
+        for (long long i = t; i < m; i += 256) {
+            const double yp = (y1 * rec[4 * i + 2]) / nu0;
+            a += pass == 0 ? yp : (yp - mean) * (yp - mean);
+        }
+        sh[t] = a;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (t < o) sh[t] += sh[t + o];
+            __syncthreads();
+        }
+        const double v = sh[0] / (double)m;
+        __syncthreads();
+        if (pass == 0) {
+            mean = v;
+        } else if (t == 0) {
+            ms[0] = mean;
+            ms[1] = sqrt(v);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_yplus_hist(const double* __restrict__ rec, long long m, double y1, double nu0,
+                                                    const double* __restrict__ ms, double lo, double scale, int nbins,
+                                                    unsigned long long* __restrict__ counts)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double yp = (y1 * rec[4 * i + 2]) / nu0;
+    const double z = (yp - ms[0]) / ms[1];
+    const double u = (z - lo) * scale;
+    int bin;
+    if (!(u >= 0.0)) bin = 0;                 // below lo (and NaN)
+    else if (u >= (double)nbins) bin = nbins + 1;
+    else bin = 1 + (int)floor(u);
+    atomicAdd(&counts[bin], 1ull);
+}
+
+hipError_t launch_yplus_pdf(const double* rec, long long m, double y1, double nu0, double* ms, double lo, double scale,
+                            int nbins, unsigned long long* counts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_yplus_moments, dim3(1), dim3(256), 0, s, rec, m, y1, nu0, ms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_yplus_hist, blocks_for(m, 256), dim3(256), 0, s, rec, m, y1, nu0, ms, lo, scale, nbins,
+                       counts);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
 {
     if (bytes % 16 != 0) return hipErrorInvalidValue;

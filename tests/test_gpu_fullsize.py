@@ -20,11 +20,11 @@ def P():
     return P
 
 
-def _channel(P, store, named=False, workload="c3"):
+def _channel(P, store, named=False, workload="c3", collision="bgk", van_driest=0.0):
     from paper_2009_04352_amd import workloads as W
     p = W.params(workload, named_tau=named)
     ch = P.Channel(*p["grid"], p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
-                   tiles=W.launch_tiles(workload, store))
+                   tiles=W.launch_tiles(workload, store, collision), collision=collision, van_driest=van_driest)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     return ch, p
 
@@ -42,17 +42,24 @@ def _release(ch):
 FULL = [("c3", "f64"), ("c3", "f32"), ("c3", "f16"), ("c3", "bf16"), ("c5", "f16"), ("c5", "f32"), ("c5", "f64")]
 
 
-@pytest.mark.parametrize("workload,store", FULL)
-def test_one_step_sampled(P, orc, workload, store):
+# the MRT line of the benchmark (--collision mrt --van-driest 26) on the
+# 512 x 128 x 256 channel
+FULL_MRT = [("c3", "f64", "mrt"), ("c3", "f32", "mrt"), ("c3", "f16", "mrt"), ("c3", "bf16", "mrt")]
+
+
+@pytest.mark.parametrize("workload,store,collision", [f + ("bgk",) for f in FULL] + FULL_MRT)
+def test_one_step_sampled(P, orc, workload, store, collision):
     """Tolerance: the initial rounding to the store (half an ulp of each input
     population, carried through one collision with relaxation factor below 2
     into at most 19 terms) plus one ulp of the output and the arithmetic bound."""
     from paper_2009_04352_amd import workloads as W
-    print("full-size sampled step: %s %s" % (workload, store), flush=True)
-    ch, p = _channel(P, store, workload=workload)
+    print("full-size sampled step: %s %s %s" % (workload, store, collision), flush=True)
+    vd = 26.0 if collision == "mrt" else 0.0
+    ch, p = _channel(P, store, workload=workload, collision=collision, van_driest=vd)
     cells = W.sample_cells(p["grid"], 3000, seed=1)
     nx, ny, nz = p["grid"]
-    op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB)
+    op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB,
+                         collision=orc.MRT if collision == "mrt" else orc.BGK, vd_aplus=vd)
     w = orc.tables()[1][None, :]
     h_init = orc.init_cells(op, p["u_tau"], p["noise"], p["seed"], cells) - w
     ref_round = ref_rounding(w, h_init)   # the oracle's f - w in FP64
