@@ -1,0 +1,107 @@
+"""Mean-profile validation of a channel run against the wall law (Sec. 3.2):
+the L2 error norm of Eq. 19 against Spalding's law (Eq. 16) in the buffer
+layer, the logarithmic layer and the whole half channel, and the log-law
+intercept b of Eq. 20.
+
+profile_metrics works on the FP64 plane statistics of a run; run() drives a
+channel on the GPU (develop, then sample) and returns the metrics:
+
+python -m paper_2009_04352_amd.validation --workload c3 --store f16 --bc wfb \
+    --collision mrt --van-driest 26 --develop 400000 --sample 400000
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from .channel import spalding_uplus
+
+
+def profile_metrics(mean_ux, u_tau, nu0, y1=1.0, kappa=0.41, B=5.5, split=100.0):
+    """Metrics of a mean streamwise profile mean_ux[y] (y = 0 .. ny - 1, walls
+    below 0 and above ny - 1): the two halves are folded onto the distance
+    d = y + y1 from the nearer wall (the first-layer rule), u+ = <u_x> / u_tau,
+    y+ = d u_tau / nu0.  Returns the layers' y+, u+ and Spalding's u+, the
+    Eq. 19 norms for y+ < split (buffer), y+ >= split (logarithmic) and all
+    layers, and b = mean of u+ - ln(y+) / kappa over the logarithmic layers
+    (the least-squares intercept of Eq. 20 at fixed kappa)."""
+    u = np.asarray(mean_ux, dtype=np.float64)
+    half = len(u) // 2
+    fold = 0.5 * (u[:half] + u[::-1][:half])
+    yp = (np.arange(half) + y1) * u_tau / nu0
+    up = fold / u_tau
+    us = np.array([spalding_uplus(v, kappa, B) for v in yp])
+
+    def eps(mask):
+        if not np.any(mask):
+            return None
+        return float(math.sqrt(((up[mask] - us[mask]) ** 2).sum() / (us[mask] ** 2).sum()))
+
+    buf, log = yp < split, yp >= split
+    b = float((up[log] - np.log(yp[log]) / kappa).mean()) if np.any(log) else None
+    return dict(yplus=yp.tolist(), uplus=up.tolist(), spalding=us.tolist(), eps_buffer=eps(buf), eps_log=eps(log),
+                eps_all=eps(np.ones_like(buf)), b=b)
+
+
+def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, develop=400000, sample=400000,
+        stats_every=20, report_every=50000, out=sys.stderr):
+    """Develop the channel from its Spalding initial state, then sample the
+    plane statistics every stats_every steps; progress lines every
+    report_every steps.  Returns the metrics with the run's parameters."""
+    import torch
+
+    from . import Channel
+    from . import workloads as W
+    p = W.params(workload)
+    nx, ny, nz = p["grid"]
+    ch = Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
+                 tiles=W.launch_tiles(workload, store, collision), collision=collision, van_driest=van_driest)
+    ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
+    T = (ny / 2.0) / p["u_tau"]            # D / u_tau in steps
+    t0 = time.time()
+    done = 0
+    for phase, n in (("develop", develop), ("sample", sample)):
+        if phase == "sample":
+            ch.set_param(3, stats_every)   # LBM_P_STATS_EVERY
+            ch.stats_reset()
+        while n > 0:
+            k = min(n, report_every)
+            ch.step(k)
+            st, first = ch.sync()
+            n -= k
+            done += k
+            print("[validation] %s %s %s %s: step %d (%.2f T), %.0f s, status %d"
+                  % (workload, store, bc, collision, done, done / T, time.time() - t0, st), file=out, flush=True)
+            if st != 0:
+                return dict(status=st, first_bad_step=first, steps=done)
+    stats, nsamp = ch.stats()
+    m = profile_metrics(stats[:, 0], p["u_tau"], p["nu0"])
+    m.update(workload=workload, grid=[nx, ny, nz], store=store, bc=bc, collision=collision,
+             van_driest_aplus=van_driest, re_tau=W.WORKLOADS[workload]["re_tau"], u_tau=p["u_tau"],
+             develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
+             seconds=time.time() - t0)
+    ch.close()
+    torch.cuda.empty_cache()
+    return m
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--store", default="f16")
+    ap.add_argument("--bc", default="wfb")
+    ap.add_argument("--collision", default="mrt")
+    ap.add_argument("--van-driest", type=float, default=26.0)
+    ap.add_argument("--develop", type=int, default=400000)
+    ap.add_argument("--sample", type=int, default=400000)
+    ap.add_argument("--stats-every", type=int, default=20)
+    a = ap.parse_args()
+    m = run(a.workload, a.store, a.bc, a.collision, a.van_driest, a.develop, a.sample, a.stats_every)
+    print(json.dumps(m))
+
+
+if __name__ == "__main__":
+    main()

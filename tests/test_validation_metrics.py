@@ -1,0 +1,40 @@
+"""The profile metrics of Eq. 19 and Eq. 20 on profiles of known answer."""
+import math
+
+import numpy as np
+
+from paper_2009_04352_amd.channel import spalding_uplus
+from paper_2009_04352_amd.validation import profile_metrics
+
+
+def _profile(ny, u_tau, nu0, uplus_of):
+    d = np.minimum(np.arange(ny), ny - 1 - np.arange(ny)) + 1.0
+    return np.array([u_tau * uplus_of(v * u_tau / nu0) for v in d])
+
+
+def test_spalding_profile_has_zero_error():
+    u_tau, nu0 = 2e-3, 1e-4           # y+ from 20 to 1280 over 64 layers
+    m = profile_metrics(_profile(128, u_tau, nu0, spalding_uplus), u_tau, nu0)
+    assert m["eps_buffer"] <= 1e-14 and m["eps_log"] <= 1e-14 and m["eps_all"] <= 1e-14
+    assert len(m["yplus"]) == 64 and abs(m["yplus"][0] - 20.0) <= 1e-12
+
+
+def test_scaled_profile_error_is_the_scale():
+    u_tau, nu0 = 2e-3, 1e-4
+    m = profile_metrics(1.03 * _profile(128, u_tau, nu0, spalding_uplus), u_tau, nu0)
+    for k in ("eps_buffer", "eps_log", "eps_all"):
+        assert abs(m[k] - 0.03) <= 1e-12
+
+
+def test_log_law_intercept():
+    u_tau, nu0, b0 = 2e-3, 1e-4, 6.5
+    m = profile_metrics(_profile(128, u_tau, nu0, lambda yp: math.log(yp) / 0.41 + b0), u_tau, nu0)
+    assert abs(m["b"] - b0) <= 1e-12
+
+
+def test_halves_are_folded():
+    u_tau, nu0 = 2e-3, 1e-4
+    u = _profile(128, u_tau, nu0, spalding_uplus)
+    skew = np.linspace(-1.0, 1.0, 128) * 1e-3 * u.max()     # antisymmetric: cancels in the fold
+    m = profile_metrics(u + skew, u_tau, nu0)
+    assert m["eps_all"] <= 1e-12
