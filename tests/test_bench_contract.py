@@ -1,0 +1,44 @@
+"""The benchmark's command-line contract that holds without a GPU: more than
+one GPU is refused with a message, the options parse, the kernel source hash
+covers the device sources, and committed traffic summaries are used only for
+the kernel sources they were taken on."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_help_lists_the_options():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 0
+    for opt in ("--steps", "--warmup", "--workload", "--stores", "--collision", "--van-driest"):
+        assert opt in r.stdout
+
+
+def test_traffic_used_only_for_its_kernel_sources(tmp_path, monkeypatch):
+    import bench
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    for wl in ("c3", "c5"):
+        path = os.path.join(ROOT, "profiles", "traffic_%s.json" % wl)
+        with open(path) as fh:
+            t = json.load(fh)
+        if t["kernel_source"] == h:
+            rec = t["stores"]["f16"]["odd"]
+            assert bench.measured_traffic(wl, "f16", "odd") == rec["bytes_per_launch"]
+            # a traffic figure within 3 % of the algorithmic bytes: no re-reads
+            assert abs(rec["bytes_per_launch"] / rec["algorithmic"] - 1.0) <= 0.03
+    # a summary taken on other sources is ignored
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("c3", "f16", "odd") is None
