@@ -221,7 +221,9 @@ constexpr int kBCRuntime = 3;
 template <typename S, int V, bool ODD, bool MRT>
 constexpr int min_waves() { return (sizeof(typename S::T) == 2 && V == 4 && !(ODD && MRT)) ? 3 : 1; }
 
-template <typename S, int V, bool ODD, int BCT, bool STATS, bool MRT>
+// WHOLE: every block holds whole rows (the odd step's exchange then never
+// needs a halo or a partial store, and that code is left out).
+template <typename S, int V, bool ODD, int BCT, bool STATS, bool MRT, bool WHOLE>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_waves<S, V, ODD, MRT>()))) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
                                                     const int* __restrict__ tile_inst, int ntiles_all)
 {
@@ -260,7 +262,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     const int bgk = last_brick ? p.bg_last : p.bgroups;          // row groups of this brick
     const int z = last_brick ? fdiv(rem, p.fd_bg_last) : fdiv(rem, p.fd_bgroups);
     const int yt = yb * p.bgroups + (rem - z * bgk);
-    const bool whole = (p.ntx == 1);
+    const bool whole = WHOLE || (p.ntx == 1);
     const int tpr = whole ? p.nx / V : nthr;        // threads per row segment
     const int r = fdiv(t, p.fd_tpr), tr = t - r * tpr;
     const int y = yt * p.rpb + r;
@@ -845,17 +847,24 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
         if (a.nseg > 0) return launch_odd_rows<S, V, MRT>(bc, a, s);
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
     const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
-#define LBM_STEP(BCT)                                                                                              \
-    do {                                                                                                           \
-        if (a.partials)                                                                                            \
-            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, true, MRT>), grid, block, lds, s, a, nullptr, nullptr, 0);  \
-        else                                                                                                       \
-            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false, MRT>), grid, block, lds, s, a, nullptr, nullptr, 0); \
+#define LBM_STEP_W(BCT, W)                                                                                          \
+    do {                                                                                                            \
+        if (a.partials)                                                                                             \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, true, MRT, W>), grid, block, lds, s, a, nullptr, nullptr, 0);  \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false, MRT, W>), grid, block, lds, s, a, nullptr, nullptr, 0); \
+    } while (0)
+    // the odd step of whole-row blocks runs the kernel without segment code
+#define LBM_STEP(BCT)                                   \
+    do {                                                \
+        if (ODD && a.ntx == 1) LBM_STEP_W(BCT, ODD);    \
+        else LBM_STEP_W(BCT, false);                    \
     } while (0)
     if (bc == kBB) LBM_STEP(kBB);
     else if (bc == kWFB) LBM_STEP(kWFB);
     else LBM_STEP(kFreeSlip);
 #undef LBM_STEP
+#undef LBM_STEP_W
     return hipGetLastError();
 }
 
@@ -868,11 +877,11 @@ static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* t
     if (odd && a0.nseg > 0)
         hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false, MRT>), grid, block, 0, s, a0, table, tile_inst, ntiles);
     else if (odd)
-        hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false, MRT>), grid, block, lds, s, a0, table, tile_inst,
-                           ntiles);
+        hipLaunchKernelGGL((k_step<S, V, true, kBCRuntime, false, MRT, false>), grid, block, lds, s, a0, table,
+                           tile_inst, ntiles);
     else
-        hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false, MRT>), grid, block, lds, s, a0, table, tile_inst,
-                           ntiles);
+        hipLaunchKernelGGL((k_step<S, V, false, kBCRuntime, false, MRT, false>), grid, block, lds, s, a0, table,
+                           tile_inst, ntiles);
     return hipGetLastError();
 }
 
