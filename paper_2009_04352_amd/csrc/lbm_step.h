@@ -221,8 +221,9 @@ constexpr int kBCRuntime = 3;
 template <typename S, int V, bool ODD, bool MRT>
 constexpr int min_waves() { return (sizeof(typename S::T) == 2 && V == 4 && !(ODD && MRT)) ? 3 : 1; }
 
-// WHOLE: every block holds whole rows (the odd step's exchange then never
-// needs a halo or a partial store, and that code is left out).
+// WHOLE: every block holds exactly one whole row, nx / V threads (the odd
+// step's exchange then never needs a halo or a partial store, and that code
+// is left out; the row is uniform over the block).
 template <typename S, int V, bool ODD, int BCT, bool STATS, bool MRT, bool WHOLE>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_waves<S, V, ODD, MRT>()))) void k_step(StepArgs p0, const StepArgs* __restrict__ table,
                                                     const int* __restrict__ tile_inst, int ntiles_all)
@@ -262,9 +263,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     const int bgk = last_brick ? p.bg_last : p.bgroups;          // row groups of this brick
     const int z = last_brick ? fdiv(rem, p.fd_bg_last) : fdiv(rem, p.fd_bgroups);
     const int yt = yb * p.bgroups + (rem - z * bgk);
+    // WHOLE: one whole row per block, so the row (y, the wall flags, the
+    // row factors) is the same for every thread and stays in scalar registers
     const bool whole = WHOLE || (p.ntx == 1);
     const int tpr = whole ? p.nx / V : nthr;        // threads per row segment
-    const int r = fdiv(t, p.fd_tpr), tr = t - r * tpr;
+    const int r = WHOLE ? 0 : fdiv(t, p.fd_tpr), tr = t - r * tpr;
     const int y = yt * p.rpb + r;
     const int seg0 = xt * nthr * V;                  // first cell of the segment
     const int nact = whole ? tpr : min(nthr, (p.nx - seg0) / V);
@@ -840,6 +843,9 @@ static hipError_t launch_odd_rows(int bc, const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Blocks of exactly one whole row: nx / V threads per block.
+inline bool whole_row_blocks(const StepArgs& a) { return a.ntx == 1 && a.rpb == 1 && a.nx == a.vw * a.tile_x; }
+
 template <typename S, int V, bool ODD, bool MRT>
 static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
@@ -854,11 +860,11 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
         else                                                                                                        \
             hipLaunchKernelGGL((k_step<S, V, ODD, BCT, false, MRT, W>), grid, block, lds, s, a, nullptr, nullptr, 0); \
     } while (0)
-    // the odd step of whole-row blocks runs the kernel without segment code
-#define LBM_STEP(BCT)                                   \
-    do {                                                \
-        if (ODD && a.ntx == 1) LBM_STEP_W(BCT, ODD);    \
-        else LBM_STEP_W(BCT, false);                    \
+    // blocks of one whole row run the kernel without segment code
+#define LBM_STEP(BCT)                                         \
+    do {                                                      \
+        if (whole_row_blocks(a)) LBM_STEP_W(BCT, true);       \
+        else LBM_STEP_W(BCT, false);                          \
     } while (0)
     if (bc == kBB) LBM_STEP(kBB);
     else if (bc == kWFB) LBM_STEP(kWFB);
