@@ -203,6 +203,19 @@ int lbm_wall_shear(lbm_ctx* ctx, double* tau_x, double* tau_z, double* u_tau, do
  * lo < hi, else LBM_E_ARG.  Synchronises. */
 int lbm_wall_yplus_pdf(lbm_ctx* ctx, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std);
 
+/* Mass check of the wall correction (Appendix B, Eq. B-1): for every wall cell
+ * the sum of the 19 populations after the WFB correction (Eq. 14) the next
+ * step would make, minus the sum before it, as the step kernel computes them
+ * (its own precision: FP64 for the FP64 store, FP32 otherwise; summed in
+ * direction order over the deviations h_a = f_a - w_a the kernel holds, so the
+ * weights cancel exactly).  In exact arithmetic it is zero; the value is the
+ * round-off of the four corrected populations.  dsum and rho (either may be
+ * NULL, not both) are host arrays of 2 * nx * nz doubles, layout [w][z][x]
+ * (w = 0 bottom, 1 top); rho is the cell's density before the correction, so
+ * that the mean population is rho / 19.  Zeros for bounce-back and free-slip
+ * walls, whose reflections only permute.  Synchronises. */
+int lbm_wall_mass_change(lbm_ctx* ctx, double* dsum, double* rho);
+
 /* Plane statistics (Sec. 3.1 time and plane averages, Fig. 6 moments),
  * accumulated in FP64 on sampled steps from the velocity each sampled step
  * computes.  lbm_stats_sums: out[y][8] = sums of ux, uy, uz, ux^2, uy^2, uz^2,

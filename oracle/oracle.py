@@ -236,6 +236,47 @@ class Oracle:
             raise RuntimeError("oracle wall failed: %d" % st)
         return tuple(o.reshape(2, self.params.nz, self.params.nx) for o in outs)
 
+    def wall_mass_change(self):
+        """Appendix B, Eq. B-1, per wall cell: the sum of the 19 populations after
+        the WFB collision (Eq. 14) of the next step minus the sum before it, in
+        FP64 over the full populations f, and the density before it.  The gather
+        is the first-layer one of the halfway walls: in-domain populations from
+        the neighbour, the wall-normal ones bounced back in place, the tangential
+        diagonals mirrored (bounce-back walls: all bounced back).  Returns
+        (dsum, rho), each [2, nz, nx], bottom wall first."""
+        nx, ny, nz = self.params.nx, self.params.ny, self.params.nz
+        bc = self.params.bc
+        e, _, opp, mir = tables()
+        f0 = self.state()
+        dsum = np.zeros((2, nz, nx))
+        rho = np.zeros((2, nz, nx))
+        for wall, y in ((0, 0), (1, ny - 1)):
+            for z in range(nz):
+                for x in range(nx):
+                    f = np.empty(Q)
+                    for a in range(Q):
+                        sy = y - e[a, 1]
+                        if 0 <= sy < ny:
+                            f[a] = f0[a, (z - e[a, 2]) % nz, sy, (x - e[a, 0]) % nx]
+                        elif bc == BB or (e[a, 0] == 0 and e[a, 2] == 0):
+                            f[a] = f0[opp[a], z, y, x]
+                        else:
+                            f[a] = f0[mir[a], (z - e[a, 2]) % nz, y, (x - e[a, 0]) % nx]
+                    g = f
+                    if bc == WFB:
+                        g, _, st, _ = wfb_cell(self.params, wall, f)
+                        if st != OK:
+                            raise RuntimeError("oracle WFB failed: %d" % st)
+                    s0 = 0.0
+                    for a in range(Q):
+                        s0 += f[a]
+                    s1 = 0.0
+                    for a in range(Q):
+                        s1 += g[a]
+                    dsum[wall, z, x] = s1 - s0
+                    rho[wall, z, x] = s0
+        return dsum, rho
+
     def stats_sums(self):
         out = np.zeros(8 * self.params.ny)
         ns = C.c_int64(0)

@@ -210,6 +210,15 @@ class Channel:
                                               L.dptr(ms)))
         return counts, np.linspace(lo, hi, nbins + 1), ms[0], ms[1]
 
+    def wall_mass_change(self):
+        """Eq. B-1 per wall cell: (change of the population sum made by the WFB
+        correction the next step would apply, density before it), each of
+        shape (2, nz, nx), bottom wall first."""
+        ds = np.empty(2 * self.nx * self.nz)
+        rho = np.empty(2 * self.nx * self.nz)
+        self._chk(self.lib.lbm_wall_mass_change(self._h, L.dptr(ds), L.dptr(rho)))
+        return ds.reshape(2, self.nz, self.nx), rho.reshape(2, self.nz, self.nx)
+
     def stats_reset(self):
         self._chk(self.lib.lbm_stats_reset(self._h))
 

@@ -868,7 +868,8 @@ int lbm_steps_done(const lbm_ctx* c, int64_t* s)
     return LBM_OK;
 }
 
-static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* cells, double* out, int* iters)
+static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* cells, double* out, int* iters,
+                        double* dmass = nullptr)
 {
     int st = check_ready(c);
     if (st != LBM_OK) return st;
@@ -886,8 +887,11 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
     hipError_t e = hipSuccess;
     if (cells) e = hipMalloc((void**)&dcells, (size_t)chunk * sizeof(long long));
     if (e == hipSuccess && iters) e = hipMalloc((void**)&dit, (size_t)chunk * sizeof(int));
+    double* ddm = nullptr;
+    if (e == hipSuccess && dmass) e = hipMalloc((void**)&ddm, (size_t)chunk * 2 * sizeof(double));
     std::vector<double> result((size_t)count * 4);
     std::vector<int> itres(iters ? (size_t)count : 0);
+    std::vector<double> dmres(dmass ? (size_t)count * 2 : 0);
     for (long long first = 0; first < count && e == hipSuccess; first += chunk) {
         const long long cnt = std::min(chunk, count - first);
         ObsArgs a = obs_args(c);
@@ -897,6 +901,7 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
         a.count = cnt;
         a.out = tmp;
         a.iters = dit;
+        a.dmass = ddm;
         if (cells)
             e = hipMemcpyAsync(dcells, cells + first, (size_t)cnt * sizeof(long long), hipMemcpyHostToDevice,
                                c->stream);
@@ -907,14 +912,19 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
                                hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess && iters)
             e = hipMemcpyAsync(itres.data() + first, dit, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && dmass)
+            e = hipMemcpyAsync(dmres.data() + (size_t)first * 2, ddm, (size_t)cnt * 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     }
     (void)hipFree(tmp);
     if (dcells) (void)hipFree(dcells);
     if (dit) (void)hipFree(dit);
+    if (ddm) (void)hipFree(ddm);
     if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("observe: ") + hipGetErrorString(e));
     std::memcpy(out, result.data(), result.size() * sizeof(double));
     if (iters) std::memcpy(iters, itres.data(), itres.size() * sizeof(int));
+    if (dmass) std::memcpy(dmass, dmres.data(), dmres.size() * sizeof(double));
     return LBM_OK;
 }
 
@@ -957,6 +967,21 @@ int lbm_wall_shear(lbm_ctx* c, double* tx, double* tz, double* ut, double* U)
         if (tz) tz[i] = buf[4 * i + 1];
         if (ut) ut[i] = buf[4 * i + 2];
         if (U) U[i] = buf[4 * i + 3];
+    }
+    return LBM_OK;
+}
+
+int lbm_wall_mass_change(lbm_ctx* c, double* dsum, double* rho)
+{
+    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+    if (!dsum && !rho) return fail(c, LBM_E_ARG, "null argument");
+    const long long m = 2ll * c->nx * c->nz;
+    std::vector<double> buf((size_t)m * 4), dm((size_t)m * 2);
+    int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr, dm.data());
+    if (st != LBM_OK) return st;
+    for (long long i = 0; i < m; ++i) {
+        if (dsum) dsum[i] = dm[2 * i];
+        if (rho) rho[i] = dm[2 * i + 1];
     }
     return LBM_OK;
 }

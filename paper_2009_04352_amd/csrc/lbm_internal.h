@@ -120,6 +120,8 @@ struct ObsArgs {
     double* out;          // [count][4]: rho, ux, uy, uz      (mode 0)
                           // [count][4]: tau_x, tau_z, u_tau, U (mode 1, wall cells)
     int* iters;           // optional, mode 1: Newton iterations per wall cell
+    double* dmass;        // optional, mode 1: [count][2] = change of the population sum made
+                          // by the wall correction, rho before it (Eq. B-1)
     int mode;
 };
 

@@ -359,11 +359,22 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
     });
     WallRecord rec{0.0, 0.0, 0.0, 0.0};
     int iters = 0;
+    // Eq. B-1 per wall cell: the population sum after the wall correction minus
+    // the sum before, both summed in direction order in the step's own precision
+    // over the deviations h_a = f_a - w_a the step holds (the weights cancel)
+    R sum0 = R(0);
+    if (p.dmass) for_each_dir([&](auto A) { sum0 += f[decltype(A)::value]; });
     if (p.bc == kWFB && (bot || top)) {
         bool fail = false;
         rec = wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, iters,
                           fail);
         if (fail) iters = -iters;
+    }
+    if (p.dmass) {
+        R sum1 = R(0);
+        for_each_dir([&](auto A) { sum1 += f[decltype(A)::value]; });
+        p.dmass[2 * i] = (double)(sum1 - sum0);
+        p.dmass[2 * i + 1] = 1.0 + (double)sum0;
     }
     R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
     for_each_dir([&](auto A) {

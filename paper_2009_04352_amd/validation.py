@@ -46,11 +46,38 @@ def profile_metrics(mean_ux, u_tau, nu0, y1=1.0, kappa=0.41, B=5.5, split=100.0)
                 eps_all=eps(np.ones_like(buf)), b=b)
 
 
+def mass_check(ch, steps):
+    """Appendix B (Eq. B-1, Table B-1) over `steps` single steps of a channel:
+    before each step, the change of the population sum that its WFB correction
+    makes at every wall cell, from the device (the step's own arithmetic).
+    Returns the fraction of steps whose wall-averaged change (Eq. B-1, both
+    walls) is not zero and the largest |change| over the mean population
+    f_a = rho / 19 of the wall cells, and the same two figures per cell."""
+    hits = cell_hits = cells = 0
+    worst = cell_worst = 0.0
+    for _ in range(steps):
+        ds, rho = ch.wall_mass_change()
+        fbar = float(rho.mean()) / 19.0
+        df = float(ds.mean())
+        hits += df != 0.0
+        worst = max(worst, abs(df) / fbar)
+        cell_hits += int(np.count_nonzero(ds))
+        cells += ds.size
+        cell_worst = max(cell_worst, float(np.max(np.abs(ds) / (rho / 19.0))))
+        ch.step(1)
+    return dict(steps=steps, rate_nonzero=hits / max(steps, 1), max_over_fbar=worst,
+                cell_rate_nonzero=cell_hits / max(cells, 1), cell_max_over_fbar=cell_worst)
+
+
 def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, develop=400000, sample=400000,
-        stats_every=20, report_every=50000, out=sys.stderr):
+        stats_every=20, report_every=50000, pdf_bins=40, pdf_range=4.0, mass_steps=0, out=sys.stderr):
     """Develop the channel from its Spalding initial state, then sample the
     plane statistics every stats_every steps; progress lines every
-    report_every steps.  Returns the metrics with the run's parameters."""
+    report_every steps, at which the sampling phase also takes a snapshot of
+    the first-layer y+ distribution (pdf_bins bins over +-pdf_range standard
+    deviations).  With mass_steps > 0, the Appendix B mass check runs over
+    that many steps between the two phases.  Returns the metrics with the
+    run's parameters."""
     import torch
 
     from . import Channel
@@ -63,7 +90,13 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     T = (ny / 2.0) / p["u_tau"]            # D / u_tau in steps
     t0 = time.time()
     done = 0
+    pdf_counts, pdf_mean, pdf_std, pdf_snaps = None, 0.0, 0.0, 0
+    mass = None
     for phase, n in (("develop", develop), ("sample", sample)):
+        if phase == "sample" and mass_steps > 0:
+            mass = mass_check(ch, mass_steps)
+            done += mass_steps
+            print("[validation] mass check over %d steps: %s" % (mass_steps, mass), file=out, flush=True)
         if phase == "sample":
             ch.set_param(3, stats_every)   # LBM_P_STATS_EVERY
             ch.stats_reset()
@@ -77,12 +110,27 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
                   % (workload, store, bc, collision, done, done / T, time.time() - t0, st), file=out, flush=True)
             if st != 0:
                 return dict(status=st, first_bad_step=first, steps=done)
-    stats, nsamp = ch.stats()
-    m = profile_metrics(stats[:, 0], p["u_tau"], p["nu0"])
+            if phase == "sample":
+                # Fig. 7: first-layer y+ normalised per snapshot, counts summed over snapshots
+                c, edges, mu, sd = ch.wall_yplus_pdf(pdf_bins, -pdf_range, pdf_range)
+                pdf_counts = c if pdf_counts is None else pdf_counts + c
+                pdf_mean += mu
+                pdf_std += sd
+                pdf_snaps += 1
+    m, nsamp = {}, 0
+    if sample > 0:
+        stats, nsamp = ch.stats()
+        m = profile_metrics(stats[:, 0], p["u_tau"], p["nu0"])
     m.update(workload=workload, grid=[nx, ny, nz], store=store, bc=bc, collision=collision,
              van_driest_aplus=van_driest, re_tau=W.WORKLOADS[workload]["re_tau"], u_tau=p["u_tau"],
              develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
              seconds=time.time() - t0)
+    if mass is not None:
+        m.update(mass_check=mass)
+    if pdf_snaps:
+        m.update(yplus_pdf_counts=pdf_counts.tolist(), yplus_pdf_edges=np.linspace(-pdf_range, pdf_range,
+                 pdf_bins + 1).tolist(), yplus_mean=pdf_mean / pdf_snaps, yplus_std=pdf_std / pdf_snaps,
+                 yplus_snapshots=pdf_snaps)
     ch.close()
     torch.cuda.empty_cache()
     return m
@@ -98,8 +146,11 @@ def main():
     ap.add_argument("--develop", type=int, default=400000)
     ap.add_argument("--sample", type=int, default=400000)
     ap.add_argument("--stats-every", type=int, default=20)
+    ap.add_argument("--report-every", type=int, default=50000)
+    ap.add_argument("--mass-steps", type=int, default=0)
     a = ap.parse_args()
-    m = run(a.workload, a.store, a.bc, a.collision, a.van_driest, a.develop, a.sample, a.stats_every)
+    m = run(a.workload, a.store, a.bc, a.collision, a.van_driest, a.develop, a.sample, a.stats_every,
+            a.report_every, mass_steps=a.mass_steps)
     print(json.dumps(m))
 
 

@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 
 from paper_2009_04352_amd.channel import spalding_uplus
 from paper_2009_04352_amd.validation import profile_metrics
@@ -38,3 +39,36 @@ def test_halves_are_folded():
     skew = np.linspace(-1.0, 1.0, 128) * 1e-3 * u.max()     # antisymmetric: cancels in the fold
     m = profile_metrics(u + skew, u_tau, nu0)
     assert m["eps_all"] <= 1e-12
+
+
+def test_mass_check_aggregates_eq_b1():
+    """Eq. B-1 averages the per-cell change over every wall cell of both walls;
+    Table B-1 counts the steps whose average is not zero and takes the largest
+    |average| over the mean population rho / 19.  A stand-in channel hands out
+    known per-cell changes."""
+    from paper_2009_04352_amd import validation
+
+    class Fake:
+        def __init__(self):
+            self.k = 0
+            self.steps = 0
+
+        def wall_mass_change(self):
+            ds = np.zeros((2, 2, 3))
+            if self.k == 1:
+                ds[0, 0, 0], ds[1, 1, 2] = 3e-17, -1e-17   # average 2e-17 / 12
+            elif self.k == 2:
+                ds[0, 1, 1], ds[1, 0, 0] = 4e-17, -4e-17   # cancels: average zero
+            return ds, np.full((2, 2, 3), 0.95)
+
+        def step(self, n):
+            self.k += 1
+            self.steps += n
+
+    ch = Fake()
+    m = validation.mass_check(ch, 4)
+    assert ch.steps == 4 and m["steps"] == 4
+    assert m["rate_nonzero"] == 0.25                       # only the second step
+    assert m["max_over_fbar"] == pytest.approx((2e-17 / 12) / (0.95 / 19), rel=1e-12)
+    assert m["cell_rate_nonzero"] == 4 / 48
+    assert m["cell_max_over_fbar"] == pytest.approx(4e-17 / (0.95 / 19), rel=1e-12)
