@@ -281,7 +281,7 @@ constexpr int mrt_row(int k, int a)
     switch (k) {
         case 0: return 1;
         case 1: return 19 * e2 - 30;
-        case 2: return (21 * e2 * e2 - 53 * e2 + 24) / 2;   // even: 24, -8, 1 for |e|^2 = 0, 1, 2
+        case 2: return (21 * e2 * e2 - 53 * e2 + 24) / 2;   // 12, -4, 1 for |e|^2 = 0, 1, 2
         case 3: return ex;
         case 4: return (5 * e2 - 9) * ex;
         case 5: return ey;
@@ -309,6 +309,13 @@ constexpr int mrt_norm(int k)
 }
 
 static_assert(mrt_norm(1) == 2394 && mrt_norm(2) == 252 && mrt_norm(10) == 72 && mrt_norm(16) == 8, "basis norms");
+// entries the reduced moments of the collision below rely on
+static_assert(mrt_row(1, 0) == -30 && mrt_row(1, 1) == -11 && mrt_row(1, 7) == 8 && mrt_row(2, 0) == 12 &&
+              mrt_row(2, 1) == -4 && mrt_row(2, 7) == 1, "energy rows");
+static_assert(mrt_row(4, 1) == -4 && mrt_row(4, 7) == 1 && mrt_row(10, 1) == -4 && mrt_row(10, 3) == 2 &&
+              mrt_row(10, 7) == mrt_row(9, 7) && mrt_row(10, 11) == mrt_row(9, 11) && mrt_row(12, 3) == -2 &&
+              mrt_row(12, 5) == 2 && mrt_row(12, 7) == mrt_row(11, 7) && mrt_row(12, 9) == mrt_row(11, 9),
+              "heat-flux and fourth-order rows");
 
 // The non-hydrodynamic moments and the rate (index into MrtRates::s) each
 // relaxes at: energy, energy square, heat flux, fourth-order normal
@@ -407,23 +414,28 @@ __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx
     const R m3ux = R(-3) * ux;
     const R t0 = fmad(rho, -usq, drho);          // drho - rho * 1.5 u.u
 
-    // MRT: x_k = n_k + F_k / 2 of the non-hydrodynamic moments, from the
-    // pre-collision pairs.  Per pair (a, opp a) of the weight class w the
-    // sum and difference of g = f - f_eq + F / 2 are
-    //   s - w (2 t0 + 9 rho (e.u)^2 + 3 u_x Fx - 9 e_x (e.u) Fx),
-    //   d - 3 w (2 rho e.u - e_x Fx),
-    // and the rest population's is f0 - w0 (t0 + 1.5 u_x Fx).
+    // MRT: x_k = n_k + F_k / 2 of the non-hydrodynamic moments, i.e. the
+    // moments of g = f - f_eq + F / 2.  g carries no mass and no momentum, and
+    // its second moments are the non-equilibrium stress plus half of
+    // u F + F u (for F along x: u_x F_x on the xx entry, which enters below,
+    // and off-diagonal terms, which do not).  With
+    //   T = tr = p_xx + p_yy + p_zz + u_x F_x,
+    //   P9 = 3 (xx) - tr = 2 p_xx - p_yy - p_zz + 2 u_x F_x,  P11 = (yy) - (zz) = p_yy - p_zz,
+    // the sums gs and differences gd of g over the axis pairs 1, 3, 5 and
+    // the differences over the diagonal pairs, the rows reduce to
+    //   x1 = 19 T,  x2 = -(5.5 T + 10.5 (gs1 + gs3 + gs5)),
+    //   x4 = -5 gd1,  x6 = -5 gd3,  x8 = -5 gd5,
+    //   x10 = P9 - 6 gs1 + 3 (gs3 + gs5),  x12 = P11 + 3 (gs5 - gs3),
+    // and the third-order rows 16-18, which live on the diagonal pairs only.
+    // Per pair (a, opp a) of the weight class w,
+    //   gs = s - w (2 t0 + 9 rho (e.u)^2 + 3 u_x Fx - 9 e_x (e.u) Fx),
+    //   gd = d - 3 w (2 rho e.u - e_x Fx).
     R xk[10] = {};
     if constexpr (MRT) {
-        const R g0 = f[0] - weight<R>(0) * fmad(R(1.5) * ux, fx, t0);
+        R gs[kQ], gd[kQ];   // indexed like s and d
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
-            if constexpr (a == 0) {
-#pragma unroll
-                for (int i = 0; i < 10; ++i)
-                    if (kMrtNH[i] == 1 || kMrtNH[i] == 2 || kMrtNH[i] == 10 || kMrtNH[i] == 12)
-                        xk[i] = R(mrt_row(kMrtNH[i], 0)) * g0;
-            } else if constexpr (a % 2 == 1) {
+            if constexpr (a % 2 == 1) {
                 constexpr R w = weight<R>(a);
                 R eu = R(0);
                 if constexpr (kEx[a] == 1) eu = ux;
@@ -432,14 +444,30 @@ __device__ __forceinline__ Moments<R> collide(R (&f)[kQ], R tau0, R cs2_18, R fx
                 if constexpr (kEz[a] == 1) eu = (kEx[a] != 0 || kEy[a] != 0) ? eu + uz : uz;
                 if constexpr (kEz[a] == -1) eu = eu - uz;
                 const R ex_fx = (kEx[a] != 0) ? fx : R(0);
-                const R gs = s[a] - w * fmad(R(9) * rho * eu, eu, fmad(R(3) * ux, fx, fmad(R(-9) * eu, ex_fx, R(2) * t0)));
-                const R gd = d[a] - (R(3) * w) * fmad(R(2) * rho, eu, -ex_fx);
+                if constexpr (a <= 5)
+                    gs[a] = s[a] - w * fmad(R(9) * rho * eu, eu, fmad(R(3) * ux, fx, fmad(R(-9) * eu, ex_fx, R(2) * t0)));
+                gd[a] = d[a] - (R(3) * w) * fmad(R(2) * rho, eu, -ex_fx);
+            }
+        });
+        const R uxfx = ux * fx;
+        const R tr = ((pxx + pyy) + pzz) + uxfx;
+        const R p9 = fmad(R(2), pxx + uxfx, -(pyy + pzz));
+        const R p11 = pyy - pzz;
+        const R ax = (gs[1] + gs[3]) + gs[5];
+        xk[0] = R(19) * tr;
+        xk[1] = -fmad(R(5.5), tr, R(10.5) * ax);
+        xk[2] = R(-5) * gd[1];
+        xk[3] = R(-5) * gd[3];
+        xk[4] = R(-5) * gd[5];
+        xk[5] = fmad(R(-6), gs[1], fmad(R(3), gs[3] + gs[5], p9));
+        xk[6] = fmad(R(3), gs[5] - gs[3], p11);
+        for_each_dir([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            if constexpr (a % 2 == 1 && a >= 7) {
 #pragma unroll
-                for (int i = 0; i < 10; ++i) {
-                    const int k = kMrtNH[i];
-                    const int c = mrt_row(k, a);
-                    const bool even = (k == 1 || k == 2 || k == 10 || k == 12);
-                    if (c != 0) xk[i] = fmad(R(c), even ? gs : gd, xk[i]);
+                for (int i = 7; i < 10; ++i) {
+                    const int c = mrt_row(kMrtNH[i], a);
+                    if (c != 0) xk[i] = fmad(R(c), gd[a], xk[i]);
                 }
             }
         });
