@@ -154,6 +154,14 @@ int lbm_set_boundary(lbm_ctx* ctx, int bc);
  * counter 3 c + i from state `seed`.  Resets the step count to 0. */
 int lbm_init_spalding(lbm_ctx* ctx, double u_tau, double noise, uint64_t seed);
 
+/* Initial state from given moments: f = f_eq(rho, u) of Eq. 1 (second-order
+ * equilibrium) taken as post-collision populations, computed on the device
+ * and rounded to the store format.  rho: ncells doubles, u: [3][ncells]
+ * (u_x, u_y, u_z), both host arrays indexed c = x + nx (y + ny z).  Every
+ * rho must be positive and every value finite (else LBM_E_ARG, nothing
+ * written).  Resets the step count to 0.  Synchronises. */
+int lbm_init_moments(lbm_ctx* ctx, const double* rho, const double* u);
+
 /* Sets the state from host memory: h[a][c] = f*_a(c) - w_a, the post-collision
  * populations minus the weights, 19 * ncells doubles (rounded to the store
  * format).  Resets the step count to `steps`. Synchronises. */

@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbm_moments_cells": (C.c_int, [_vp, C.c_int64, _i64p, _dp]),
     "lbm_wall_shear": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm_wall_yplus_pdf": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, C.c_void_p, _dp]),
+    "lbm_init_moments": (C.c_int, [_vp, _dp, _dp]),
     "lbm_wall_mass_change": (C.c_int, [_vp, _dp, _dp]),
     "lbm_stats_reset": (C.c_int, [_vp]),
     "lbm_stats_sums": (C.c_int, [_vp, _dp, _i64p]),

@@ -148,6 +148,15 @@ class Channel:
     def init_spalding(self, u_tau, noise=0.05, seed=0):
         self._chk(self.lib.lbm_init_spalding(self._h, float(u_tau), float(noise), int(seed)))
 
+    def init_moments(self, rho, u):
+        """f = f_eq(rho, u) as the post-collision state of step 0; rho is
+        [nz, ny, nx] (or flat), u is [3, nz, ny, nx] (or [3, ncell])."""
+        rho = np.ascontiguousarray(rho, dtype=np.float64).reshape(-1)
+        u = np.ascontiguousarray(u, dtype=np.float64).reshape(-1)
+        if rho.size != self.ncell or u.size != 3 * self.ncell:
+            raise ValueError("rho must hold ncell values and u 3 * ncell")
+        self._chk(self.lib.lbm_init_moments(self._h, L.dptr(rho), L.dptr(u)))
+
     def set_state(self, h, steps=0):
         """h: [19, nz, ny, nx] (or flat) float64, post-collision f - w."""
         h = np.ascontiguousarray(h, dtype=np.float64).reshape(-1)

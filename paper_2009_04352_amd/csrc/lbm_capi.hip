@@ -680,6 +680,48 @@ static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t s
     return LBM_OK;
 }
 
+int lbm_init_moments(lbm_ctx* c, const double* rho, const double* u)
+{
+    if (!c || !rho || !u) return fail(c, LBM_E_ARG, "null argument");
+    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
+    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+    for (long long i = 0; i < c->n; ++i) {
+        const double r = rho[i], x = u[i], y = u[c->n + i], z = u[2 * c->n + i];
+        if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+            return fail(c, LBM_E_ARG, "need finite moments and rho > 0");
+    }
+    DeviceGuard dg(c->dev);
+    const long long chunk = std::min<long long>(c->n, 1ll << 24);
+    double* tmp = nullptr;
+    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 4 * sizeof(double)));
+    std::vector<double> stage((size_t)chunk * 4);
+    c->initialized = false;  // the layout is chosen afresh
+    c->brick = brick_for_tiles(c);
+    int st = LBM_OK;
+    for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
+        const long long cnt = std::min(chunk, c->n - first);
+        std::memcpy(stage.data(), rho + first, (size_t)cnt * sizeof(double));
+        for (int k = 0; k < 3; ++k)
+            std::memcpy(stage.data() + (size_t)(k + 1) * cnt, u + (size_t)k * c->n + first, (size_t)cnt * sizeof(double));
+        hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 4 * sizeof(double), hipMemcpyHostToDevice,
+                                      c->stream);
+        if (e == hipSuccess)
+            e = launch_init_moments(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("init_moments: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(tmp);
+    if (st != LBM_OK) return st;
+    c->steps = 0;
+    c->layout_s = 0;
+    c->layout_spec = (c->bc != kBB);
+    c->initialized = true;
+    st = reset_flags(c);
+    if (st != LBM_OK) return st;
+    LBM_HIP(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
 int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
 {
     if (!c || !in) return fail(c, LBM_E_ARG, "null argument");

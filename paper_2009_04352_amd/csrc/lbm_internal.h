@@ -141,6 +141,8 @@ hipError_t launch_init_spalding(int store, void* h, long long n, int nx, int ny,
                                 const double* profile, double noise, unsigned long long seed, hipStream_t s);
 hipError_t launch_set_state(int store, void* h, long long n, int nx, int ny, int nz, int brick, long long first,
                             long long count, const double* in, hipStream_t s);
+hipError_t launch_init_moments(int store, void* h, long long n, int nx, int ny, int nz, int brick, long long first,
+                               long long count, const double* in, hipStream_t s);
 hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int brick, int layout_s,
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
                             hipStream_t s);

@@ -235,6 +235,29 @@ __global__ __launch_bounds__(256) void k_init(void* hv, long long n, int nx, int
     });
 }
 
+// in[k][i], k = rho, u_x, u_y, u_z of cell c = first + i: the post-collision
+// state f*(0) = f_eq(rho, u) of Eq. 1, stored as h = f - w in layout P.
+template <typename S>
+__global__ __launch_bounds__(256) void k_init_moments(void* hv, long long n, int nx, int ny, int nz, int brick,
+                                                      long long first, long long count, const double* __restrict__ in)
+{
+    using T = typename S::T;
+    T* h = (T*)hv;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const long long c = first + i;
+    const int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((long long)nx * ny));
+    const long long m = cell_index(x, y, z, nx, ny, nz, brick);
+    const double rho = in[i], ux = in[count + i], uy = in[2 * count + i], uz = in[3 * count + i];
+    const double usq = 1.5 * (ux * ux + uy * uy + uz * uz);
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        const double eu = kEx[a] * ux + kEy[a] * uy + kEz[a] * uz;
+        const double heq = weight<double>(a) * ((rho - 1.0) + rho * (3.0 * eu + 4.5 * eu * eu - usq));
+        h[(long long)opp(a) * n + m] = S::from_double(heq);
+    });
+}
+
 // ------------------------------------------------- state in canonical form
 
 // in[a][i]: h of the post-collision f*_a(c), c = first + i; written in layout P.
@@ -511,6 +534,7 @@ static hipError_t dispatch_store(int store, dim3 g, dim3 b, hipStream_t s, Args.
 
 template <typename S> struct InitK { static constexpr auto fn = k_init<S>; };
 template <typename S> struct SetK { static constexpr auto fn = k_set_state<S>; };
+template <typename S> struct InitMK { static constexpr auto fn = k_init_moments<S>; };
 template <typename S> struct GetK { static constexpr auto fn = k_get_state<S>; };
 template <typename S> struct ObsK { static constexpr auto fn = k_observe<S>; };
 template <typename S> struct RelK { static constexpr auto fn = k_relayout<S>; };
@@ -532,6 +556,14 @@ hipError_t launch_set_state(int store, void* h, long long n, int nx, int ny, int
     if (count <= 0) return hipSuccess;
     return dispatch_store<SetK>(store, blocks_for(count, 256), dim3(256), s, h, n, nx, ny, nz, brick, first, count,
                                 in);
+}
+
+hipError_t launch_init_moments(int store, void* h, long long n, int nx, int ny, int nz, int brick, long long first,
+                               long long count, const double* in, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    return dispatch_store<InitMK>(store, blocks_for(count, 256), dim3(256), s, h, n, nx, ny, nz, brick, first, count,
+                                  in);
 }
 
 hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int brick, int layout_s,
