@@ -8,6 +8,9 @@ channel on the GPU (develop, then sample) and returns the metrics:
 
 python -m paper_2009_04352_amd.validation --workload c3 --store f16 --bc wfb \
     --collision mrt --van-driest 26 --develop 400000 --sample 400000
+
+The workload is a benchmark channel (c3, ...) or one of Table 1's cases
+(A20, A40, B40, B80).
 """
 import argparse
 import json
@@ -84,8 +87,9 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     from . import workloads as W
     p = W.params(workload)
     nx, ny, nz = p["grid"]
+    tiles = W.launch_tiles(workload, store, collision) if workload in W.LAUNCH_TILES else None
     ch = Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
-                 tiles=W.launch_tiles(workload, store, collision), collision=collision, van_driest=van_driest)
+                 tiles=tiles, collision=collision, van_driest=van_driest)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     T = (ny / 2.0) / p["u_tau"]            # D / u_tau in steps
     t0 = time.time()
@@ -122,7 +126,7 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
         stats, nsamp = ch.stats()
         m = profile_metrics(stats[:, 0], p["u_tau"], p["nu0"])
     m.update(workload=workload, grid=[nx, ny, nz], store=store, bc=bc, collision=collision,
-             van_driest_aplus=van_driest, re_tau=W.WORKLOADS[workload]["re_tau"], u_tau=p["u_tau"],
+             van_driest_aplus=van_driest, re_tau=W.case(workload)["re_tau"], u_tau=p["u_tau"],
              develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
              seconds=time.time() - t0)
     if mass is not None:

@@ -39,6 +39,21 @@ WORKLOADS = {
                tau=None, desc="large channel 2048x512x1024 (1.07B cells), Re_tau 2003, WFB, 500 steps"),
 }
 
+# The paper's own cases (Table 1): grid, Re_tau, Ma_LB; used by the wall-law
+# validation runs, not by the benchmark.
+TABLE1 = {
+    "A20": dict(grid=(128, 40, 64), re_tau=640.0, ma=0.060, tau=None),
+    "A40": dict(grid=(256, 80, 128), re_tau=640.0, ma=0.060, tau=None),
+    "B40": dict(grid=(256, 80, 128), re_tau=2003.0, ma=0.069, tau=None),
+    "B80": dict(grid=(512, 160, 256), re_tau=2003.0, ma=0.069, tau=None),
+}
+
+
+def case(name):
+    """The workload or Table 1 case of that name."""
+    return WORKLOADS[name] if name in WORKLOADS else TABLE1[name]
+
+
 # the batched ensemble (see ensemble()): 64 channels, FP32 store, 1000 steps
 ENSEMBLE = dict(n=64, store="f32", steps=1000,
                 desc="64 independent channels, grids {32,64,128}x{16,32,64}x{16,32,64}, Re_tau in [300,2003), "
@@ -75,7 +90,7 @@ def ensemble(n=64, ma=0.060):
 
 def params(name, named_tau=False):
     """Lattice parameters of a workload: dict(grid, tau0, fx, u_tau, ...)."""
-    w = WORKLOADS[name]
+    w = case(name)
     nx, ny, nz = w["grid"]
     p = rule_m(ny, w["re_tau"], w["ma"])
     if named_tau:

@@ -72,3 +72,19 @@ def test_mass_check_aggregates_eq_b1():
     assert m["max_over_fbar"] == pytest.approx((2e-17 / 12) / (0.95 / 19), rel=1e-12)
     assert m["cell_rate_nonzero"] == 4 / 48
     assert m["cell_max_over_fbar"] == pytest.approx(4e-17 / (0.95 / 19), rel=1e-12)
+
+
+def test_table1_cases_match_the_paper():
+    """The validation cases are Table 1's: grid, Re_tau, Ma_LB, D = ny / 2 equal
+    to the resolution column, and the first-layer y+ of the Rule-M parameters
+    equal to the printed one (to the table's rounding)."""
+    import golden_io
+    from paper_2009_04352_amd import workloads as W
+    rows = golden_io.table1()
+    assert sorted(r["case"] for r in rows) == sorted(W.TABLE1)
+    for r in rows:
+        c = W.TABLE1[r["case"]]
+        assert c["grid"] == (r["nx"], r["ny"], r["nz"]) and c["re_tau"] == r["re_tau"] and c["ma"] == r["ma"]
+        assert r["ny"] // 2 == r["res"]
+        p = W.params(r["case"])
+        assert abs(p["yplus1"] - r["yplus"]) <= 0.5
