@@ -99,7 +99,9 @@ extern "C" {
 #define LBM_P_MRT_S_E 19      /* MRT rate of the energy moment, in (0, 2); default 1.19 */
 #define LBM_P_MRT_S_EPS 20    /* ... of the energy-square moment; default 1.4 */
 #define LBM_P_MRT_S_Q 21      /* ... of the three heat-flux moments; default 1.2 */
-#define LBM_P_MRT_S_PI 22     /* ... of the two fourth-order normal-stress moments; default 1.4 */
+#define LBM_P_MRT_S_PI 22     /* ... of the two fourth-order normal-stress moments; default 1.99, near the
+                               * shear rate of a channel at tau0 -> 1/2: with d'Humieres' 1.4 the channel's
+                               * mean profile falls well below the wall law of Tables 2-3 */
 #define LBM_P_MRT_S_M 23      /* ... of the three third-order moments; default 1.98 */
 #define LBM_P_VD_APLUS 24     /* van Driest damping of the Smagorinsky constant (Sec. 3.1): Cs (1 - exp(-y+/A+))
                                * with y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1; A+ >= 0, 0 = no damping

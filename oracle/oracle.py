@@ -14,10 +14,11 @@ from . import build as _build
 Q = 19
 BB, WFB, FREESLIP = 0, 1, 2
 BGK, MRT = 0, 1
-# MRT rates of the non-hydrodynamic moments suggested by d'Humieres et al.
-# (2002) for D3Q19: energy, energy square, heat flux, fourth-order normal
-# stresses, third-order m moments
-MRT_RATES = dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.4, s_m=1.98)
+# MRT rates of the non-hydrodynamic moments for D3Q19: energy, energy square,
+# heat flux and third-order m moments as suggested by d'Humieres et al. (2002);
+# the fourth-order normal stresses near the shear rate (1.99), the value with
+# which the channel runs reproduce the wall-law figures of Tables 2 and 3
+MRT_RATES = dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.99, s_m=1.98)
 OK, E_ARG, E_NONFINITE, E_NEWTON = 0, -1, -5, -6
 
 

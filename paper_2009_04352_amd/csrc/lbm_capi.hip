@@ -49,7 +49,9 @@ struct lbm_ctx {
     int brick = 0;               // rows per brick in use; fixed while the state is initialised
     int odd_rows = 1;            // odd step by rows: 0 never, 1 when rows are longer than a block, 2 whenever possible
     int coll = kBGK;             // collision: kBGK or kMRT
-    double mrt_s[5] = {1.19, 1.4, 1.2, 1.4, 1.98};  // MRT rates (d'Humieres et al. 2002): e, epsilon, q, pi, m
+    // MRT rates e, epsilon, q, pi, m: d'Humieres et al. (2002) for e, epsilon, q, m; the fourth-order
+    // normal stresses near the shear rate (the value with which the wall-law runs match Tables 2-3)
+    double mrt_s[5] = {1.19, 1.4, 1.2, 1.99, 1.98};
     double vd_aplus = 0.0;       // van Driest A+; 0 = no damping
     double vd_utau = 0.0;        // friction velocity of the damping's y+; 0 = sqrt(|Fx| ny / 2)
     int spread = -1;             // launch order: log2 of the tile chunks that cycle through the bricks; 0 = memory

@@ -73,12 +73,15 @@ def mass_check(ch, steps):
 
 
 def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, develop=400000, sample=400000,
-        stats_every=20, report_every=50000, pdf_bins=40, pdf_range=4.0, mass_steps=0, out=sys.stderr):
+        stats_every=20, report_every=50000, pdf_bins=40, pdf_range=4.0, mass_steps=0, mrt_rates=None,
+        out=sys.stderr):
     """Develop the channel from its Spalding initial state, then sample the
     plane statistics every stats_every steps; progress lines every
     report_every steps, at which the sampling phase also takes a snapshot of
     the first-layer y+ distribution (pdf_bins bins over +-pdf_range standard
-    deviations).  With mass_steps > 0, the Appendix B mass check runs over
+    deviations).  mrt_rates: dict of MRT rates overriding the defaults
+    (keys s_e, s_eps, s_q, s_pi, s_m).  With mass_steps > 0, the Appendix B
+    mass check runs over
     that many steps between the two phases.  Returns the metrics with the
     run's parameters."""
     import torch
@@ -89,7 +92,7 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     nx, ny, nz = p["grid"]
     tiles = W.launch_tiles(workload, store, collision) if workload in W.LAUNCH_TILES else None
     ch = Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
-                 tiles=tiles, collision=collision, van_driest=van_driest)
+                 tiles=tiles, collision=collision, van_driest=van_driest, mrt_rates=mrt_rates)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     T = (ny / 2.0) / p["u_tau"]            # D / u_tau in steps
     t0 = time.time()
@@ -152,9 +155,13 @@ def main():
     ap.add_argument("--stats-every", type=int, default=20)
     ap.add_argument("--report-every", type=int, default=50000)
     ap.add_argument("--mass-steps", type=int, default=0)
+    ap.add_argument("--mrt-rates", default="", help="e.g. s_e=1.19,s_q=1.2 (MRT rates to override)")
     a = ap.parse_args()
+    rates = {k: float(v) for k, v in (kv.split("=") for kv in a.mrt_rates.split(",") if kv)} or None
     m = run(a.workload, a.store, a.bc, a.collision, a.van_driest, a.develop, a.sample, a.stats_every,
-            a.report_every, mass_steps=a.mass_steps)
+            a.report_every, mass_steps=a.mass_steps, mrt_rates=rates)
+    if rates:
+        m.update(mrt_rates=rates)
     print(json.dumps(m))
 
 

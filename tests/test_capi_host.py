@@ -141,7 +141,7 @@ def test_collision_and_damping_parameters(L):
         get = lambda k: (lib.lbm_get_param(h, k, C.byref(v)), v.value)[1]
         assert get(L.LBM_P_COLLISION) == L.LBM_BGK
         keys = (L.LBM_P_MRT_S_E, L.LBM_P_MRT_S_EPS, L.LBM_P_MRT_S_Q, L.LBM_P_MRT_S_PI, L.LBM_P_MRT_S_M)
-        assert [get(k) for k in keys] == [1.19, 1.4, 1.2, 1.4, 1.98]
+        assert [get(k) for k in keys] == [1.19, 1.4, 1.2, 1.99, 1.98]
         assert get(L.LBM_P_VD_APLUS) == 0.0 and get(L.LBM_P_VD_UTAU) == 0.0
         assert lib.lbm_set_param(h, L.LBM_P_COLLISION, L.LBM_MRT) == 0 and get(L.LBM_P_COLLISION) == L.LBM_MRT
         assert lib.lbm_set_param(h, L.LBM_P_COLLISION, 2) == L.LBM_E_ARG
