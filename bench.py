@@ -1,21 +1,26 @@
 """Benchmark: MLUPS and HBM-roofline fraction of the fused WFB LBM-LES step on
-one MI355X, FP16 / FP32 / BF16 stores against the plain FP64 store, with the
-accuracy of each reduced store stated against the FP64 GPU run.
+one MI355X: the plain FP64 store (the headline) and the FP32 / FP16 / BF16
+stores beside it, each reduced store with its accuracy stated against the FP64
+GPU run after the workload's own step count.
 
 Workloads (synthetic inputs generated on the device, see workloads.py):
-  c3 (default)  512 x 128 x 256 channel (16.8M cells), Re_tau 2003, WFB walls,
-                Smagorinsky Cs = 0.1, Spalding profile + 5 % seeded noise;
-  c5            2048 x 512 x 1024 channel (1.07B cells), same physics;
+  c5 (default)  2048 x 512 x 1024 channel (1.07G cells), Re_tau 2003, WFB
+                walls, Smagorinsky Cs = 0.1, Spalding profile + 5 % seeded
+                noise; accuracy after 500 steps;
+  c3            512 x 128 x 256 channel (16.8M cells), same physics; 2,000 steps;
+  c2            128 x 64 x 64 channel, Re_tau 640, FP32 with WFB and with
+                bounce-back walls; 10,000 steps (40 MB of populations: it lives
+                in the 256 MB Infinity Cache, so its "HBM" figures are flagged
+                as cache-resident);
   c4            64 independent channels in one launch per step (FP32 store).
 One step is one launch of the fused kernel over every cell (odd and even AA
-kernels alternate).  Timing: W untimed warm-up steps (default 200: in a
-fresh process the first ~100 odd steps of the 2-byte stores run up to 30 %
-slower, on MI355X, than the steady state a long run sees), then K steps
-bracketed by synchronisation, a HIP event recorded on the library's stream
-after every launch (per-kernel durations for the roofline).  Prints one
-JSON line.
+kernels alternate).  Per store: W untimed warm-up steps, then K steps
+bracketed by synchronisation with a HIP event recorded on the library's stream
+after every launch (per-kernel durations for the roofline), then untimed
+steps up to the workload's step count, after which the velocity field (on the
+device) is compared with the FP64 run's.  Prints one JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c4|c5]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c3|c2|c4]
                 [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
                 [--collision bgk|mrt] [--van-driest A+]
 The headline line is the BGK step (the default); --collision mrt with
@@ -35,8 +40,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS and % of HBM roofline at 1 GPU, FP16/FP32-store vs FP64, at stated ε_u+"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
-HEADLINE = "f16"
-FULL_FIELD_LIMIT = 64 << 20    # cells; larger grids compare sampled cells
+DTYPE = {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}   # arithmetic of each store
+# per workload: headline store, default timed steps and warm-up
+DEFAULTS = {"c5": ("f64", 100, 20), "c3": ("f64", 1000, 200), "c2": ("f32", 2000, 200), "c4": ("f32", 1000, 100)}
+CACHE_RESIDENT = {"c2"}        # populations fit the 256 MB Infinity Cache
 
 
 def kernel_source_hash():
@@ -66,9 +73,11 @@ def measured_traffic(workload, store, kernel):
 
 def timed_steps(torch, stepper, stream, steps, warmup, first_step):
     """Runs warm-up steps, then `steps` timed steps with an event after each
-    launch; returns (total ms, mean odd-kernel ms, mean even-kernel ms)."""
+    launch; returns (total ms, mean odd-kernel ms, mean even-kernel ms, the
+    per-step times in ms)."""
     import numpy as np
-    stepper(warmup)
+    if warmup:
+        stepper(warmup)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
@@ -82,46 +91,71 @@ def timed_steps(torch, stepper, stream, steps, warmup, first_step):
     t_index = first_step + warmup + np.arange(steps)      # 1-based step numbers; odd ones run the odd kernel
     odd = float(per[t_index % 2 == 1].mean()) if np.any(t_index % 2 == 1) else float("nan")
     even = float(per[t_index % 2 == 0].mean()) if np.any(t_index % 2 == 0) else float("nan")
-    return total, odd, even
+    return total, odd, even, per
 
 
 def collision_kw(args):
     return dict(collision=args.collision, van_driest=args.van_driest)
 
 
-def run_store(P, W, name, store, steps, warmup, coll):
+def step_profile(per, first_step):
+    """Per-step times summarised: the first 8 timed steps and the mean of each
+    tenth of the timed region, by kernel (a cold start shows as a trend)."""
     import numpy as np
+    idx = first_step + np.arange(len(per))
+    out = {"first_ms": [round(float(v), 5) for v in per[:8]]}
+    for name, sel in (("odd", idx % 2 == 1), ("even", idx % 2 == 0)):
+        v = per[sel]
+        if len(v) >= 10:
+            out[name + "_tenths_ms"] = [round(float(c.mean()), 5) for c in np.array_split(v, 10)]
+    return out
+
+
+def run_store(P, W, name, store, bc, steps, warmup, coll, acc_steps, ref):
+    """Times one store on one workload, then continues (untimed) to the
+    workload's own step count and compares the velocity field on the device
+    with the FP64 run's (ref; None for the FP64 run itself, whose fields it
+    returns)."""
     import torch
     p = W.params(name)
     nx, ny, nz = p["grid"]
     n = nx * ny * nz
-    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
+    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
                    tiles=W.launch_tiles(name, store, coll["collision"]), graph_steps=0, **coll)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
-    total_ms, odd_ms, even_ms = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
-    status, first_bad = ch.sync()
+    total_ms, odd_ms, even_ms, per = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
     out = dict(ms_per_step=total_ms / steps, mlups=n * steps / (total_ms * 1e-3) / 1e6,
-               odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status), first_bad_step=int(first_bad),
-               odd_by_rows=int(ch.get_param(17)))
-    acc = None
+               odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, odd_by_rows=int(ch.get_param(17)),
+               steps_profile=step_profile(per, 1 + warmup))
+    done = warmup + steps
+    # the accuracy figures belong to the workload's own step count, whatever K and W were
+    ch.set_param(8, 32)                      # LBM_P_GRAPH_STEPS: the untimed remainder runs in graphs
+    if done > acc_steps:
+        ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
+        done = 0
+    ch.step(acc_steps - done)
+    status, first_bad = ch.sync()
+    out.update(status=int(status), first_bad_step=int(first_bad), accuracy_steps=acc_steps)
+    fields = None
     if status == 0:
-        cells = W.sample_cells(p["grid"], 200000, seed=7)
-        if n <= FULL_FIELD_LIMIT:
-            rho, ux, uy, uz = ch.moments()
-            fields = (ux, uy, uz)
-        else:
-            m = ch.moments_cells(cells)
-            fields = (m[:, 1], m[:, 2], m[:, 3])
-        # plane-averaged streamwise profile: one further (untimed) step sampled into the FP64 statistics
-        ch.set_param(3, 1)
-        ch.stats_reset()
-        ch.step(1)
-        st, _ = ch.stats()
-        acc = dict(fields=fields, profile=st[:, 0])
+        fields = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+        ch.moments_device(None, *fields)
+        torch.cuda.synchronize()
+        # plane-averaged streamwise velocity per layer (FP64)
+        out["profile"] = fields[0].view(nz, ny, nx).mean(dim=(0, 2)).cpu().numpy()
     ch.close()
     del ch
     torch.cuda.empty_cache()
-    return out, acc, p
+    if fields is not None and ref is not None:
+        du = 0.0
+        for a, b in zip(fields, ref["fields"]):
+            du = max(du, float((a - b).abs_().max()))
+        prof, prof_ref = out["profile"] / p["u_tau"], ref["profile"] / p["u_tau"]
+        out["max_du_over_utau_vs_f64"] = du / p["u_tau"]
+        out["eps_uplus_vs_f64"] = float(math.sqrt(((prof - prof_ref) ** 2).sum() / (prof_ref ** 2).sum()))
+        fields = None
+        torch.cuda.empty_cache()
+    return out, fields, p
 
 
 def copy_probe_gbs(P, nbytes=4 << 30, reps=10):
@@ -144,9 +178,27 @@ def copy_probe_gbs(P, nbytes=4 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(W, name, coll, budget_s=20.0):
+def _oracle_rate(O, p, grid, okw, budget_s):
+    """MLUPS of the oracle on a channel of this grid from the workload's initial
+    state: one untimed step, then as many steps as fit the budget."""
+    nx, ny, nz = grid
+    o = O.Oracle(O.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=O.WFB, **okw))
+    o.init_spalding(p["u_tau"], p["noise"], p["seed"])
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    k = max(1, min(200, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t0
+    del o
+    return nx * ny * nz * k / dt / 1e6, k, dt
+
+
+def cpu_baseline(W, name, coll, budget_s=20.0, budget_1core_s=8.0):
     """The FP64 CPU oracle on this host's cores: a bounded sample of the same
-    workload (the same grid from the same initial state, a few steps)."""
+    workload (the same grid from the same initial state, or a z-slab of it when
+    the grid does not fit the host twice), on all cores and on one core."""
     from oracle import oracle as O
     okw = dict(collision=O.MRT if coll["collision"] == "mrt" else O.BGK, vd_aplus=coll["van_driest"])
     if name == "c4":
@@ -167,38 +219,39 @@ def cpu_baseline(W, name, coll, budget_s=20.0):
         for o in o_list:
             o.step(k)
         dt = time.perf_counter() - t0
-        sample = "the 64 ensemble channels, FP64, %d steps each after one untimed step (%.1f s)" % (k, dt)
-    else:
-        p = W.params(name)
-        nx, ny, nz = p["grid"]
-        if nx * ny * nz > FULL_FIELD_LIMIT:   # a z-slab of the large channel fits the host
-            nz = 16
-        cells = nx * ny * nz
-        o = O.Oracle(O.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=O.WFB, **okw))
-        o.init_spalding(p["u_tau"], p["noise"], p["seed"])
-        t0 = time.perf_counter()
-        o.step(1)
-        t1 = time.perf_counter() - t0
-        k = max(1, min(200, int(budget_s / max(t1, 1e-6))))
-        t0 = time.perf_counter()
-        o.step(k)
-        dt = time.perf_counter() - t0
-        sample = "%dx%dx%d channel, WFB, FP64, %d steps after one untimed step (%.1f s)" % (nx, ny, nz, k, dt)
-        del o
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=cells * k / dt / 1e6, unit="MLUPS", cores=cores, kind="oracle", sample=sample)
+        return dict(value=cells * k / dt / 1e6, unit="MLUPS", cores=O.threads(), kind="oracle",
+                    sample="the 64 ensemble channels, FP64, %d steps each after one untimed step (%.1f s)" % (k, dt))
+    p = W.params(name)
+    nx, ny, nz = p["grid"]
+    slab = nx * ny * nz > (64 << 20)          # a z-slab of the large channel fits the host
+    grid = (nx, ny, 16 if slab else nz)
+    cores = O.threads()
+    rate, k, dt = _oracle_rate(O, p, grid, okw, budget_s)
+    grid1 = (nx, ny, 2 if slab else nz)
+    O.set_threads(1)
+    try:
+        rate1, k1, dt1 = _oracle_rate(O, p, grid1, okw, budget_1core_s)
+    finally:
+        O.set_threads(cores)
+    sample = ("%dx%dx%d channel%s, WFB, FP64, %d steps after one untimed step (%.1f s) on %d threads; "
+              "one core: %dx%dx%d, %d steps (%.1f s)" % (grid + (" (z-slab of the workload)" if slab else "",
+                                                                 k, dt, cores) + grid1 + (k1, dt1)))
+    return dict(value=rate, unit="MLUPS", cores=cores, kind="oracle", sample=sample, value_1core=rate1)
 
 
 def roofline(per, kernel_key, n_cells, workload, collision="bgk"):
     kern = per["dominant_kernel"]
     # the committed counter summaries were taken with the BGK kernels
     traffic = measured_traffic(workload, kernel_key, kern) if collision == "bgk" else None
-    return dict(bound="hbm", achieved=per["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=per["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
-                kernel=(("k_odd_rows odd (one wavefront per row; pull/push with wall reflections)"
-                         if per.get("odd_by_rows") else "k_step odd (pull/push with wall reflections)")
-                        if kern == "odd" else "k_step even (local)"),
-                kernel_ms=per[kern + "_kernel_ms"], algorithmic_bytes_per_launch=per["bytes_per_cell"] * n_cells)
+    r = dict(bound="hbm", achieved=per["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+             frac=per["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
+             kernel=(("k_odd_rows odd (one wavefront per row; pull/push with wall reflections)"
+                      if per.get("odd_by_rows") else "k_step odd (pull/push with wall reflections)")
+                     if kern == "odd" else "k_step even (local)"),
+             kernel_ms=per[kern + "_kernel_ms"], algorithmic_bytes_per_launch=per["bytes_per_cell"] * n_cells)
+    if workload in CACHE_RESIDENT:
+        r["cache_resident"] = True
+    return r
 
 
 def store_record(r, s, n, copy_gbs):
@@ -209,45 +262,60 @@ def store_record(r, s, n, copy_gbs):
              odd_kernel_ms=r["odd_kernel_ms"], even_kernel_ms=r["even_kernel_ms"], dominant_kernel=kern,
              kernel_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS, odd_by_rows=r.get("odd_by_rows", 0),
              step_gbs=bytes_cell * n / (r["ms_per_step"] * 1e-3) / 1e9, status=r["status"])
+    for k in ("first_bad_step", "accuracy_steps", "max_du_over_utau_vs_f64", "eps_uplus_vs_f64", "steps_profile"):
+        if k in r:
+            d[k] = r[k]
     if copy_gbs:
         d["copy_frac"] = gbs / copy_gbs
     return d
 
 
 def bench_single(P, W, args, copy_gbs):
-    import numpy as np
     stores = args.stores.split(",")
     if "f64" not in stores:
         stores = ["f64"] + stores
+    stores = ["f64"] + [s for s in stores if s != "f64"]     # the reference runs first
     wl = W.WORKLOADS[args.workload]
     nx, ny, nz = wl["grid"]
     n = nx * ny * nz
-    res, acc = {}, {}
-    for s in stores:
-        r, a, p = run_store(P, W, args.workload, s, args.steps, args.warmup, collision_kw(args))
-        print("[bench] %s: %.1f MLUPS, odd %.4f ms, even %.4f ms, status %d"
-              % (s, r["mlups"], r["odd_kernel_ms"], r["even_kernel_ms"], r["status"]), file=sys.stderr, flush=True)
-        res[s], acc[s] = r, a
-    u_tau = p["u_tau"]
-    ref = acc.get("f64")
-    per_store = {}
-    for s in stores:
-        d = store_record(res[s], s, n, copy_gbs)
-        if ref is not None and acc[s] is not None:
-            du = max(float(np.abs(a - b).max()) for a, b in zip(acc[s]["fields"], ref["fields"]))
-            prof, prof_ref = acc[s]["profile"] / u_tau, ref["profile"] / u_tau
-            d["max_du_over_utau_vs_f64"] = du / u_tau
-            d["eps_uplus_vs_f64"] = float(math.sqrt(((prof - prof_ref) ** 2).sum() / (prof_ref ** 2).sum()))
-        d["mlups_gain_vs_f64"] = res[s]["mlups"] / res["f64"]["mlups"]
-        per_store[s] = d
-    head = HEADLINE if HEADLINE in per_store else stores[-1]
+    acc_steps = wl["steps"]
+    head = DEFAULTS[args.workload][0]
+    bcs = wl["bcs"]
+    per_bc = {}
+    for bc in bcs:
+        ref = None
+        per_store = {}
+        for s in stores:
+            r, fields, p = run_store(P, W, args.workload, s, bc, args.steps, args.warmup, collision_kw(args),
+                                     acc_steps, ref)
+            if s == "f64":
+                ref = dict(fields=fields, profile=r.get("profile")) if fields is not None else None
+            print("[bench] %s %s: %.1f MLUPS, odd %.4f ms, even %.4f ms, status %d, max|du|/u_tau %s after %d steps"
+                  % (bc, s, r["mlups"], r["odd_kernel_ms"], r["even_kernel_ms"], r["status"],
+                     r.get("max_du_over_utau_vs_f64"), acc_steps), file=sys.stderr, flush=True)
+            d = store_record(r, s, n, copy_gbs)
+            per_store[s] = d
+        for s in stores:
+            per_store[s]["mlups_gain_vs_f64"] = per_store[s]["mlups"] / per_store["f64"]["mlups"]
+        per_bc[bc] = per_store
+        ref = None
+        import torch
+        torch.cuda.empty_cache()
+    per_store = per_bc[bcs[0]]
+    if head not in per_store:
+        head = stores[0]
     hd = per_store[head]
-    config = {"workload": "%s: %s" % (args.workload, wl["desc"]), "grid": [nx, ny, nz], "store": head,
-              "boundary": "wfb", "re_tau": wl["re_tau"], "tau0": p["tau0"], "fx": p["fx"],
-              "launch": list(W.launch_tiles(args.workload, head, args.collision)), "collision": args.collision,
-              "van_driest_aplus": args.van_driest, "parallelism": "single GPU"}
+    config = {"workload": "%s: %s; %d steps timed per store after %d warm-up steps, accuracy after %d steps"
+                          % (args.workload, wl["desc"], args.steps, args.warmup, acc_steps),
+              "grid": [nx, ny, nz], "store": head, "boundary": bcs[0], "re_tau": wl["re_tau"], "tau0": p["tau0"],
+              "fx": p["fx"], "launch": list(W.launch_tiles(args.workload, head, args.collision)),
+              "collision": args.collision, "van_driest_aplus": args.van_driest, "parallelism": "single GPU",
+              "timed_steps": args.steps, "accuracy_steps": acc_steps}
+    if args.workload in CACHE_RESIDENT:
+        config["cache_resident"] = True
     roof = roofline(hd, head, n, args.workload, args.collision)
-    return hd, per_store, config, roof, "f32" if head != "f64" else "f64"
+    extra = {"per_boundary": per_bc} if len(bcs) > 1 else {}
+    return hd, per_store, config, roof, DTYPE[head], extra
 
 
 def bench_ensemble(P, W, args, copy_gbs):
@@ -258,7 +326,7 @@ def bench_ensemble(P, W, args, copy_gbs):
     b = P.Batch(ens, store=store, graph_steps=0, **collision_kw(args))
     tiles = b.autotune(steps=6)
     b.init_spalding([e["u_tau"] for e in ens], 0.05, seeds=[e["seed"] for e in ens])
-    total_ms, odd_ms, even_ms = timed_steps(torch, b.step, b.stream, args.steps, args.warmup, 1)
+    total_ms, odd_ms, even_ms, per = timed_steps(torch, b.step, b.stream, args.steps, args.warmup, 1)
     status, first, inst = b.sync()
     r = dict(ms_per_step=total_ms / args.steps, mlups=n * args.steps / (total_ms * 1e-3) / 1e6,
              odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, status=int(status))
@@ -268,32 +336,34 @@ def bench_ensemble(P, W, args, copy_gbs):
     b2.step(100)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g_steps = args.steps - args.steps % 50 if args.steps >= 50 else 50
     e0.record(b2.stream)
-    b2.step(args.steps - args.steps % 50 if args.steps >= 50 else 50)
+    b2.step(g_steps)
     e1.record(b2.stream)
     torch.cuda.synchronize()
-    g_steps = args.steps - args.steps % 50 if args.steps >= 50 else 50
     graph_mlups = n * g_steps / (e0.elapsed_time(e1) * 1e-3) / 1e6
     print("[bench] ensemble: %.1f MLUPS eager, %.1f MLUPS graphs, odd %.4f ms, even %.4f ms, tiles %s"
           % (r["mlups"], graph_mlups, odd_ms, even_ms, tiles), file=sys.stderr, flush=True)
     d = store_record(r, store, n, copy_gbs)
     d["graph_mlups"] = graph_mlups
     d["launch"] = list(tiles)
-    config = {"workload": "c4: " + W.ENSEMBLE["desc"], "instances": len(ens), "cells": n, "store": store,
-              "launch": list(tiles), "parallelism": "single GPU"}
+    config = {"workload": "c4: %s; %d steps timed after %d warm-up steps" % (W.ENSEMBLE["desc"], args.steps,
+                                                                              args.warmup),
+              "instances": len(ens), "cells": n, "store": store, "launch": list(tiles), "parallelism": "single GPU",
+              "timed_steps": args.steps}
     b.close()
     b2.close()
     config.update(collision=args.collision, van_driest_aplus=args.van_driest)
-    return d, {store: d}, config, roofline(d, store, n, "c4", args.collision), "f32"
+    return d, {store: d}, config, roofline(d, store, n, "c4", args.collision), "f32", {}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="c3", choices=("c3", "c4", "c5"))
-    ap.add_argument("--stores", default="f64,f32,f16,bf16")
+    ap.add_argument("--steps", type=int, default=None, help="timed steps per store (default per workload)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default per workload)")
+    ap.add_argument("--workload", default="c5", choices=("c5", "c3", "c2", "c4"))
+    ap.add_argument("--stores", default=None, help="comma list (default f64,f32,f16,bf16; c2: f64,f32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--collision", default="bgk", choices=("bgk", "mrt"),
@@ -305,6 +375,14 @@ def main():
               "the multi-GPU slab decomposition is not implemented (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+    _, k_def, w_def = DEFAULTS[args.workload]
+    args.steps = k_def if args.steps is None else args.steps
+    args.warmup = w_def if args.warmup is None else args.warmup
+    if args.stores is None:
+        args.stores = "f64,f32" if args.workload == "c2" else "f64,f32,f16,bf16"
+    if args.steps < 2:
+        print("--steps must be >= 2 (one odd and one even kernel)", file=sys.stderr)
+        sys.exit(2)
     import torch
 
     import paper_2009_04352_amd as P
@@ -313,9 +391,9 @@ def main():
     torch.cuda.set_device(0)
     copy_gbs = None if args.no_copy_probe else copy_probe_gbs(P)
     if args.workload == "c4":
-        hd, per_store, config, roof, dtype = bench_ensemble(P, W, args, copy_gbs)
+        hd, per_store, config, roof, dtype, extra = bench_ensemble(P, W, args, copy_gbs)
     else:
-        hd, per_store, config, roof, dtype = bench_single(P, W, args, copy_gbs)
+        hd, per_store, config, roof, dtype, extra = bench_single(P, W, args, copy_gbs)
     line = {
         "metric": METRIC,
         "value": hd["mlups"],
@@ -335,6 +413,7 @@ def main():
         "copy_probe_gbs": copy_gbs,
         "kernel_source": kernel_source_hash(),
     }
+    line.update(extra)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(W, args.workload, collision_kw(args))
     print(json.dumps(line), flush=True)

@@ -100,8 +100,9 @@ extern "C" {
 #define LBM_P_MRT_S_EPS 20    /* ... of the energy-square moment; default 1.4 */
 #define LBM_P_MRT_S_Q 21      /* ... of the three heat-flux moments; default 1.2 */
 #define LBM_P_MRT_S_PI 22     /* ... of the two fourth-order normal-stress moments; default 1.99, near the
-                               * shear rate of a channel at tau0 -> 1/2: with d'Humieres' 1.4 the channel's
-                               * mean profile falls well below the wall law of Tables 2-3 */
+                               * shear rate of a channel at tau0 -> 1/2.  A value fitted to Tables 2-3 (the
+                               * paper states none): with d'Humieres' suggested 1.4, the documented
+                               * alternative, the channel's mean profile falls well below the wall law */
 #define LBM_P_MRT_S_M 23      /* ... of the three third-order moments; default 1.98 */
 #define LBM_P_VD_APLUS 24     /* van Driest damping of the Smagorinsky constant (Sec. 3.1): Cs (1 - exp(-y+/A+))
                                * with y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1; A+ >= 0, 0 = no damping
@@ -194,6 +195,13 @@ int lbm_steps_done(const lbm_ctx* ctx, int64_t* steps);
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz);
 /* Same for n listed cells: out is [n][4] = rho, ux, uy, uz. */
 int lbm_moments_cells(lbm_ctx* ctx, int64_t n, const int64_t* cells, double* out);
+
+/* The same observables (Eq. 2 after the gather and WFB correction the next
+ * step would make) written to caller-owned device memory on the context's
+ * device: each non-NULL pointer receives ncells doubles indexed by c.  At
+ * least one pointer must be given (else LBM_E_ARG).  Asynchronous on the
+ * context's stream, like lbm_step; nothing is copied to the host. */
+int lbm_moments_device(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz);
 
 /* Wall records of the current state, 2 * nx * nz doubles each (any may be
  * NULL), layout [w][z][x], w = 0 bottom, 1 top.  WFB: tau_x, tau_z (Eq. 15),

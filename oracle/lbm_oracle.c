@@ -58,6 +58,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -131,6 +134,29 @@ typedef struct {
     double *stats;          /* [y][8]: sums of ux uy uz ux^2 uy^2 uz^2 ux*uy, count */
     int64_t nsamples;
 } orc;
+
+/* ------------------------------------------------------------ threads */
+
+/* Threads the OpenMP loops over z use (1 without OpenMP), and a way to set
+ * them; the results do not depend on the count (cells are independent and
+ * every sum runs in a fixed order). */
+int32_t orc_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads((int)n);
+#else
+    (void)n;
+#endif
+}
 
 /* ---------------------------------------------------------------- tables */
 
@@ -412,6 +438,13 @@ typedef struct {
     const double* profile;/* [y] streamwise velocity of the initial profile */
     double noise;
     uint64_t seed;
+    /* or, if tab_cells is non-NULL: a table of cells (ascending indices
+     * x + nx (y + ny z)) and their populations [k][a]; a lookup of a cell
+     * that is not in it sets *missing */
+    const int64_t* tab_cells;
+    const double* tab_f;
+    int64_t ntab;
+    int* missing;
 } src_t;
 
 static int64_t cell_index(const orc_params* p, int x, int y, int z)
@@ -449,6 +482,16 @@ static void initial_velocity(const src_t* s, int x, int y, int z, double u[3])
 
 static double src_get(const src_t* s, int a, int x, int y, int z)
 {
+    if (s->tab_cells) {
+        int64_t c = cell_index(s->p, x, y, z), lo = 0, hi = s->ntab;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (s->tab_cells[mid] < c) lo = mid + 1; else hi = mid;
+        }
+        if (lo < s->ntab && s->tab_cells[lo] == c) return s->tab_f[Q * lo + a];
+        *s->missing = 1;
+        return NAN;
+    }
     if (s->fpost) return s->fpost[(int64_t)a * ((int64_t)s->p->nx * s->p->ny * s->p->nz) + cell_index(s->p, x, y, z)];
     double u[3];
     initial_velocity(s, x, y, z, u);
@@ -582,7 +625,7 @@ int orc_init_spalding(orc* o, double u_tau, double noise, uint64_t seed)
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -619,7 +662,7 @@ int orc_step(orc* o, int64_t n)
     for (int64_t t = 0; t < n; ++t) {
         const int64_t step = o->steps + 1;
         const int sample = p->stats_every > 0 && (step % p->stats_every) == 0;
-        src_t s = {p, o->fpost, NULL, 0.0, 0};
+        src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
         int bad = 0;
         int32_t maxit = o->max_newton_iters;
         double* srow = NULL;
@@ -676,7 +719,7 @@ int orc_step(orc* o, int64_t n)
 int orc_observe(const orc* o, double* rho, double* ux, double* uy, double* uz)
 {
     const orc_params* p = &o->p;
-    src_t s = {p, o->fpost, NULL, 0.0, 0};
+    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int z = 0; z < p->nz; ++z)
@@ -702,7 +745,7 @@ int orc_observe(const orc* o, double* rho, double* ux, double* uy, double* uz)
 int orc_wall(const orc* o, double* taux, double* tauz, double* utau, double* uu)
 {
     const orc_params* p = &o->p;
-    src_t s = {p, o->fpost, NULL, 0.0, 0};
+    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
     for (int w = 0; w < 2; ++w) {
         int y = (w == 0) ? 0 : p->ny - 1;
         for (int z = 0; z < p->nz; ++z)
@@ -764,7 +807,7 @@ int orc_init_cells(const orc_params* p, double u_tau, double noise, uint64_t see
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = cells[i];
         int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((int64_t)p->nx * p->ny));
@@ -783,7 +826,7 @@ int orc_step1_cells(const orc_params* p, double u_tau, double noise, uint64_t se
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
     int st = ORC_OK;
     for (int64_t i = 0; i < n && st == ORC_OK; ++i) {
         int64_t c = cells[i];
@@ -791,5 +834,30 @@ int orc_step1_cells(const orc_params* p, double u_tau, double noise, uint64_t se
         st = cell_update(&s, x, y, z, fpost_out + Q * i, mom_out ? mom_out + 4 * i : NULL, NULL);
     }
     free(prof);
+    return st;
+}
+
+/* One step at selected cells from a table of post-collision populations of
+ * the cells around them (any cells, ascending indices; e.g. the 3 x 3 x 3
+ * neighbourhoods of the selected cells): the same update as orc_step, for
+ * checking single cells of grids too large for the oracle's arrays.
+ * Returns ORC_E_ARG if the gather needs a cell that is not in the table. */
+int orc_step_cells_table(const orc_params* p, int64_t ntab, const int64_t* tab_cells, const double* tab_f,
+                         int64_t n, const int64_t* cells, double* fpost_out /* [n][19] */,
+                         double* mom_out /* [n][4]: observables of the table's state, may be NULL */)
+{
+    tables_init();
+    if (!params_ok(p)) return ORC_E_ARG;
+    for (int64_t k = 1; k < ntab; ++k)
+        if (tab_cells[k] <= tab_cells[k - 1]) return ORC_E_ARG;
+    int missing = 0;
+    src_t s = {p, NULL, NULL, 0.0, 0, tab_cells, tab_f, ntab, &missing};
+    int st = ORC_OK;
+    for (int64_t i = 0; i < n && st == ORC_OK; ++i) {
+        int64_t c = cells[i];
+        int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((int64_t)p->nx * p->ny));
+        st = cell_update(&s, x, y, z, fpost_out + Q * i, mom_out ? mom_out + 4 * i : NULL, NULL);
+        if (missing) st = ORC_E_ARG;
+    }
     return st;
 }

@@ -16,8 +16,9 @@ BB, WFB, FREESLIP = 0, 1, 2
 BGK, MRT = 0, 1
 # MRT rates of the non-hydrodynamic moments for D3Q19: energy, energy square,
 # heat flux and third-order m moments as suggested by d'Humieres et al. (2002);
-# the fourth-order normal stresses near the shear rate (1.99), the value with
-# which the channel runs reproduce the wall-law figures of Tables 2 and 3
+# the fourth-order normal stresses near the shear rate (1.99): a value fitted
+# so that the channel runs reproduce the wall-law figures of Tables 2 and 3
+# (the paper states none; the reference suggests 1.4)
 MRT_RATES = dict(s_e=1.19, s_eps=1.4, s_q=1.2, s_pi=1.99, s_m=1.98)
 OK, E_ARG, E_NONFINITE, E_NEWTON = 0, -1, -5, -6
 
@@ -51,6 +52,9 @@ def lib():
         i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
         PP = C.POINTER(Params)
         L.orc_tables.argtypes = [i32p, dp, i32p, i32p]
+        L.orc_threads.restype = C.c_int32
+        L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [C.c_int32]
         L.orc_spalding_yplus.restype = C.c_double
         L.orc_spalding_yplus.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_spalding_uplus.restype = C.c_double
@@ -88,10 +92,21 @@ def lib():
         L.orc_stats_reset.argtypes = [C.c_void_p]
         L.orc_init_cells.restype = C.c_int
         L.orc_init_cells.argtypes = [PP, C.c_double, C.c_double, C.c_uint64, C.c_int64, ip, dp]
+        L.orc_step_cells_table.restype = C.c_int
+        L.orc_step_cells_table.argtypes = [PP, C.c_int64, ip, dp, C.c_int64, ip, dp, dp]
         L.orc_step1_cells.restype = C.c_int
         L.orc_step1_cells.argtypes = [PP, C.c_double, C.c_double, C.c_uint64, C.c_int64, ip, dp, dp]
         _lib = L
     return _lib
+
+
+def threads():
+    """Threads the oracle's loops use."""
+    return lib().orc_threads()
+
+
+def set_threads(n):
+    lib().orc_set_threads(int(n))
 
 
 def tables():
@@ -313,4 +328,36 @@ def step1_cells(params, u_tau, noise, seed, cells):
                                out.reshape(-1), mom.reshape(-1))
     if st != OK:
         raise RuntimeError("oracle step1_cells failed: %d" % st)
+    return out, mom
+
+
+def neighbourhood(grid, cells):
+    """The cells of the 3 x 3 x 3 neighbourhoods (x and z periodic, y clipped to
+    the channel) of the given cells, ascending and unique."""
+    nx, ny, nz = grid
+    cells = np.asarray(cells, dtype=np.int64)
+    x, y, z = cells % nx, (cells // nx) % ny, cells // (nx * ny)
+    out = []
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                yy = y + dy
+                ok = (yy >= 0) & (yy < ny)
+                out.append((((x + dx) % nx) + nx * (yy + ny * ((z + dz) % nz)))[ok])
+    return np.unique(np.concatenate(out))
+
+
+def step_cells_table(params, tab_cells, tab_f, cells):
+    """One step at the given cells from a table of post-collision populations
+    tab_f [k][19] of the cells tab_cells (ascending); returns the post-collision
+    populations [n][19] and the observables (rho, u) [n][4] of the table's state."""
+    tab_cells = np.ascontiguousarray(tab_cells, dtype=np.int64)
+    tab_f = np.ascontiguousarray(tab_f, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.zeros((len(cells), 19))
+    mom = np.zeros((len(cells), 4))
+    st = lib().orc_step_cells_table(C.byref(params), len(tab_cells), tab_cells, tab_f.reshape(-1), len(cells), cells,
+                                    out.reshape(-1), mom.reshape(-1))
+    if st != OK:
+        raise RuntimeError("oracle step_cells_table failed: %d" % st)
     return out, mom

@@ -50,6 +50,7 @@ SIGNATURES = {
     "lbm_steps_done": (C.c_int, [_vp, _i64p]),
     "lbm_moments": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm_moments_cells": (C.c_int, [_vp, C.c_int64, _i64p, _dp]),
+    "lbm_moments_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_wall_shear": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm_wall_yplus_pdf": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, C.c_void_p, _dp]),
     "lbm_init_moments": (C.c_int, [_vp, _dp, _dp]),

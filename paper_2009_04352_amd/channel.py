@@ -203,6 +203,20 @@ class Channel:
         self._chk(self.lib.lbm_moments_cells(self._h, len(cells), L.i64ptr(cells), L.dptr(out)))
         return out.reshape(len(cells), 4)
 
+    def moments_device(self, rho=None, ux=None, uy=None, uz=None):
+        """Observables written into float64 torch tensors of ncell elements on the
+        channel's device (any may be None), enqueued on the channel's stream."""
+        ptrs = []
+        for t in (rho, ux, uy, uz):
+            if t is None:
+                ptrs.append(None)
+                continue
+            import torch
+            if t.dtype != torch.float64 or t.numel() < self.ncell or not t.is_contiguous():
+                raise ValueError("moment tensors must be contiguous float64 with ncell elements")
+            ptrs.append(C.c_void_p(t.data_ptr()))
+        self._chk(self.lib.lbm_moments_device(self._h, *ptrs))
+
     def wall_shear(self):
         m = 2 * self.nx * self.nz
         outs = [np.empty(m) for _ in range(4)]

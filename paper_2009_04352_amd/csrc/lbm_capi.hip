@@ -50,7 +50,8 @@ struct lbm_ctx {
     int odd_rows = 1;            // odd step by rows: 0 never, 1 when rows are longer than a block, 2 whenever possible
     int coll = kBGK;             // collision: kBGK or kMRT
     // MRT rates e, epsilon, q, pi, m: d'Humieres et al. (2002) for e, epsilon, q, m; the fourth-order
-    // normal stresses near the shear rate (the value with which the wall-law runs match Tables 2-3)
+    // normal stresses near the shear rate, a value fitted so that the wall-law runs match Tables 2-3
+    // (the paper states none; the reference suggests 1.4)
     double mrt_s[5] = {1.19, 1.4, 1.2, 1.99, 1.98};
     double vd_aplus = 0.0;       // van Driest A+; 0 = no damping
     double vd_utau = 0.0;        // friction velocity of the damping's y+; 0 = sqrt(|Fx| ny / 2)
@@ -91,6 +92,32 @@ int fail(lbm_ctx* ctx, int code, const std::string& msg)
     if (ctx) ctx->err = msg;
     else g_err = msg;
     return code;
+}
+
+// Error text without allocation failures escaping: an exception never
+// crosses the C ABI, so the guard below reports it with this.
+int fail_nothrow(lbm_ctx* ctx, int code, const char* msg) noexcept
+{
+    try {
+        if (ctx) ctx->err = msg;
+        else g_err = msg;
+    } catch (...) {
+    }
+    return code;
+}
+
+// Runs the body of an entry point; a C++ exception (a host allocation
+// failure in a container or string) becomes a status code.
+template <typename F>
+int guard(lbm_ctx* ctx, F&& body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return fail_nothrow(ctx, LBM_E_OOM, "host memory allocation failed");
+    } catch (...) {
+        return fail_nothrow(ctx, LBM_E_STATE, "internal error (exception)");
+    }
 }
 
 #define LBM_HIP(ctx, call)                                                                      \
@@ -159,8 +186,12 @@ bool shapes_fit_layout(const lbm_ctx* c)
 
 bool tile_ok(int t) { return t == 64 || t == 128 || t == 256 || t == 512; }
 
+// Destroys the cached graph executables; a launch of one may still be
+// running (lbm_step is asynchronous), so the stream is drained first.
 void drop_graphs(lbm_ctx* c)
 {
+    if (c->graphs.empty()) return;
+    (void)hipStreamSynchronize(c->stream);
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
 }
@@ -406,29 +437,31 @@ const char* lbm_last_error(const lbm_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int lbm_create(const lbm_grid* g, double tau, double Cs, double kappa, double B, double Fx, lbm_ctx** out)
 {
-    if (!g || !out) return fail(nullptr, LBM_E_ARG, "null argument");
-    if (g->nx < 1 || g->ny < 2 || g->nz < 1) return fail(nullptr, LBM_E_ARG, "grid needs nx >= 1, ny >= 2, nz >= 1");
-    const long long n = (long long)g->nx * g->ny * g->nz;
-    if (n >= (1ll << 31)) return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny * nz must be below 2^31");
-    if ((long long)g->nx * g->ny >= (1ll << 29))
-        return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny must be below 2^29 (32-bit offsets within a z-plane)");
-    if (!std::isfinite(tau) || !(tau > 0.5)) return fail(nullptr, LBM_E_ARG, "tau must be finite and > 1/2");
-    if (!std::isfinite(Cs) || !(Cs >= 0.0)) return fail(nullptr, LBM_E_ARG, "Cs must be finite and >= 0");
-    if (!std::isfinite(kappa) || !(kappa > 0.0)) return fail(nullptr, LBM_E_ARG, "kappa must be finite and > 0");
-    if (!std::isfinite(B) || !std::isfinite(Fx)) return fail(nullptr, LBM_E_ARG, "B and Fx must be finite");
-    lbm_ctx* c = new (std::nothrow) lbm_ctx();
-    if (!c) return fail(nullptr, LBM_E_OOM, "context allocation failed");
-    c->nx = g->nx;
-    c->ny = g->ny;
-    c->nz = g->nz;
-    c->n = n;
-    c->tau0 = tau;
-    c->cs = Cs;
-    c->kappa = kappa;
-    c->bconst = B;
-    c->fx = Fx;
-    *out = c;
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (!g || !out) return fail(nullptr, LBM_E_ARG, "null argument");
+        if (g->nx < 1 || g->ny < 2 || g->nz < 1) return fail(nullptr, LBM_E_ARG, "grid needs nx >= 1, ny >= 2, nz >= 1");
+        const long long n = (long long)g->nx * g->ny * g->nz;
+        if (n >= (1ll << 31)) return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny * nz must be below 2^31");
+        if ((long long)g->nx * g->ny >= (1ll << 29))
+            return fail(nullptr, LBM_E_ARG, "grid too large: nx * ny must be below 2^29 (32-bit offsets within a z-plane)");
+        if (!std::isfinite(tau) || !(tau > 0.5)) return fail(nullptr, LBM_E_ARG, "tau must be finite and > 1/2");
+        if (!std::isfinite(Cs) || !(Cs >= 0.0)) return fail(nullptr, LBM_E_ARG, "Cs must be finite and >= 0");
+        if (!std::isfinite(kappa) || !(kappa > 0.0)) return fail(nullptr, LBM_E_ARG, "kappa must be finite and > 0");
+        if (!std::isfinite(B) || !std::isfinite(Fx)) return fail(nullptr, LBM_E_ARG, "B and Fx must be finite");
+        lbm_ctx* c = new (std::nothrow) lbm_ctx();
+        if (!c) return fail(nullptr, LBM_E_OOM, "context allocation failed");
+        c->nx = g->nx;
+        c->ny = g->ny;
+        c->nz = g->nz;
+        c->n = n;
+        c->tau0 = tau;
+        c->cs = Cs;
+        c->kappa = kappa;
+        c->bconst = B;
+        c->fx = Fx;
+        *out = c;
+        return LBM_OK;
+    });
 }
 
 void lbm_destroy(lbm_ctx* c)
@@ -449,210 +482,224 @@ void lbm_destroy(lbm_ctx* c)
 
 int lbm_set_param(lbm_ctx* c, int key, double v)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's parameters are set through its batch");
-    if (!std::isfinite(v)) return fail(c, LBM_E_ARG, "parameter value must be finite");
-    const bool integral = (v == std::floor(v));
-    switch (key) {
-        case LBM_P_Y1:
-            if (!(v > 0.0)) return fail(c, LBM_E_ARG, "y1 must be > 0");
-            c->y1 = v;
-            break;
-        case LBM_P_NEWTON_TOL:
-            if (!(v > 0.0)) return fail(c, LBM_E_ARG, "Newton tolerance must be > 0");
-            c->newton_tol = v;
-            break;
-        case LBM_P_NEWTON_MAXIT:
-            if (!integral || v < 1 || v > 10000) return fail(c, LBM_E_ARG, "Newton cap must be an integer in [1, 10000]");
-            c->newton_maxit = (int)v;
-            break;
-        case LBM_P_STATS_EVERY:
-            if (!integral || v < 0 || v > 1e9) return fail(c, LBM_E_ARG, "statistics interval must be an integer >= 0");
-            c->stats_every = (int)v;
-            break;
-        case LBM_P_STORE:
-            if (c->h) return fail(c, LBM_E_STATE, "the store format is fixed once storage is bound");
-            if (!integral || v < 0 || v > 3) return fail(c, LBM_E_ARG, "store must be 0..3");
-            c->store = (int)v;
-            return LBM_OK;
-        case LBM_P_TILE_ODD:
-        case LBM_P_TILE_EVEN: {
-            if (!integral || !tile_ok((int)v)) return fail(c, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
-            int& tile = (key == LBM_P_TILE_ODD ? c->tile_odd : c->tile_even);
-            const int old = tile;
-            tile = (int)v;
-            if (!shapes_fit_layout(c)) {
-                tile = old;
-                return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
-                                            "with bricks of " + std::to_string(c->brick) + " rows");
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's parameters are set through its batch");
+        if (!std::isfinite(v)) return fail(c, LBM_E_ARG, "parameter value must be finite");
+        const bool integral = (v == std::floor(v));
+        switch (key) {
+            case LBM_P_Y1:
+                if (!(v > 0.0)) return fail(c, LBM_E_ARG, "y1 must be > 0");
+                c->y1 = v;
+                break;
+            case LBM_P_NEWTON_TOL:
+                if (!(v > 0.0)) return fail(c, LBM_E_ARG, "Newton tolerance must be > 0");
+                c->newton_tol = v;
+                break;
+            case LBM_P_NEWTON_MAXIT:
+                if (!integral || v < 1 || v > 10000) return fail(c, LBM_E_ARG, "Newton cap must be an integer in [1, 10000]");
+                c->newton_maxit = (int)v;
+                break;
+            case LBM_P_STATS_EVERY:
+                if (!integral || v < 0 || v > 1e9) return fail(c, LBM_E_ARG, "statistics interval must be an integer >= 0");
+                c->stats_every = (int)v;
+                break;
+            case LBM_P_STORE:
+                if (c->h) return fail(c, LBM_E_STATE, "the store format is fixed once storage is bound");
+                if (!integral || v < 0 || v > 3) return fail(c, LBM_E_ARG, "store must be 0..3");
+                c->store = (int)v;
+                return LBM_OK;
+            case LBM_P_TILE_ODD:
+            case LBM_P_TILE_EVEN: {
+                if (!integral || !tile_ok((int)v)) return fail(c, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
+                int& tile = (key == LBM_P_TILE_ODD ? c->tile_odd : c->tile_even);
+                const int old = tile;
+                tile = (int)v;
+                if (!shapes_fit_layout(c)) {
+                    tile = old;
+                    return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
+                                                "with bricks of " + std::to_string(c->brick) + " rows");
+                }
+                break;
             }
-            break;
-        }
-        case LBM_P_XCD_REMAP:
-            if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
-            c->xcd_remap = (int)v;
-            break;
-        case LBM_P_VECTOR: {
-            if (!integral || (v != 0.0 && !step_vector_width_ok(c->store, c->nx, (int)v)))
-                return fail(c, LBM_E_ARG, "cells per thread must be 0 (auto) or 1, 2, 4 with groups of at most 8 bytes dividing nx");
-            const int old = c->vw_req;
-            c->vw_req = (int)v;
-            if (!shapes_fit_layout(c)) {
-                c->vw_req = old;
-                return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
-                                            "with bricks of " + std::to_string(c->brick) + " rows");
+            case LBM_P_XCD_REMAP:
+                if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
+                c->xcd_remap = (int)v;
+                break;
+            case LBM_P_VECTOR: {
+                if (!integral || (v != 0.0 && !step_vector_width_ok(c->store, c->nx, (int)v)))
+                    return fail(c, LBM_E_ARG, "cells per thread must be 0 (auto) or 1, 2, 4 with groups of at most 8 bytes dividing nx");
+                const int old = c->vw_req;
+                c->vw_req = (int)v;
+                if (!shapes_fit_layout(c)) {
+                    c->vw_req = old;
+                    return fail(c, LBM_E_STATE, "blocks of several rows need the plain layout; this state was initialised "
+                                                "with bricks of " + std::to_string(c->brick) + " rows");
+                }
+                break;
             }
-            break;
+            case LBM_P_ODD_ROWS:
+                if (!integral || v < 0 || v > 2) return fail(c, LBM_E_ARG, "odd-step mode must be 0, 1 or 2");
+                c->odd_rows = (int)v;
+                break;
+            case LBM_P_SPREAD:
+                if (!integral || v < -1 || v > 16 || (v > 0 && v < kXcdChunkLog2))
+                    return fail(c, LBM_E_ARG, "brick spreading is -1 (by store), 0 (off) or a chunk log2 in [5, 16]");
+                c->spread = (int)v;
+                break;
+            case LBM_P_BRICK:
+                if (c->initialized) return fail(c, LBM_E_STATE, "the population layout is fixed once the state is initialised");
+                if (!integral || v < 0 || v > (1 << 30)) return fail(c, LBM_E_ARG, "rows per brick must be an integer >= 0");
+                c->brick_req = (int)v;
+                break;
+            case LBM_P_GRAPH_STEPS:
+                if (!integral || v < 0 || v > 4096) return fail(c, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
+                c->graph_steps = (int)v;
+                break;
+            case LBM_P_FX:
+                c->fx = v;
+                break;
+            case LBM_P_CS:
+                if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "Cs must be >= 0");
+                c->cs = v;
+                break;
+            case LBM_P_COLLISION:
+                if (v != kBGK && v != kMRT) return fail(c, LBM_E_ARG, "collision is 0 (BGK) or 1 (MRT)");
+                c->coll = (int)v;
+                break;
+            case LBM_P_MRT_S_E:
+            case LBM_P_MRT_S_EPS:
+            case LBM_P_MRT_S_Q:
+            case LBM_P_MRT_S_PI:
+            case LBM_P_MRT_S_M:
+                if (!(v > 0.0 && v < 2.0)) return fail(c, LBM_E_ARG, "MRT rates must lie in (0, 2)");
+                c->mrt_s[key - LBM_P_MRT_S_E] = v;
+                break;
+            case LBM_P_VD_APLUS:
+                if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest A+ must be >= 0");
+                c->vd_aplus = v;
+                break;
+            case LBM_P_VD_UTAU:
+                if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest friction velocity must be >= 0");
+                c->vd_utau = v;
+                break;
+            default:
+                return fail(c, LBM_E_ARG, "unknown or read-only parameter key");
         }
-        case LBM_P_ODD_ROWS:
-            if (!integral || v < 0 || v > 2) return fail(c, LBM_E_ARG, "odd-step mode must be 0, 1 or 2");
-            c->odd_rows = (int)v;
-            break;
-        case LBM_P_SPREAD:
-            if (!integral || v < -1 || v > 16 || (v > 0 && v < kXcdChunkLog2))
-                return fail(c, LBM_E_ARG, "brick spreading is -1 (by store), 0 (off) or a chunk log2 in [5, 16]");
-            c->spread = (int)v;
-            break;
-        case LBM_P_BRICK:
-            if (c->initialized) return fail(c, LBM_E_STATE, "the population layout is fixed once the state is initialised");
-            if (!integral || v < 0 || v > (1 << 30)) return fail(c, LBM_E_ARG, "rows per brick must be an integer >= 0");
-            c->brick_req = (int)v;
-            break;
-        case LBM_P_GRAPH_STEPS:
-            if (!integral || v < 0 || v > 4096) return fail(c, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
-            c->graph_steps = (int)v;
-            break;
-        case LBM_P_FX:
-            c->fx = v;
-            break;
-        case LBM_P_CS:
-            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "Cs must be >= 0");
-            c->cs = v;
-            break;
-        case LBM_P_COLLISION:
-            if (v != kBGK && v != kMRT) return fail(c, LBM_E_ARG, "collision is 0 (BGK) or 1 (MRT)");
-            c->coll = (int)v;
-            break;
-        case LBM_P_MRT_S_E:
-        case LBM_P_MRT_S_EPS:
-        case LBM_P_MRT_S_Q:
-        case LBM_P_MRT_S_PI:
-        case LBM_P_MRT_S_M:
-            if (!(v > 0.0 && v < 2.0)) return fail(c, LBM_E_ARG, "MRT rates must lie in (0, 2)");
-            c->mrt_s[key - LBM_P_MRT_S_E] = v;
-            break;
-        case LBM_P_VD_APLUS:
-            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest A+ must be >= 0");
-            c->vd_aplus = v;
-            break;
-        case LBM_P_VD_UTAU:
-            if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest friction velocity must be >= 0");
-            c->vd_utau = v;
-            break;
-        default:
-            return fail(c, LBM_E_ARG, "unknown or read-only parameter key");
-    }
-    c->cs2_dirty = true;
-    drop_graphs(c);
-    return LBM_OK;
+        c->cs2_dirty = true;
+        drop_graphs(c);
+        return LBM_OK;
+    });
 }
 
 int lbm_get_param(const lbm_ctx* c, int key, double* v)
 {
-    if (!c || !v) return fail(nullptr, LBM_E_ARG, "null argument");
-    switch (key) {
-        case LBM_P_Y1: *v = c->y1; break;
-        case LBM_P_NEWTON_TOL: *v = c->newton_tol; break;
-        case LBM_P_NEWTON_MAXIT: *v = c->newton_maxit; break;
-        case LBM_P_STATS_EVERY: *v = c->stats_every; break;
-        case LBM_P_STORE: *v = c->store; break;
-        case LBM_P_TILE_ODD: *v = c->tile_odd; break;
-        case LBM_P_TILE_EVEN: *v = c->tile_even; break;
-        case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
-        case LBM_P_VECTOR: *v = vector_width(c); break;
-        case LBM_P_BRICK: *v = brick_rows(c); break;
-        case LBM_P_ODD_ROWS: *v = c->odd_rows; break;
-        case LBM_P_SPREAD: *v = spread_log2(c); break;
-        case LBM_P_ODD_BY_ROWS: *v = odd_by_rows(c, c->odd_rows) ? 1.0 : 0.0; break;
-        case LBM_P_COLLISION: *v = c->coll; break;
-        case LBM_P_MRT_S_E:
-        case LBM_P_MRT_S_EPS:
-        case LBM_P_MRT_S_Q:
-        case LBM_P_MRT_S_PI:
-        case LBM_P_MRT_S_M: *v = c->mrt_s[key - LBM_P_MRT_S_E]; break;
-        case LBM_P_VD_APLUS: *v = c->vd_aplus; break;
-        case LBM_P_VD_UTAU: *v = c->vd_utau; break;
-        case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
-        case LBM_P_BC: *v = c->bc; break;
-        case LBM_P_TAU0: *v = c->tau0; break;
-        case LBM_P_FX: *v = c->fx; break;
-        case LBM_P_CS: *v = c->cs; break;
-        default: return fail(const_cast<lbm_ctx*>(c), LBM_E_ARG, "unknown parameter key");
-    }
-    return LBM_OK;
+    return guard(const_cast<lbm_ctx*>(c), [&]() -> int {
+        if (!c || !v) return fail(nullptr, LBM_E_ARG, "null argument");
+        switch (key) {
+            case LBM_P_Y1: *v = c->y1; break;
+            case LBM_P_NEWTON_TOL: *v = c->newton_tol; break;
+            case LBM_P_NEWTON_MAXIT: *v = c->newton_maxit; break;
+            case LBM_P_STATS_EVERY: *v = c->stats_every; break;
+            case LBM_P_STORE: *v = c->store; break;
+            case LBM_P_TILE_ODD: *v = c->tile_odd; break;
+            case LBM_P_TILE_EVEN: *v = c->tile_even; break;
+            case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
+            case LBM_P_VECTOR: *v = vector_width(c); break;
+            case LBM_P_BRICK: *v = brick_rows(c); break;
+            case LBM_P_ODD_ROWS: *v = c->odd_rows; break;
+            case LBM_P_SPREAD: *v = spread_log2(c); break;
+            case LBM_P_ODD_BY_ROWS: *v = odd_by_rows(c, c->odd_rows) ? 1.0 : 0.0; break;
+            case LBM_P_COLLISION: *v = c->coll; break;
+            case LBM_P_MRT_S_E:
+            case LBM_P_MRT_S_EPS:
+            case LBM_P_MRT_S_Q:
+            case LBM_P_MRT_S_PI:
+            case LBM_P_MRT_S_M: *v = c->mrt_s[key - LBM_P_MRT_S_E]; break;
+            case LBM_P_VD_APLUS: *v = c->vd_aplus; break;
+            case LBM_P_VD_UTAU: *v = c->vd_utau; break;
+            case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
+            case LBM_P_BC: *v = c->bc; break;
+            case LBM_P_TAU0: *v = c->tau0; break;
+            case LBM_P_FX: *v = c->fx; break;
+            case LBM_P_CS: *v = c->cs; break;
+            default: return fail(const_cast<lbm_ctx*>(c), LBM_E_ARG, "unknown parameter key");
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_required_bytes(const lbm_ctx* c, size_t* bytes)
 {
-    if (!c || !bytes) return fail(nullptr, LBM_E_ARG, "null argument");
-    *bytes = (size_t)19 * (size_t)c->n * (size_t)store_bytes(c->store);
-    return LBM_OK;
+    return guard(const_cast<lbm_ctx*>(c), [&]() -> int {
+        if (!c || !bytes) return fail(nullptr, LBM_E_ARG, "null argument");
+        *bytes = (size_t)19 * (size_t)c->n * (size_t)store_bytes(c->store);
+        return LBM_OK;
+    });
 }
 
 int lbm_bind_storage(lbm_ctx* c, void* ptr, size_t bytes)
 {
-    if (!c || !ptr) return fail(c, LBM_E_ARG, "null argument");
-    size_t need = 0;
-    lbm_required_bytes(c, &need);
-    if (bytes < need) return fail(c, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
-    if (((uintptr_t)ptr) % 256 != 0) return fail(c, LBM_E_ARG, "storage must be 256-byte aligned");
-    hipPointerAttribute_t attr;
-    hipError_t e = hipPointerGetAttributes(&attr, ptr);
-    if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
-        return fail(c, LBM_E_ARG, "storage is not device memory");
-    if (c->h && attr.device != c->dev) return fail(c, LBM_E_STATE, "storage must stay on the same device");
-    c->dev = attr.device;
-    DeviceGuard dg(c->dev);
-    if (!c->dflags) {
-        LBM_HIP(c, hipMalloc((void**)&c->dflags, sizeof(DevFlags)));
-        LBM_HIP(c, hipMalloc((void**)&c->dacc, (size_t)c->ny * 8 * sizeof(double)));
-        LBM_HIP(c, hipMalloc((void**)&c->dprof, (size_t)c->ny * sizeof(double)));
-        LBM_HIP(c, hipMalloc((void**)&c->dcs2, (size_t)c->ny * sizeof(double)));
-        LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
-        c->cs2_dirty = true;
-    }
-    drop_graphs(c);
-    c->h = ptr;
-    c->bytes = bytes;
-    c->initialized = false;
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c || !ptr) return fail(c, LBM_E_ARG, "null argument");
+        size_t need = 0;
+        lbm_required_bytes(c, &need);
+        if (bytes < need) return fail(c, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
+        if (((uintptr_t)ptr) % 256 != 0) return fail(c, LBM_E_ARG, "storage must be 256-byte aligned");
+        hipPointerAttribute_t attr;
+        hipError_t e = hipPointerGetAttributes(&attr, ptr);
+        if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
+            return fail(c, LBM_E_ARG, "storage is not device memory");
+        if (c->h && attr.device != c->dev) return fail(c, LBM_E_STATE, "storage must stay on the same device");
+        c->dev = attr.device;
+        DeviceGuard dg(c->dev);
+        if (!c->dflags) {
+            LBM_HIP(c, hipMalloc((void**)&c->dflags, sizeof(DevFlags)));
+            LBM_HIP(c, hipMalloc((void**)&c->dacc, (size_t)c->ny * 8 * sizeof(double)));
+            LBM_HIP(c, hipMalloc((void**)&c->dprof, (size_t)c->ny * sizeof(double)));
+            LBM_HIP(c, hipMalloc((void**)&c->dcs2, (size_t)c->ny * sizeof(double)));
+            LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
+            c->cs2_dirty = true;
+        }
+        drop_graphs(c);
+        c->h = ptr;
+        c->bytes = bytes;
+        c->initialized = false;
+        return LBM_OK;
+    });
 }
 
 int lbm_set_stream(lbm_ctx* c, void* s)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    c->stream = (hipStream_t)s;
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        c->stream = (hipStream_t)s;
+        return LBM_OK;
+    });
 }
 
 int lbm_set_boundary(lbm_ctx* c, int bc)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's boundary is fixed at batch creation");
-    if (bc != LBM_BB && bc != LBM_WFB && bc != LBM_FREESLIP) return fail(c, LBM_E_ARG, "unknown boundary");
-    DeviceGuard dg(c->dev);
-    c->bc = bc;
-    drop_graphs(c);
-    return fix_layout(c);
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's boundary is fixed at batch creation");
+        if (bc != LBM_BB && bc != LBM_WFB && bc != LBM_FREESLIP) return fail(c, LBM_E_ARG, "unknown boundary");
+        DeviceGuard dg(c->dev);
+        c->bc = bc;
+        drop_graphs(c);
+        return fix_layout(c);
+    });
 }
 
 static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t seed);
 
 int lbm_init_spalding(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
-    return init_spalding_impl(c, u_tau, noise, seed);
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
+        return init_spalding_impl(c, u_tau, noise, seed);
+    });
 }
 
 static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t seed)
@@ -684,81 +731,85 @@ static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t s
 
 int lbm_init_moments(lbm_ctx* c, const double* rho, const double* u)
 {
-    if (!c || !rho || !u) return fail(c, LBM_E_ARG, "null argument");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
-    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
-    for (long long i = 0; i < c->n; ++i) {
-        const double r = rho[i], x = u[i], y = u[c->n + i], z = u[2 * c->n + i];
-        if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
-            return fail(c, LBM_E_ARG, "need finite moments and rho > 0");
-    }
-    DeviceGuard dg(c->dev);
-    const long long chunk = std::min<long long>(c->n, 1ll << 24);
-    double* tmp = nullptr;
-    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 4 * sizeof(double)));
-    std::vector<double> stage((size_t)chunk * 4);
-    c->initialized = false;  // the layout is chosen afresh
-    c->brick = brick_for_tiles(c);
-    int st = LBM_OK;
-    for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
-        const long long cnt = std::min(chunk, c->n - first);
-        std::memcpy(stage.data(), rho + first, (size_t)cnt * sizeof(double));
-        for (int k = 0; k < 3; ++k)
-            std::memcpy(stage.data() + (size_t)(k + 1) * cnt, u + (size_t)k * c->n + first, (size_t)cnt * sizeof(double));
-        hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 4 * sizeof(double), hipMemcpyHostToDevice,
-                                      c->stream);
-        if (e == hipSuccess)
-            e = launch_init_moments(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("init_moments: ") + hipGetErrorString(e));
-    }
-    (void)hipFree(tmp);
-    if (st != LBM_OK) return st;
-    c->steps = 0;
-    c->layout_s = 0;
-    c->layout_spec = (c->bc != kBB);
-    c->initialized = true;
-    st = reset_flags(c);
-    if (st != LBM_OK) return st;
-    LBM_HIP(c, hipStreamSynchronize(c->stream));
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c || !rho || !u) return fail(c, LBM_E_ARG, "null argument");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is initialised through its batch");
+        if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+        for (long long i = 0; i < c->n; ++i) {
+            const double r = rho[i], x = u[i], y = u[c->n + i], z = u[2 * c->n + i];
+            if (!(r > 0.0) || !std::isfinite(r) || !std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+                return fail(c, LBM_E_ARG, "need finite moments and rho > 0");
+        }
+        DeviceGuard dg(c->dev);
+        const long long chunk = std::min<long long>(c->n, 1ll << 24);
+        double* tmp = nullptr;
+        LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 4 * sizeof(double)));
+        std::vector<double> stage((size_t)chunk * 4);
+        c->initialized = false;  // the layout is chosen afresh
+        c->brick = brick_for_tiles(c);
+        int st = LBM_OK;
+        for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
+            const long long cnt = std::min(chunk, c->n - first);
+            std::memcpy(stage.data(), rho + first, (size_t)cnt * sizeof(double));
+            for (int k = 0; k < 3; ++k)
+                std::memcpy(stage.data() + (size_t)(k + 1) * cnt, u + (size_t)k * c->n + first, (size_t)cnt * sizeof(double));
+            hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 4 * sizeof(double), hipMemcpyHostToDevice,
+                                          c->stream);
+            if (e == hipSuccess)
+                e = launch_init_moments(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("init_moments: ") + hipGetErrorString(e));
+        }
+        (void)hipFree(tmp);
+        if (st != LBM_OK) return st;
+        c->steps = 0;
+        c->layout_s = 0;
+        c->layout_spec = (c->bc != kBB);
+        c->initialized = true;
+        st = reset_flags(c);
+        if (st != LBM_OK) return st;
+        LBM_HIP(c, hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    });
 }
 
 int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
 {
-    if (!c || !in) return fail(c, LBM_E_ARG, "null argument");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's state is set through its batch");
-    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
-    if (steps < 0) return fail(c, LBM_E_ARG, "steps must be >= 0");
-    DeviceGuard dg(c->dev);
-    const long long chunk = std::min<long long>(c->n, 1ll << 24);
-    double* tmp = nullptr;
-    LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
-    std::vector<double> stage((size_t)chunk * 19);
-    c->initialized = false;  // the layout is chosen afresh
-    c->brick = brick_for_tiles(c);
-    int st = LBM_OK;
-    for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
-        const long long cnt = std::min(chunk, c->n - first);
-        for (int a = 0; a < 19; ++a)
-            std::memcpy(stage.data() + (size_t)a * cnt, in + (size_t)a * c->n + first, (size_t)cnt * sizeof(double));
-        hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 19 * sizeof(double), hipMemcpyHostToDevice,
-                                      c->stream);
-        if (e == hipSuccess)
-            e = launch_set_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("set_state: ") + hipGetErrorString(e));
-    }
-    (void)hipFree(tmp);
-    if (st != LBM_OK) return st;
-    c->steps = steps;
-    c->layout_s = 0;
-    c->layout_spec = (c->bc != kBB);
-    c->initialized = true;
-    st = reset_flags(c);
-    if (st != LBM_OK) return st;
-    LBM_HIP(c, hipStreamSynchronize(c->stream));
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c || !in) return fail(c, LBM_E_ARG, "null argument");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance's state is set through its batch");
+        if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+        if (steps < 0) return fail(c, LBM_E_ARG, "steps must be >= 0");
+        DeviceGuard dg(c->dev);
+        const long long chunk = std::min<long long>(c->n, 1ll << 24);
+        double* tmp = nullptr;
+        LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
+        std::vector<double> stage((size_t)chunk * 19);
+        c->initialized = false;  // the layout is chosen afresh
+        c->brick = brick_for_tiles(c);
+        int st = LBM_OK;
+        for (long long first = 0; first < c->n && st == LBM_OK; first += chunk) {
+            const long long cnt = std::min(chunk, c->n - first);
+            for (int a = 0; a < 19; ++a)
+                std::memcpy(stage.data() + (size_t)a * cnt, in + (size_t)a * c->n + first, (size_t)cnt * sizeof(double));
+            hipError_t e = hipMemcpyAsync(tmp, stage.data(), (size_t)cnt * 19 * sizeof(double), hipMemcpyHostToDevice,
+                                          c->stream);
+            if (e == hipSuccess)
+                e = launch_set_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, first, cnt, tmp, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) st = fail(c, LBM_E_DEVICE, std::string("set_state: ") + hipGetErrorString(e));
+        }
+        (void)hipFree(tmp);
+        if (st != LBM_OK) return st;
+        c->steps = steps;
+        c->layout_s = 0;
+        c->layout_spec = (c->bc != kBB);
+        c->initialized = true;
+        st = reset_flags(c);
+        if (st != LBM_OK) return st;
+        LBM_HIP(c, hipStreamSynchronize(c->stream));
+        return LBM_OK;
+    });
 }
 
 static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, double* out)
@@ -809,22 +860,26 @@ static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, dou
 
 int lbm_get_state(lbm_ctx* c, double* out)
 {
-    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
-    return get_state_impl(c, c->n, nullptr, out);
+    return guard(c, [&]() -> int {
+        if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+        return get_state_impl(c, c->n, nullptr, out);
+    });
 }
 
 int lbm_get_state_cells(lbm_ctx* c, int64_t n, const int64_t* cells, double* out)
 {
-    if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
-    if (n == 0) return LBM_OK;
-    return get_state_impl(c, n, cells, out);
+    return guard(c, [&]() -> int {
+        if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
+        if (n == 0) return LBM_OK;
+        return get_state_impl(c, n, cells, out);
+    });
 }
 
 // The per-row Smagorinsky factor 18 Cs^2 (1 - exp(-y+/A+))^2 with
 // y+ = d u_tau / nu0, d = min(y, ny - 1 - y) + y1 (the first-layer distance
 // rule) and u_tau the given friction velocity or sqrt(|Fx| ny / 2) from the
 // force balance; uploaded in stream order when a parameter changed.
-int refresh_damping(lbm_ctx* c, hipStream_t s)
+static int refresh_damping(lbm_ctx* c, hipStream_t s)
 {
     if (!(c->vd_aplus > 0.0) || !c->cs2_dirty) return LBM_OK;
     const double nu0 = (c->tau0 - 0.5) / 3.0;
@@ -844,72 +899,83 @@ int refresh_damping(lbm_ctx* c, hipStream_t s)
 
 int lbm_step(lbm_ctx* c, int64_t n)
 {
-    int st = check_ready(c);
-    if (st != LBM_OK) return st;
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is stepped by lbm_batch_step");
-    if (n < 0) return fail(c, LBM_E_ARG, "n must be >= 0");
-    if (n == 0) return LBM_OK;
-    DeviceGuard dg(c->dev);
-    if ((st = fix_layout(c)) != LBM_OK) return st;
-    if ((st = ensure_partials(c)) != LBM_OK) return st;
-    if ((st = refresh_damping(c, c->stream)) != LBM_OK) return st;
-    long long left = n;
-    while (left > 0) {
-        if (c->graph_steps > 0 && left >= c->graph_steps) {
-            const long long L = c->graph_steps;
-            GraphKey key{c->layout_s, (int)L, c->stats_every, c->stats_every > 0 ? c->steps % c->stats_every : 0};
-            auto it = c->graphs.find(key);
-            if (it == c->graphs.end()) {
-                if (!c->cap_stream) LBM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-                hipGraph_t g = nullptr;
-                LBM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = enqueue_steps(c, c->cap_stream, c->layout_s, c->steps, L);
-                hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
-                if (e != hipSuccess || e2 != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return fail(c, LBM_E_DEVICE, std::string("graph capture: ") +
-                                                     hipGetErrorString(e != hipSuccess ? e : e2));
+    return guard(c, [&]() -> int {
+        int st = check_ready(c);
+        if (st != LBM_OK) return st;
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch instance is stepped by lbm_batch_step");
+        if (n < 0) return fail(c, LBM_E_ARG, "n must be >= 0");
+        if (n == 0) return LBM_OK;
+        DeviceGuard dg(c->dev);
+        if ((st = fix_layout(c)) != LBM_OK) return st;
+        if ((st = ensure_partials(c)) != LBM_OK) return st;
+        if ((st = refresh_damping(c, c->stream)) != LBM_OK) return st;
+        long long left = n;
+        while (left > 0) {
+            if (c->graph_steps > 0 && left >= c->graph_steps) {
+                const long long L = c->graph_steps;
+                GraphKey key{c->layout_s, (int)L, c->stats_every, c->stats_every > 0 ? c->steps % c->stats_every : 0};
+                auto it = c->graphs.find(key);
+                if (it == c->graphs.end()) {
+                    if (!c->cap_stream) LBM_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+                    hipGraph_t g = nullptr;
+                    LBM_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+                    hipError_t e = enqueue_steps(c, c->cap_stream, c->layout_s, c->steps, L);
+                    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+                    if (e != hipSuccess || e2 != hipSuccess) {
+                        if (g) (void)hipGraphDestroy(g);
+                        return fail(c, LBM_E_DEVICE, std::string("graph capture: ") +
+                                                         hipGetErrorString(e != hipSuccess ? e : e2));
+                    }
+                    hipGraphExec_t ex = nullptr;
+                    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                    try {
+                        it = c->graphs.emplace(key, ex).first;
+                    } catch (...) {
+                        (void)hipGraphExecDestroy(ex);
+                        throw;
+                    }
                 }
-                hipGraphExec_t ex = nullptr;
-                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-                it = c->graphs.emplace(key, ex).first;
+                LBM_HIP(c, hipGraphLaunch(it->second, c->stream));
+                advance_bookkeeping(c, L);
+                left -= L;
+            } else {
+                LBM_HIP(c, enqueue_steps(c, c->stream, c->layout_s, c->steps, 1));
+                advance_bookkeeping(c, 1);
+                left -= 1;
             }
-            LBM_HIP(c, hipGraphLaunch(it->second, c->stream));
-            advance_bookkeeping(c, L);
-            left -= L;
-        } else {
-            LBM_HIP(c, enqueue_steps(c, c->stream, c->layout_s, c->steps, 1));
-            advance_bookkeeping(c, 1);
-            left -= 1;
         }
-    }
-    return LBM_OK;
+        return LBM_OK;
+    });
 }
 
 int lbm_sync(lbm_ctx* c, int64_t* first_bad)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (first_bad) *first_bad = -1;
-    if (!c->dflags) return LBM_OK;
-    DeviceGuard dg(c->dev);
-    DevFlags f;
-    int st = read_flags(c, &f);
-    if (st != LBM_OK) return st;
-    st = status_of(f);
-    if (st != LBM_OK) {
-        if (first_bad) *first_bad = (int64_t)f.first_bad;
-        return fail(c, st, std::string(lbm_status_str(st)) + " at step " + std::to_string((long long)f.first_bad));
-    }
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (first_bad) *first_bad = -1;
+        if (!c->dflags) return LBM_OK;
+        DeviceGuard dg(c->dev);
+        DevFlags f;
+        int st = read_flags(c, &f);
+        if (st != LBM_OK) return st;
+        st = status_of(f);
+        if (st != LBM_OK) {
+            if (first_bad) *first_bad = (int64_t)f.first_bad;
+            return fail(c, st, std::string(lbm_status_str(st)) + " at step " + std::to_string((long long)f.first_bad));
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_steps_done(const lbm_ctx* c, int64_t* s)
 {
-    if (!c || !s) return fail(nullptr, LBM_E_ARG, "null argument");
-    *s = c->steps;
-    return LBM_OK;
+    return guard(const_cast<lbm_ctx*>(c), [&]() -> int {
+        if (!c || !s) return fail(nullptr, LBM_E_ARG, "null argument");
+        *s = c->steps;
+        return LBM_OK;
+    });
 }
 
 static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* cells, double* out, int* iters,
@@ -974,285 +1040,343 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
 
 int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    std::vector<double> buf;
-    try {
-        buf.resize((size_t)c->n * 4);
-    } catch (...) {
-        return fail(c, LBM_E_OOM, "host buffer allocation failed");
-    }
-    int st = observe_impl(c, 0, c->n, nullptr, buf.data(), nullptr);
-    if (st != LBM_OK) return st;
-    for (long long i = 0; i < c->n; ++i) {
-        if (rho) rho[i] = buf[4 * i];
-        if (ux) ux[i] = buf[4 * i + 1];
-        if (uy) uy[i] = buf[4 * i + 2];
-        if (uz) uz[i] = buf[4 * i + 3];
-    }
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        std::vector<double> buf;
+        try {
+            buf.resize((size_t)c->n * 4);
+        } catch (...) {
+            return fail(c, LBM_E_OOM, "host buffer allocation failed");
+        }
+        int st = observe_impl(c, 0, c->n, nullptr, buf.data(), nullptr);
+        if (st != LBM_OK) return st;
+        for (long long i = 0; i < c->n; ++i) {
+            if (rho) rho[i] = buf[4 * i];
+            if (ux) ux[i] = buf[4 * i + 1];
+            if (uy) uy[i] = buf[4 * i + 2];
+            if (uz) uz[i] = buf[4 * i + 3];
+        }
+        return LBM_OK;
+    });
+}
+
+int lbm_moments_device(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz)
+{
+    return guard(c, [&]() -> int {
+        int st = check_ready(c);
+        if (st != LBM_OK) return st;
+        double* outs[4] = {rho, ux, uy, uz};
+        bool any = false;
+        for (double* p : outs) {
+            if (!p) continue;
+            any = true;
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+                attr.device != c->dev)
+                return fail(c, LBM_E_ARG, "moment arrays must be device memory on the context's device");
+        }
+        if (!any) return fail(c, LBM_E_ARG, "no output array given");
+        DeviceGuard dg(c->dev);
+        if ((st = fix_layout(c)) != LBM_OK) return st;
+        ObsArgs a = obs_args(c);
+        a.mode = 0;
+        a.cells = nullptr;
+        a.first = 0;
+        a.count = c->n;
+        a.out = nullptr;
+        for (int k = 0; k < 4; ++k) a.soa[k] = outs[k];
+        a.iters = nullptr;
+        a.dmass = nullptr;
+        LBM_HIP(c, launch_observe(c->store, a, c->stream));
+        return LBM_OK;
+    });
 }
 
 int lbm_moments_cells(lbm_ctx* c, int64_t n, const int64_t* cells, double* out)
 {
-    if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
-    if (n == 0) return LBM_OK;
-    return observe_impl(c, 0, n, cells, out, nullptr);
+    return guard(c, [&]() -> int {
+        if (!c || !cells || !out || n < 0) return fail(c, LBM_E_ARG, "bad argument");
+        if (n == 0) return LBM_OK;
+        return observe_impl(c, 0, n, cells, out, nullptr);
+    });
 }
 
 int lbm_wall_shear(lbm_ctx* c, double* tx, double* tz, double* ut, double* U)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    const long long m = 2ll * c->nx * c->nz;
-    std::vector<double> buf((size_t)m * 4);
-    int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr);
-    if (st != LBM_OK) return st;
-    for (long long i = 0; i < m; ++i) {
-        if (tx) tx[i] = buf[4 * i];
-        if (tz) tz[i] = buf[4 * i + 1];
-        if (ut) ut[i] = buf[4 * i + 2];
-        if (U) U[i] = buf[4 * i + 3];
-    }
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        const long long m = 2ll * c->nx * c->nz;
+        std::vector<double> buf((size_t)m * 4);
+        int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr);
+        if (st != LBM_OK) return st;
+        for (long long i = 0; i < m; ++i) {
+            if (tx) tx[i] = buf[4 * i];
+            if (tz) tz[i] = buf[4 * i + 1];
+            if (ut) ut[i] = buf[4 * i + 2];
+            if (U) U[i] = buf[4 * i + 3];
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_wall_mass_change(lbm_ctx* c, double* dsum, double* rho)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (!dsum && !rho) return fail(c, LBM_E_ARG, "null argument");
-    const long long m = 2ll * c->nx * c->nz;
-    std::vector<double> buf((size_t)m * 4), dm((size_t)m * 2);
-    int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr, dm.data());
-    if (st != LBM_OK) return st;
-    for (long long i = 0; i < m; ++i) {
-        if (dsum) dsum[i] = dm[2 * i];
-        if (rho) rho[i] = dm[2 * i + 1];
-    }
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (!dsum && !rho) return fail(c, LBM_E_ARG, "null argument");
+        const long long m = 2ll * c->nx * c->nz;
+        std::vector<double> buf((size_t)m * 4), dm((size_t)m * 2);
+        int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr, dm.data());
+        if (st != LBM_OK) return st;
+        for (long long i = 0; i < m; ++i) {
+            if (dsum) dsum[i] = dm[2 * i];
+            if (rho) rho[i] = dm[2 * i + 1];
+        }
+        return LBM_OK;
+    });
 }
 
 int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std)
 {
-    if (!c || !counts || !mean_std) return fail(c, LBM_E_ARG, "null argument");
-    if (nbins < 1 || nbins > (1 << 20) || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
-        return fail(c, LBM_E_ARG, "need 1 <= nbins <= 2^20 and finite lo < hi");
-    int st = check_ready(c);
-    if (st != LBM_OK) return st;
-    DeviceGuard dg(c->dev);
-    if ((st = fix_layout(c)) != LBM_OK) return st;
-    if ((st = sync_check(c)) != LBM_OK) return st;
-    const long long m = 2ll * c->nx * c->nz;
-    double* rec = nullptr;
-    double* ms = nullptr;
-    unsigned long long* dcnt = nullptr;
-    hipError_t e = hipMalloc((void**)&rec, (size_t)m * 4 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&ms, 2 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&dcnt, (size_t)(nbins + 2) * sizeof(unsigned long long));
-    std::vector<unsigned long long> hc((size_t)nbins + 2);
-    double hms[2] = {0.0, 0.0};
-    if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)(nbins + 2) * sizeof(unsigned long long), c->stream);
-    if (e == hipSuccess) {
-        ObsArgs a = obs_args(c);
-        a.mode = 1;
-        a.cells = nullptr;
-        a.first = 0;
-        a.count = m;
-        a.out = rec;
-        a.iters = nullptr;
-        e = launch_observe(c->store, a, c->stream);
-    }
-    const double nu0 = (c->tau0 - 0.5) / 3.0;
-    if (e == hipSuccess)
-        e = launch_yplus_pdf(rec, m, c->y1, nu0, ms, lo, (double)nbins / (hi - lo), nbins, dcnt, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hms, ms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hc.data(), dcnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (rec) (void)hipFree(rec);
-    if (ms) (void)hipFree(ms);
-    if (dcnt) (void)hipFree(dcnt);
-    if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("wall y+ distribution: ") + hipGetErrorString(e));
-    for (size_t i = 0; i < hc.size(); ++i) counts[i] = (int64_t)hc[i];
-    mean_std[0] = hms[0];
-    mean_std[1] = hms[1];
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c || !counts || !mean_std) return fail(c, LBM_E_ARG, "null argument");
+        if (nbins < 1 || nbins > (1 << 20) || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+            return fail(c, LBM_E_ARG, "need 1 <= nbins <= 2^20 and finite lo < hi");
+        int st = check_ready(c);
+        if (st != LBM_OK) return st;
+        DeviceGuard dg(c->dev);
+        if ((st = fix_layout(c)) != LBM_OK) return st;
+        if ((st = sync_check(c)) != LBM_OK) return st;
+        const long long m = 2ll * c->nx * c->nz;
+        double* rec = nullptr;
+        double* ms = nullptr;
+        unsigned long long* dcnt = nullptr;
+        hipError_t e = hipMalloc((void**)&rec, (size_t)m * 4 * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&ms, 2 * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&dcnt, (size_t)(nbins + 2) * sizeof(unsigned long long));
+        std::vector<unsigned long long> hc((size_t)nbins + 2);
+        double hms[2] = {0.0, 0.0};
+        if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)(nbins + 2) * sizeof(unsigned long long), c->stream);
+        if (e == hipSuccess) {
+            ObsArgs a = obs_args(c);
+            a.mode = 1;
+            a.cells = nullptr;
+            a.first = 0;
+            a.count = m;
+            a.out = rec;
+            a.iters = nullptr;
+            e = launch_observe(c->store, a, c->stream);
+        }
+        const double nu0 = (c->tau0 - 0.5) / 3.0;
+        if (e == hipSuccess)
+            e = launch_yplus_pdf(rec, m, c->y1, nu0, ms, lo, (double)nbins / (hi - lo), nbins, dcnt, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(hms, ms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(hc.data(), dcnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (rec) (void)hipFree(rec);
+        if (ms) (void)hipFree(ms);
+        if (dcnt) (void)hipFree(dcnt);
+        if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("wall y+ distribution: ") + hipGetErrorString(e));
+        for (size_t i = 0; i < hc.size(); ++i) counts[i] = (int64_t)hc[i];
+        mean_std[0] = hms[0];
+        mean_std[1] = hms[1];
+        return LBM_OK;
+    });
 }
 
 int lbm_stats_reset(lbm_ctx* c)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
-    DeviceGuard dg(c->dev);
-    LBM_HIP(c, hipStreamSynchronize(c->stream));
-    LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
-    c->nsamples = 0;
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
+        DeviceGuard dg(c->dev);
+        LBM_HIP(c, hipStreamSynchronize(c->stream));
+        LBM_HIP(c, hipMemset(c->dacc, 0, (size_t)c->ny * 8 * sizeof(double)));
+        c->nsamples = 0;
+        return LBM_OK;
+    });
 }
 
 int lbm_stats_sums(lbm_ctx* c, double* out, int64_t* nsamples)
 {
-    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
-    if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
-    DeviceGuard dg(c->dev);
-    int st = sync_check(c);
-    if (st != LBM_OK) return st;
-    LBM_HIP(c, hipMemcpy(out, c->dacc, (size_t)c->ny * 8 * sizeof(double), hipMemcpyDeviceToHost));
-    if (nsamples) *nsamples = c->nsamples;
-    return LBM_OK;
+    return guard(c, [&]() -> int {
+        if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+        if (!c->dacc) return fail(c, LBM_E_STATE, "no storage bound");
+        DeviceGuard dg(c->dev);
+        int st = sync_check(c);
+        if (st != LBM_OK) return st;
+        LBM_HIP(c, hipMemcpy(out, c->dacc, (size_t)c->ny * 8 * sizeof(double), hipMemcpyDeviceToHost));
+        if (nsamples) *nsamples = c->nsamples;
+        return LBM_OK;
+    });
 }
 
 int lbm_stats_get(lbm_ctx* c, double* out, int64_t* nsamples)
 {
-    if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
-    std::vector<double> s((size_t)c->ny * 8);
-    int st = lbm_stats_sums(c, s.data(), nsamples);
-    if (st != LBM_OK) return st;
-    for (int y = 0; y < c->ny; ++y) {
-        const double* r = &s[(size_t)y * 8];
-        double* o = out + (size_t)y * 8;
-        const double m = r[7];
-        if (m <= 0.0) {
-            for (int k = 0; k < 8; ++k) o[k] = 0.0;
-            continue;
+    return guard(c, [&]() -> int {
+        if (!c || !out) return fail(c, LBM_E_ARG, "null argument");
+        std::vector<double> s((size_t)c->ny * 8);
+        int st = lbm_stats_sums(c, s.data(), nsamples);
+        if (st != LBM_OK) return st;
+        for (int y = 0; y < c->ny; ++y) {
+            const double* r = &s[(size_t)y * 8];
+            double* o = out + (size_t)y * 8;
+            const double m = r[7];
+            if (m <= 0.0) {
+                for (int k = 0; k < 8; ++k) o[k] = 0.0;
+                continue;
+            }
+            const double mx = r[0] / m, my = r[1] / m, mz = r[2] / m;
+            o[0] = mx; o[1] = my; o[2] = mz;
+            o[3] = r[3] / m - mx * mx;
+            o[4] = r[4] / m - my * my;
+            o[5] = r[5] / m - mz * mz;
+            o[6] = r[6] / m - mx * my;
+            o[7] = m;
         }
-        const double mx = r[0] / m, my = r[1] / m, mz = r[2] / m;
-        o[0] = mx; o[1] = my; o[2] = mz;
-        o[3] = r[3] / m - mx * mx;
-        o[4] = r[4] / m - my * my;
-        o[5] = r[5] / m - mz * mz;
-        o[6] = r[6] / m - mx * my;
-        o[7] = m;
-    }
-    return LBM_OK;
+        return LBM_OK;
+    });
 }
 
 int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
 {
-    if (!c) return fail(nullptr, LBM_E_ARG, "null context");
-    if (c->batch_member) return fail(c, LBM_E_STATE, "a batch is tuned with lbm_batch_autotune");
-    if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
-    if (c->initialized) return fail(c, LBM_E_STATE, "autotune runs before the state is initialised");
-    if (steps < 2) return fail(c, LBM_E_ARG, "steps must be >= 2");
-    DeviceGuard dg(c->dev);
-    // a representative state: the initial profile the body force implies
-    const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
-    int st = init_spalding_impl(c, ut, 0.05, 0);
-    if (st != LBM_OK) return st;
-    c->initialized = false;  // a timing state only: each candidate takes the layout its shapes want
-    const int tcand[4] = {64, 128, 256, 512};
-    const int vcand[3] = {1, 2, 4};
-    hipEvent_t ev[3];
-    for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
-    // the odd and even kernels are timed separately; the group width is shared
-    float best = 1e30f;
-    int bo = c->tile_odd, be = c->tile_even, bv = vector_width(c);
-    hipError_t err = hipSuccess;
-    for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
-        if (!step_vector_width_ok(c->store, c->nx, vcand[iv])) continue;
-        c->vw_req = vcand[iv];
-        float bo_t = 1e30f, be_t = 1e30f;
-        int bo_k = 256, be_k = 256;
-        for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-            c->tile_odd = c->tile_even = tcand[k];
-            float to = 0.f, te = 0.f;
-            // one warm-up pair, then timed pairs
-            for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
-                const StepArgs ao = step_args(c, true, c->odd_rows), ae = step_args(c, false, c->odd_rows);
-                err = hipEventRecord(ev[0], c->stream);
-                if (err == hipSuccess) err = launch_step(c->store, true, c->bc, ao, c->stream);
-                if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
-                if (err == hipSuccess) err = launch_step(c->store, false, c->bc, ae, c->stream);
-                if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
-                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
-                float a = 0.f, b = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
-                if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
-                if (r > 0) {
-                    to += a;
-                    te += b;
+    return guard(c, [&]() -> int {
+        if (!c) return fail(nullptr, LBM_E_ARG, "null context");
+        if (c->batch_member) return fail(c, LBM_E_STATE, "a batch is tuned with lbm_batch_autotune");
+        if (!c->h) return fail(c, LBM_E_STATE, "no storage bound");
+        if (c->initialized) return fail(c, LBM_E_STATE, "autotune runs before the state is initialised");
+        if (steps < 2) return fail(c, LBM_E_ARG, "steps must be >= 2");
+        DeviceGuard dg(c->dev);
+        // a representative state: the initial profile the body force implies
+        const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
+        int st = init_spalding_impl(c, ut, 0.05, 0);
+        if (st != LBM_OK) return st;
+        c->initialized = false;  // a timing state only: each candidate takes the layout its shapes want
+        const int tcand[4] = {64, 128, 256, 512};
+        const int vcand[3] = {1, 2, 4};
+        hipEvent_t ev[3];
+        for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
+        // the odd and even kernels are timed separately; the group width is shared
+        float best = 1e30f;
+        int bo = c->tile_odd, be = c->tile_even, bv = vector_width(c);
+        hipError_t err = hipSuccess;
+        for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
+            if (!step_vector_width_ok(c->store, c->nx, vcand[iv])) continue;
+            c->vw_req = vcand[iv];
+            float bo_t = 1e30f, be_t = 1e30f;
+            int bo_k = 256, be_k = 256;
+            for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+                c->tile_odd = c->tile_even = tcand[k];
+                float to = 0.f, te = 0.f;
+                // one warm-up pair, then timed pairs
+                for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
+                    const StepArgs ao = step_args(c, true, c->odd_rows), ae = step_args(c, false, c->odd_rows);
+                    err = hipEventRecord(ev[0], c->stream);
+                    if (err == hipSuccess) err = launch_step(c->store, true, c->bc, ao, c->stream);
+                    if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
+                    if (err == hipSuccess) err = launch_step(c->store, false, c->bc, ae, c->stream);
+                    if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
+                    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                    float a = 0.f, b = 0.f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
+                    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
+                    if (r > 0) {
+                        to += a;
+                        te += b;
+                    }
                 }
+                if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
+                if (te < be_t) { be_t = te; be_k = tcand[k]; }
             }
-            if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
-            if (te < be_t) { be_t = te; be_k = tcand[k]; }
+            if (bo_t + be_t < best) {
+                best = bo_t + be_t;
+                bo = bo_k;
+                be = be_k;
+                bv = vcand[iv];
+            }
         }
-        if (bo_t + be_t < best) {
-            best = bo_t + be_t;
-            bo = bo_k;
-            be = be_k;
-            bv = vcand[iv];
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        c->tile_odd = bo;
+        c->tile_even = be;
+        c->vw_req = bv;
+        c->initialized = false;
+        drop_graphs(c);
+        if (err != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+        DevFlags f;
+        if ((st = read_flags(c, &f)) != LBM_OK) return st;
+        if (tiles) {
+            tiles[0] = bo;
+            tiles[1] = be;
+            tiles[2] = bv;
         }
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    c->tile_odd = bo;
-    c->tile_even = be;
-    c->vw_req = bv;
-    c->initialized = false;
-    drop_graphs(c);
-    if (err != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
-    DevFlags f;
-    if ((st = read_flags(c, &f)) != LBM_OK) return st;
-    if (tiles) {
-        tiles[0] = bo;
-        tiles[1] = be;
-        tiles[2] = bv;
-    }
-    return LBM_OK;
+        return LBM_OK;
+    });
 }
 
 int lbm_spalding_uplus(double yplus, double kappa, double B, double* uplus)
 {
-    if (!uplus || !std::isfinite(yplus) || yplus < 0.0 || !(kappa > 0.0) || !std::isfinite(B))
-        return fail(nullptr, LBM_E_ARG, "need y+ >= 0, kappa > 0, finite B");
-    *uplus = spalding_uplus_host(yplus, kappa, B);
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (!uplus || !std::isfinite(yplus) || yplus < 0.0 || !(kappa > 0.0) || !std::isfinite(B))
+            return fail(nullptr, LBM_E_ARG, "need y+ >= 0, kappa > 0, finite B");
+        *uplus = spalding_uplus_host(yplus, kappa, B);
+        return LBM_OK;
+    });
 }
 
 int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, double kappa, double B, double tol,
                          int32_t maxit, double* ut, int32_t* iters)
 {
-    if (n < 0 || (n > 0 && (!U || !ut || !iters))) return fail(nullptr, LBM_E_ARG, "bad argument");
-    if (!(y1 > 0) || !(nu > 0) || !(kappa > 0) || !(tol > 0) || maxit < 1) return fail(nullptr, LBM_E_ARG, "bad parameter");
-    if (n == 0) return LBM_OK;
-    double *dU = nullptr, *dut = nullptr;
-    int* dit = nullptr;
-    hipError_t e = hipMalloc((void**)&dU, (size_t)n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&dut, (size_t)n * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&dit, (size_t)n * sizeof(int));
-    if (e == hipSuccess) e = hipMemcpy(dU, U, (size_t)n * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_wall_utau(dU, n, y1, nu, kappa, B, tol, maxit, dut, dit, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(ut, dut, (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(iters, dit, (size_t)n * sizeof(int), hipMemcpyDeviceToHost);
-    if (dU) (void)hipFree(dU);
-    if (dut) (void)hipFree(dut);
-    if (dit) (void)hipFree(dit);
-    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("device wall solve: ") + hipGetErrorString(e));
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (n < 0 || (n > 0 && (!U || !ut || !iters))) return fail(nullptr, LBM_E_ARG, "bad argument");
+        if (!(y1 > 0) || !(nu > 0) || !(kappa > 0) || !(tol > 0) || maxit < 1) return fail(nullptr, LBM_E_ARG, "bad parameter");
+        if (n == 0) return LBM_OK;
+        double *dU = nullptr, *dut = nullptr;
+        int* dit = nullptr;
+        hipError_t e = hipMalloc((void**)&dU, (size_t)n * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&dut, (size_t)n * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc((void**)&dit, (size_t)n * sizeof(int));
+        if (e == hipSuccess) e = hipMemcpy(dU, U, (size_t)n * sizeof(double), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_wall_utau(dU, n, y1, nu, kappa, B, tol, maxit, dut, dit, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(ut, dut, (size_t)n * sizeof(double), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(iters, dit, (size_t)n * sizeof(int), hipMemcpyDeviceToHost);
+        if (dU) (void)hipFree(dU);
+        if (dut) (void)hipFree(dut);
+        if (dit) (void)hipFree(dit);
+        if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("device wall solve: ") + hipGetErrorString(e));
+        return LBM_OK;
+    });
 }
 
 int lbm_codec_roundtrip(int store, int64_t n, const float* in, float* out)
 {
-    if (store < 0 || store > 3 || n < 0 || (n > 0 && (!in || !out)))
-        return fail(nullptr, LBM_E_ARG, "bad argument");
-    if (n == 0) return LBM_OK;
-    float *din = nullptr, *dout = nullptr;
-    hipError_t e = hipMalloc((void**)&din, (size_t)n * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void**)&dout, (size_t)n * sizeof(float));
-    if (e == hipSuccess) e = hipMemcpy(din, in, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_codec(store, din, dout, n, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
-    if (din) (void)hipFree(din);
-    if (dout) (void)hipFree(dout);
-    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("codec round trip: ") + hipGetErrorString(e));
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (store < 0 || store > 3 || n < 0 || (n > 0 && (!in || !out)))
+            return fail(nullptr, LBM_E_ARG, "bad argument");
+        if (n == 0) return LBM_OK;
+        float *din = nullptr, *dout = nullptr;
+        hipError_t e = hipMalloc((void**)&din, (size_t)n * sizeof(float));
+        if (e == hipSuccess) e = hipMalloc((void**)&dout, (size_t)n * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(din, in, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_codec(store, din, dout, n, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess) e = hipMemcpy(out, dout, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+        if (din) (void)hipFree(din);
+        if (dout) (void)hipFree(dout);
+        if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("codec round trip: ") + hipGetErrorString(e));
+        return LBM_OK;
+    });
 }
 
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* s)
 {
-    if (!dst || !src || bytes % 16 != 0) return fail(nullptr, LBM_E_ARG, "need device pointers and bytes % 16 == 0");
-    hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)s);
-    if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
-    return LBM_OK;
+    return guard(nullptr, [&]() -> int {
+        if (!dst || !src || bytes % 16 != 0) return fail(nullptr, LBM_E_ARG, "need device pointers and bytes % 16 == 0");
+        hipError_t e = launch_copy(src, dst, bytes, (hipStream_t)s);
+        if (e != hipSuccess) return fail(nullptr, LBM_E_DEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+        return LBM_OK;
+    });
 }
 
 }  // extern "C"
@@ -1292,6 +1416,28 @@ int bfail(lbm_batch* b, int code, const std::string& msg)
     return code;
 }
 
+int bfail_nothrow(lbm_batch* b, int code, const char* msg) noexcept
+{
+    try {
+        if (b) b->err = msg;
+        else g_err = msg;
+    } catch (...) {
+    }
+    return code;
+}
+
+template <typename F>
+int bguard(lbm_batch* b, F&& body) noexcept
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc&) {
+        return bfail_nothrow(b, LBM_E_OOM, "host memory allocation failed");
+    } catch (...) {
+        return bfail_nothrow(b, LBM_E_STATE, "internal error (exception)");
+    }
+}
+
 #define LBM_BHIP(b, call)                                                                        \
     do {                                                                                         \
         hipError_t e_ = (call);                                                                  \
@@ -1316,6 +1462,8 @@ int batch_width(const lbm_batch* b)
 
 void batch_drop_graphs(lbm_batch* b)
 {
+    if (b->graphs.empty()) return;
+    (void)hipStreamSynchronize(b->stream);
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
 }
@@ -1422,28 +1570,30 @@ extern "C" {
 int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const double* Cs, const double* Fx,
                      const int32_t* bc, double kappa, double B, lbm_batch** out)
 {
-    if (n < 1 || !grids || !tau || !Cs || !Fx || !bc || !out) return bfail(nullptr, LBM_E_ARG, "bad argument");
-    for (int i = 0; i < n; ++i)
-        if (bc[i] != LBM_BB && bc[i] != LBM_WFB && bc[i] != LBM_FREESLIP)
-            return bfail(nullptr, LBM_E_ARG, "unknown boundary of instance " + std::to_string(i));
-    lbm_batch* b = new (std::nothrow) lbm_batch();
-    if (!b) return bfail(nullptr, LBM_E_OOM, "batch allocation failed");
-    b->n = n;
-    for (int i = 0; i < n; ++i) {
-        lbm_ctx* c = nullptr;
-        int st = lbm_create(&grids[i], tau[i], Cs[i], kappa, B, Fx[i], &c);
-        if (st != LBM_OK) {
-            std::string msg = "instance " + std::to_string(i) + ": " + g_err;
-            for (lbm_ctx* q : b->inst) lbm_destroy(q);
-            delete b;
-            return bfail(nullptr, st, msg);
+    return guard(nullptr, [&]() -> int {
+        if (n < 1 || !grids || !tau || !Cs || !Fx || !bc || !out) return bfail(nullptr, LBM_E_ARG, "bad argument");
+        for (int i = 0; i < n; ++i)
+            if (bc[i] != LBM_BB && bc[i] != LBM_WFB && bc[i] != LBM_FREESLIP)
+                return bfail(nullptr, LBM_E_ARG, "unknown boundary of instance " + std::to_string(i));
+        lbm_batch* b = new (std::nothrow) lbm_batch();
+        if (!b) return bfail(nullptr, LBM_E_OOM, "batch allocation failed");
+        b->n = n;
+        for (int i = 0; i < n; ++i) {
+            lbm_ctx* c = nullptr;
+            int st = lbm_create(&grids[i], tau[i], Cs[i], kappa, B, Fx[i], &c);
+            if (st != LBM_OK) {
+                std::string msg = "instance " + std::to_string(i) + ": " + g_err;
+                for (lbm_ctx* q : b->inst) lbm_destroy(q);
+                delete b;
+                return bfail(nullptr, st, msg);
+            }
+            c->bc = bc[i];
+            c->graph_steps = 0;
+            b->inst.push_back(c);
         }
-        c->bc = bc[i];
-        c->graph_steps = 0;
-        b->inst.push_back(c);
-    }
-    *out = b;
-    return LBM_OK;
+        *out = b;
+        return LBM_OK;
+    });
 }
 
 void lbm_batch_destroy(lbm_batch* b)
@@ -1460,219 +1610,238 @@ void lbm_batch_destroy(lbm_batch* b)
 
 int lbm_batch_set_param(lbm_batch* b, int key, double v)
 {
-    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
-    if (!std::isfinite(v)) return bfail(b, LBM_E_ARG, "parameter value must be finite");
-    const bool integral = (v == std::floor(v));
-    switch (key) {
-        case LBM_P_STORE:
-            if (b->h) return bfail(b, LBM_E_STATE, "the store format is fixed once storage is bound");
-            if (!integral || v < 0 || v > 3) return bfail(b, LBM_E_ARG, "store must be 0..3");
-            b->store = (int)v;
-            for (lbm_ctx* c : b->inst) c->store = b->store;
-            break;
-        case LBM_P_TILE_ODD:
-        case LBM_P_TILE_EVEN: {
-            if (!integral || !tile_ok((int)v)) return bfail(b, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
-            int& tile = (key == LBM_P_TILE_ODD ? b->tile_odd : b->tile_even);
-            const int old = tile;
-            tile = (int)v;
-            if (!batch_shapes_fit(b)) {
-                tile = old;
-                return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
+    return bguard(b, [&]() -> int {
+        if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+        if (!std::isfinite(v)) return bfail(b, LBM_E_ARG, "parameter value must be finite");
+        const bool integral = (v == std::floor(v));
+        switch (key) {
+            case LBM_P_STORE:
+                if (b->h) return bfail(b, LBM_E_STATE, "the store format is fixed once storage is bound");
+                if (!integral || v < 0 || v > 3) return bfail(b, LBM_E_ARG, "store must be 0..3");
+                b->store = (int)v;
+                for (lbm_ctx* c : b->inst) c->store = b->store;
+                break;
+            case LBM_P_TILE_ODD:
+            case LBM_P_TILE_EVEN: {
+                if (!integral || !tile_ok((int)v)) return bfail(b, LBM_E_ARG, "tile must be 64, 128, 256 or 512");
+                int& tile = (key == LBM_P_TILE_ODD ? b->tile_odd : b->tile_even);
+                const int old = tile;
+                tile = (int)v;
+                if (!batch_shapes_fit(b)) {
+                    tile = old;
+                    return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
+                }
+                break;
             }
-            break;
+            case LBM_P_VECTOR: {
+                if (!integral || v < 0 || v > 4) return bfail(b, LBM_E_ARG, "cells per thread must be 0, 1, 2 or 4");
+                const int old = b->vw_req;
+                b->vw_req = (int)v;
+                if (!batch_shapes_fit(b)) {
+                    b->vw_req = old;
+                    return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
+                }
+                break;
+            }
+            case LBM_P_ODD_ROWS:
+                if (!integral || v < 0 || v > 2) return bfail(b, LBM_E_ARG, "odd-step mode must be 0, 1 or 2");
+                b->odd_rows = (int)v;
+                break;
+            case LBM_P_SPREAD:
+                if (!integral || v < -1 || v > 16 || (v > 0 && v < kXcdChunkLog2))
+                    return bfail(b, LBM_E_ARG, "brick spreading is -1 (by store), 0 (off) or a chunk log2 in [5, 16]");
+                for (lbm_ctx* c : b->inst) c->spread = (int)v;
+                break;
+            case LBM_P_BRICK:
+                if (b->initialized) return bfail(b, LBM_E_STATE, "the population layout is fixed once the state is initialised");
+                if (!integral || v < 0 || v > (1 << 30)) return bfail(b, LBM_E_ARG, "rows per brick must be an integer >= 0");
+                for (lbm_ctx* c : b->inst) c->brick_req = (int)v;
+                break;
+            case LBM_P_XCD_REMAP:
+                if (v != 0.0 && v != 1.0) return bfail(b, LBM_E_ARG, "XCD remap is 0 or 1");
+                b->xcd_remap = (int)v;
+                break;
+            case LBM_P_GRAPH_STEPS:
+                if (!integral || v < 0 || v > 4096) return bfail(b, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
+                b->graph_steps = (int)v;
+                break;
+            case LBM_P_Y1:
+            case LBM_P_NEWTON_TOL:
+            case LBM_P_NEWTON_MAXIT:
+            case LBM_P_COLLISION:
+            case LBM_P_MRT_S_E:
+            case LBM_P_MRT_S_EPS:
+            case LBM_P_MRT_S_Q:
+            case LBM_P_MRT_S_PI:
+            case LBM_P_MRT_S_M:
+            case LBM_P_VD_APLUS:
+            case LBM_P_VD_UTAU:
+                for (lbm_ctx* c : b->inst) {
+                    c->batch_member = false;
+                    int st = lbm_set_param(c, key, v);
+                    c->batch_member = (b->h != nullptr);
+                    if (st != LBM_OK) return bfail(b, st, c->err);
+                }
+                break;
+            default:
+                return bfail(b, LBM_E_ARG, "unknown or per-instance parameter key");
         }
-        case LBM_P_VECTOR: {
-            if (!integral || v < 0 || v > 4) return bfail(b, LBM_E_ARG, "cells per thread must be 0, 1, 2 or 4");
-            const int old = b->vw_req;
-            b->vw_req = (int)v;
-            if (!batch_shapes_fit(b)) {
-                b->vw_req = old;
-                return bfail(b, LBM_E_STATE, "blocks of several rows need the plain layout of an instance's state");
-            }
-            break;
-        }
-        case LBM_P_ODD_ROWS:
-            if (!integral || v < 0 || v > 2) return bfail(b, LBM_E_ARG, "odd-step mode must be 0, 1 or 2");
-            b->odd_rows = (int)v;
-            break;
-        case LBM_P_SPREAD:
-            if (!integral || v < -1 || v > 16 || (v > 0 && v < kXcdChunkLog2))
-                return bfail(b, LBM_E_ARG, "brick spreading is -1 (by store), 0 (off) or a chunk log2 in [5, 16]");
-            for (lbm_ctx* c : b->inst) c->spread = (int)v;
-            break;
-        case LBM_P_BRICK:
-            if (b->initialized) return bfail(b, LBM_E_STATE, "the population layout is fixed once the state is initialised");
-            if (!integral || v < 0 || v > (1 << 30)) return bfail(b, LBM_E_ARG, "rows per brick must be an integer >= 0");
-            for (lbm_ctx* c : b->inst) c->brick_req = (int)v;
-            break;
-        case LBM_P_XCD_REMAP:
-            if (v != 0.0 && v != 1.0) return bfail(b, LBM_E_ARG, "XCD remap is 0 or 1");
-            b->xcd_remap = (int)v;
-            break;
-        case LBM_P_GRAPH_STEPS:
-            if (!integral || v < 0 || v > 4096) return bfail(b, LBM_E_ARG, "graph chunk must be an integer in [0, 4096]");
-            b->graph_steps = (int)v;
-            break;
-        case LBM_P_Y1:
-        case LBM_P_NEWTON_TOL:
-        case LBM_P_NEWTON_MAXIT:
-        case LBM_P_COLLISION:
-        case LBM_P_MRT_S_E:
-        case LBM_P_MRT_S_EPS:
-        case LBM_P_MRT_S_Q:
-        case LBM_P_MRT_S_PI:
-        case LBM_P_MRT_S_M:
-        case LBM_P_VD_APLUS:
-        case LBM_P_VD_UTAU:
-            for (lbm_ctx* c : b->inst) {
-                c->batch_member = false;
-                int st = lbm_set_param(c, key, v);
-                c->batch_member = (b->h != nullptr);
-                if (st != LBM_OK) return bfail(b, st, c->err);
-            }
-            break;
-        default:
-            return bfail(b, LBM_E_ARG, "unknown or per-instance parameter key");
-    }
-    b->tables_ready = false;
-    batch_drop_graphs(b);
-    return LBM_OK;
+        b->tables_ready = false;
+        batch_drop_graphs(b);
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_required_bytes(const lbm_batch* b, size_t* bytes)
 {
-    if (!b || !bytes) return bfail(nullptr, LBM_E_ARG, "null argument");
-    size_t total = 0;
-    for (const lbm_ctx* c : b->inst) {
-        size_t s = 0;
-        lbm_required_bytes(c, &s);
-        total += align256(s);
-    }
-    *bytes = total;
-    return LBM_OK;
+    return bguard(const_cast<lbm_batch*>(b), [&]() -> int {
+        if (!b || !bytes) return bfail(nullptr, LBM_E_ARG, "null argument");
+        size_t total = 0;
+        for (const lbm_ctx* c : b->inst) {
+            size_t s = 0;
+            lbm_required_bytes(c, &s);
+            total += align256(s);
+        }
+        *bytes = total;
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_bind_storage(lbm_batch* b, void* ptr, size_t bytes)
 {
-    if (!b || !ptr) return bfail(b, LBM_E_ARG, "null argument");
-    size_t need = 0;
-    lbm_batch_required_bytes(b, &need);
-    if (bytes < need) return bfail(b, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
-    if (((uintptr_t)ptr) % 256 != 0) return bfail(b, LBM_E_ARG, "storage must be 256-byte aligned");
-    b->offset.clear();
-    size_t off = 0;
-    for (lbm_ctx* c : b->inst) {
-        size_t s = 0;
-        lbm_required_bytes(c, &s);
-        c->batch_member = false;
-        int st = lbm_bind_storage(c, (char*)ptr + off, s);
-        c->batch_member = true;
-        if (st != LBM_OK) return bfail(b, st, c->err);
-        c->stream = b->stream;
-        b->offset.push_back(off);
-        off += align256(s);
-    }
-    b->dev = b->inst[0]->dev;
-    b->h = ptr;
-    b->bytes = bytes;
-    b->initialized = false;
-    b->tables_ready = false;
-    batch_drop_graphs(b);
-    return LBM_OK;
+    return bguard(b, [&]() -> int {
+        if (!b || !ptr) return bfail(b, LBM_E_ARG, "null argument");
+        size_t need = 0;
+        lbm_batch_required_bytes(b, &need);
+        if (bytes < need) return bfail(b, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
+        if (((uintptr_t)ptr) % 256 != 0) return bfail(b, LBM_E_ARG, "storage must be 256-byte aligned");
+        b->offset.clear();
+        size_t off = 0;
+        for (lbm_ctx* c : b->inst) {
+            size_t s = 0;
+            lbm_required_bytes(c, &s);
+            c->batch_member = false;
+            int st = lbm_bind_storage(c, (char*)ptr + off, s);
+            c->batch_member = true;
+            if (st != LBM_OK) return bfail(b, st, c->err);
+            c->stream = b->stream;
+            b->offset.push_back(off);
+            off += align256(s);
+        }
+        b->dev = b->inst[0]->dev;
+        b->h = ptr;
+        b->bytes = bytes;
+        b->initialized = false;
+        b->tables_ready = false;
+        batch_drop_graphs(b);
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_set_stream(lbm_batch* b, void* s)
 {
-    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
-    b->stream = (hipStream_t)s;
-    for (lbm_ctx* c : b->inst) c->stream = b->stream;
-    return LBM_OK;
+    return bguard(b, [&]() -> int {
+        if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+        b->stream = (hipStream_t)s;
+        for (lbm_ctx* c : b->inst) c->stream = b->stream;
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_init_spalding(lbm_batch* b, const double* u_tau, double noise, const uint64_t* seeds)
 {
-    if (!b || !u_tau || !seeds) return bfail(b, LBM_E_ARG, "null argument");
-    if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
-    DeviceGuard dg(b->dev);
-    batch_apply_shapes(b);  // the instances' layouts follow the shapes they will run with
-    for (int i = 0; i < b->n; ++i) {
-        int st = init_spalding_impl(b->inst[i], u_tau[i], noise, seeds[i]);
-        if (st != LBM_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
-    }
-    b->steps = 0;
-    b->layout_s = 0;
-    b->initialized = true;
-    return LBM_OK;
+    return bguard(b, [&]() -> int {
+        if (!b || !u_tau || !seeds) return bfail(b, LBM_E_ARG, "null argument");
+        if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
+        DeviceGuard dg(b->dev);
+        batch_apply_shapes(b);  // the instances' layouts follow the shapes they will run with
+        for (int i = 0; i < b->n; ++i) {
+            int st = init_spalding_impl(b->inst[i], u_tau[i], noise, seeds[i]);
+            if (st != LBM_OK) return bfail(b, st, "instance " + std::to_string(i) + ": " + b->inst[i]->err);
+        }
+        b->steps = 0;
+        b->layout_s = 0;
+        b->initialized = true;
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_step(lbm_batch* b, int64_t n)
 {
-    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
-    if (!b->h || !b->initialized) return bfail(b, LBM_E_STATE, "batch not bound and initialised");
-    if (n < 0) return bfail(b, LBM_E_ARG, "n must be >= 0");
-    if (n == 0) return LBM_OK;
-    DeviceGuard dg(b->dev);
-    int st = batch_tables(b);
-    if (st != LBM_OK) return st;
-    for (lbm_ctx* c : b->inst)
-        if ((st = refresh_damping(c, b->stream)) != LBM_OK) return bfail(b, st, c->err);
-    long long left = n;
-    while (left > 0) {
-        if (b->graph_steps > 0 && left >= b->graph_steps) {
-            const long long L = b->graph_steps;
-            GraphKey key{b->layout_s, (int)L, 0, 0};
-            auto it = b->graphs.find(key);
-            if (it == b->graphs.end()) {
-                if (!b->cap_stream) LBM_BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
-                hipGraph_t g = nullptr;
-                LBM_BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = batch_enqueue(b, b->cap_stream, b->layout_s, L);
-                hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
-                if (e != hipSuccess || e2 != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return bfail(b, LBM_E_DEVICE, std::string("graph capture: ") +
-                                                      hipGetErrorString(e != hipSuccess ? e : e2));
+    return bguard(b, [&]() -> int {
+        if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+        if (!b->h || !b->initialized) return bfail(b, LBM_E_STATE, "batch not bound and initialised");
+        if (n < 0) return bfail(b, LBM_E_ARG, "n must be >= 0");
+        if (n == 0) return LBM_OK;
+        DeviceGuard dg(b->dev);
+        int st = batch_tables(b);
+        if (st != LBM_OK) return st;
+        for (lbm_ctx* c : b->inst)
+            if ((st = refresh_damping(c, b->stream)) != LBM_OK) return bfail(b, st, c->err);
+        long long left = n;
+        while (left > 0) {
+            if (b->graph_steps > 0 && left >= b->graph_steps) {
+                const long long L = b->graph_steps;
+                GraphKey key{b->layout_s, (int)L, 0, 0};
+                auto it = b->graphs.find(key);
+                if (it == b->graphs.end()) {
+                    if (!b->cap_stream) LBM_BHIP(b, hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+                    hipGraph_t g = nullptr;
+                    LBM_BHIP(b, hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+                    hipError_t e = batch_enqueue(b, b->cap_stream, b->layout_s, L);
+                    hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+                    if (e != hipSuccess || e2 != hipSuccess) {
+                        if (g) (void)hipGraphDestroy(g);
+                        return bfail(b, LBM_E_DEVICE, std::string("graph capture: ") +
+                                                          hipGetErrorString(e != hipSuccess ? e : e2));
+                    }
+                    hipGraphExec_t ex = nullptr;
+                    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+                    try {
+                        it = b->graphs.emplace(key, ex).first;
+                    } catch (...) {
+                        (void)hipGraphExecDestroy(ex);
+                        throw;
+                    }
                 }
-                hipGraphExec_t ex = nullptr;
-                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(g);
-                if (e != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
-                it = b->graphs.emplace(key, ex).first;
+                LBM_BHIP(b, hipGraphLaunch(it->second, b->stream));
+                batch_advance(b, L);
+                left -= L;
+            } else {
+                LBM_BHIP(b, batch_enqueue(b, b->stream, b->layout_s, 1));
+                batch_advance(b, 1);
+                left -= 1;
             }
-            LBM_BHIP(b, hipGraphLaunch(it->second, b->stream));
-            batch_advance(b, L);
-            left -= L;
-        } else {
-            LBM_BHIP(b, batch_enqueue(b, b->stream, b->layout_s, 1));
-            batch_advance(b, 1);
-            left -= 1;
         }
-    }
-    return LBM_OK;
+        return LBM_OK;
+    });
 }
 
 int lbm_batch_sync(lbm_batch* b, int64_t* first_bad_step, int32_t* first_bad_instance)
 {
-    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
-    if (first_bad_step) *first_bad_step = -1;
-    if (first_bad_instance) *first_bad_instance = -1;
-    if (!b->h) return LBM_OK;
-    DeviceGuard dg(b->dev);
-    LBM_BHIP(b, hipStreamSynchronize(b->stream));
-    int worst = LBM_OK;
-    for (int i = 0; i < b->n; ++i) {
-        int64_t fb = -1;
-        int st = lbm_sync(b->inst[i], &fb);
-        if (st == LBM_E_DEVICE) return bfail(b, st, b->inst[i]->err);
-        if (st != LBM_OK && worst == LBM_OK) {
-            worst = st;
-            if (first_bad_step) *first_bad_step = fb;
-            if (first_bad_instance) *first_bad_instance = i;
-            b->err = "instance " + std::to_string(i) + ": " + b->inst[i]->err;
+    return bguard(b, [&]() -> int {
+        if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+        if (first_bad_step) *first_bad_step = -1;
+        if (first_bad_instance) *first_bad_instance = -1;
+        if (!b->h) return LBM_OK;
+        DeviceGuard dg(b->dev);
+        LBM_BHIP(b, hipStreamSynchronize(b->stream));
+        int worst = LBM_OK;
+        for (int i = 0; i < b->n; ++i) {
+            int64_t fb = -1;
+            int st = lbm_sync(b->inst[i], &fb);
+            if (st == LBM_E_DEVICE) return bfail(b, st, b->inst[i]->err);
+            if (st != LBM_OK && worst == LBM_OK) {
+                worst = st;
+                if (first_bad_step) *first_bad_step = fb;
+                if (first_bad_instance) *first_bad_instance = i;
+                b->err = "instance " + std::to_string(i) + ": " + b->inst[i]->err;
+            }
         }
-    }
-    return worst;
+        return worst;
+    });
 }
 
 lbm_ctx* lbm_batch_instance(lbm_batch* b, int32_t i)
@@ -1683,75 +1852,77 @@ lbm_ctx* lbm_batch_instance(lbm_batch* b, int32_t i)
 
 int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
 {
-    if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
-    if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
-    if (b->initialized) return bfail(b, LBM_E_STATE, "autotune runs before the state is initialised");
-    if (steps < 2) return bfail(b, LBM_E_ARG, "steps must be >= 2");
-    DeviceGuard dg(b->dev);
-    std::vector<double> ut(b->n);
-    std::vector<uint64_t> seeds(b->n, 0);
-    for (int i = 0; i < b->n; ++i) ut[i] = std::sqrt(std::fabs(b->inst[i]->fx) * b->inst[i]->ny * 0.5);
-    int st = lbm_batch_init_spalding(b, ut.data(), 0.05, seeds.data());
-    if (st != LBM_OK) return st;
-    for (lbm_ctx* c : b->inst) c->initialized = false;  // timing states: layouts follow the candidates
-    const int tcand[4] = {64, 128, 256, 512};
-    const int vcand[3] = {1, 2, 4};
-    hipEvent_t ev[3];
-    for (auto& e : ev) LBM_BHIP(b, hipEventCreate(&e));
-    float best = 1e30f;
-    int bo = b->tile_odd, be = b->tile_even, bv = batch_width(b);
-    hipError_t err = hipSuccess;
-    const int save_req = b->vw_req;
-    for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
-        b->vw_req = vcand[iv];
-        if (batch_width(b) != vcand[iv]) continue;
-        float bo_t = 1e30f, be_t = 1e30f;
-        int bo_k = 256, be_k = 256;
-        for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-            b->tile_odd = b->tile_even = tcand[k];
-            b->tables_ready = false;
-            if ((st = batch_tables(b)) != LBM_OK) return st;
-            float to = 0.f, te = 0.f;
-            for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
-                err = hipEventRecord(ev[0], b->stream);
-                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 0, 1);
-                if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
-                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 1, 1);
-                if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
-                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
-                float x = 0.f, y = 0.f;
-                if (err == hipSuccess) err = hipEventElapsedTime(&x, ev[0], ev[1]);
-                if (err == hipSuccess) err = hipEventElapsedTime(&y, ev[1], ev[2]);
-                if (r > 0) {
-                    to += x;
-                    te += y;
+    return bguard(b, [&]() -> int {
+        if (!b) return bfail(nullptr, LBM_E_ARG, "null batch");
+        if (!b->h) return bfail(b, LBM_E_STATE, "no storage bound");
+        if (b->initialized) return bfail(b, LBM_E_STATE, "autotune runs before the state is initialised");
+        if (steps < 2) return bfail(b, LBM_E_ARG, "steps must be >= 2");
+        DeviceGuard dg(b->dev);
+        std::vector<double> ut(b->n);
+        std::vector<uint64_t> seeds(b->n, 0);
+        for (int i = 0; i < b->n; ++i) ut[i] = std::sqrt(std::fabs(b->inst[i]->fx) * b->inst[i]->ny * 0.5);
+        int st = lbm_batch_init_spalding(b, ut.data(), 0.05, seeds.data());
+        if (st != LBM_OK) return st;
+        for (lbm_ctx* c : b->inst) c->initialized = false;  // timing states: layouts follow the candidates
+        const int tcand[4] = {64, 128, 256, 512};
+        const int vcand[3] = {1, 2, 4};
+        hipEvent_t ev[3];
+        for (auto& e : ev) LBM_BHIP(b, hipEventCreate(&e));
+        float best = 1e30f;
+        int bo = b->tile_odd, be = b->tile_even, bv = batch_width(b);
+        hipError_t err = hipSuccess;
+        const int save_req = b->vw_req;
+        for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
+            b->vw_req = vcand[iv];
+            if (batch_width(b) != vcand[iv]) continue;
+            float bo_t = 1e30f, be_t = 1e30f;
+            int bo_k = 256, be_k = 256;
+            for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+                b->tile_odd = b->tile_even = tcand[k];
+                b->tables_ready = false;
+                if ((st = batch_tables(b)) != LBM_OK) return st;
+                float to = 0.f, te = 0.f;
+                for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
+                    err = hipEventRecord(ev[0], b->stream);
+                    if (err == hipSuccess) err = batch_enqueue(b, b->stream, 0, 1);
+                    if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
+                    if (err == hipSuccess) err = batch_enqueue(b, b->stream, 1, 1);
+                    if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
+                    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                    float x = 0.f, y = 0.f;
+                    if (err == hipSuccess) err = hipEventElapsedTime(&x, ev[0], ev[1]);
+                    if (err == hipSuccess) err = hipEventElapsedTime(&y, ev[1], ev[2]);
+                    if (r > 0) {
+                        to += x;
+                        te += y;
+                    }
                 }
+                if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
+                if (te < be_t) { be_t = te; be_k = tcand[k]; }
             }
-            if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
-            if (te < be_t) { be_t = te; be_k = tcand[k]; }
+            if (bo_t + be_t < best) {
+                best = bo_t + be_t;
+                bo = bo_k;
+                be = be_k;
+                bv = vcand[iv];
+            }
         }
-        if (bo_t + be_t < best) {
-            best = bo_t + be_t;
-            bo = bo_k;
-            be = be_k;
-            bv = vcand[iv];
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        b->vw_req = (err == hipSuccess) ? bv : save_req;
+        b->tile_odd = bo;
+        b->tile_even = be;
+        b->tables_ready = false;
+        b->initialized = false;
+        for (lbm_ctx* c : b->inst) c->initialized = false;
+        batch_drop_graphs(b);
+        if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+        if (tiles) {
+            tiles[0] = bo;
+            tiles[1] = be;
+            tiles[2] = bv;
         }
-    }
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    b->vw_req = (err == hipSuccess) ? bv : save_req;
-    b->tile_odd = bo;
-    b->tile_even = be;
-    b->tables_ready = false;
-    b->initialized = false;
-    for (lbm_ctx* c : b->inst) c->initialized = false;
-    batch_drop_graphs(b);
-    if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
-    if (tiles) {
-        tiles[0] = bo;
-        tiles[1] = be;
-        tiles[2] = bv;
-    }
-    return LBM_OK;
+        return LBM_OK;
+    });
 }
 
 const char* lbm_batch_last_error(const lbm_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }

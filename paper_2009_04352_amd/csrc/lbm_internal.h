@@ -118,6 +118,8 @@ struct ObsArgs {
     const long long* cells;  // optional cell list (nullptr: cells first .. first + count)
     long long first, count;
     double* out;          // [count][4]: rho, ux, uy, uz      (mode 0)
+    double* soa[4];       // mode 0 without out: rho, ux, uy, uz of cell first + i at index i of each
+                          // non-null array (device memory)
                           // [count][4]: tau_x, tau_z, u_tau, U (mode 1, wall cells)
     int* iters;           // optional, mode 1: Newton iterations per wall cell
     double* dmass;        // optional, mode 1: [count][2] = change of the population sum made

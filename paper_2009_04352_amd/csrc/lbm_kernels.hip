@@ -410,8 +410,15 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
     const R rho = R(1) + drho;
     const R ux = (jx + R(0.5) * (R)p.fx) / rho, uy = jy / rho, uz = jz / rho;
     if (p.mode == 0) {
-        double* o = p.out + 4 * i;
-        o[0] = (double)rho; o[1] = (double)ux; o[2] = (double)uy; o[3] = (double)uz;
+        if (p.out) {
+            double* o = p.out + 4 * i;
+            o[0] = (double)rho; o[1] = (double)ux; o[2] = (double)uy; o[3] = (double)uz;
+        } else {
+            if (p.soa[0]) p.soa[0][i] = (double)rho;
+            if (p.soa[1]) p.soa[1][i] = (double)ux;
+            if (p.soa[2]) p.soa[2][i] = (double)uy;
+            if (p.soa[3]) p.soa[3][i] = (double)uz;
+        }
         return;
     }
     if (p.bc == kBB) {

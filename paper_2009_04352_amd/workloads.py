@@ -105,11 +105,13 @@ def params(name, named_tau=False):
 
 # Launch shapes used by the benchmark and by the full-size parity tests, per
 # workload and store format: (threads per block of the odd kernel, of the even
-# kernel, cells per thread), measured on MI355X.  On the 512-cell rows of the
-# 512 x 128 x 256 channel a block covers a whole row with 8-byte groups per
-# thread; on the 2048-cell rows of the large channel FP64 rows are split in
-# 256-thread segments, and FP16/BF16 odd steps walk rows one wavefront each.
+# kernel, cells per thread), measured on MI355X.  On the 128-cell rows of the
+# 128 x 64 x 64 channel and the 512-cell rows of the 512 x 128 x 256 channel a
+# block covers one whole row; on the 2048-cell rows of the large channel FP64
+# rows are split in 256-thread segments, and FP16/BF16 odd steps walk rows one
+# wavefront each.
 LAUNCH_TILES = {
+    "c2": {"f64": (128, 128, 1), "f32": (64, 64, 2), "f16": (64, 64, 2), "bf16": (64, 64, 2)},
     "c3": {"f64": (512, 512, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
     "c5": {"f64": (256, 256, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
 }

@@ -6,7 +6,7 @@ conservation properties that hold at any size."""
 import numpy as np
 import pytest
 
-from gpu_common import MATH_EPS, ref_rounding, ulp
+from gpu_common import MATH_EPS, one_step_tol, ref_rounding, ulp
 
 pytestmark = pytest.mark.gpu
 
@@ -36,26 +36,36 @@ def _release(ch):
     torch.cuda.empty_cache()
 
 
-# the benchmark's workloads and stores: the 512 x 128 x 256 channel in all four
-# formats, the 2048 x 512 x 1024 channel (1.07 G cells) in FP16 and FP32 and
-# its FP64 reference
-FULL = [("c3", "f64"), ("c3", "f32"), ("c3", "f16"), ("c3", "bf16"), ("c5", "f16"), ("c5", "f32"), ("c5", "f64")]
+# the benchmark's workloads and stores: the 2048 x 512 x 1024 channel (1.07 G
+# cells) in all four formats, the 512 x 128 x 256 channel in all four formats
+# and at its named relaxation time tau = 0.503 (FP64)
+FULL = [("c5", "f64", "bgk", False), ("c5", "f32", "bgk", False), ("c5", "f16", "bgk", False),
+        ("c5", "bf16", "bgk", False),
+        ("c3", "f64", "bgk", False), ("c3", "f32", "bgk", False), ("c3", "f16", "bgk", False),
+        ("c3", "bf16", "bgk", False), ("c3", "f64", "bgk", True), ("c3", "f16", "bgk", True)]
 
 
 # the MRT line of the benchmark (--collision mrt --van-driest 26) on the
 # 512 x 128 x 256 channel
-FULL_MRT = [("c3", "f64", "mrt"), ("c3", "f32", "mrt"), ("c3", "f16", "mrt"), ("c3", "bf16", "mrt")]
+FULL_MRT = [("c3", "f64", "mrt", False), ("c3", "f32", "mrt", False), ("c3", "f16", "mrt", False),
+            ("c3", "bf16", "mrt", False)]
 
 
-@pytest.mark.parametrize("workload,store,collision", [f + ("bgk",) for f in FULL] + FULL_MRT)
-def test_one_step_sampled(P, orc, workload, store, collision):
-    """Tolerance: the initial rounding to the store (half an ulp of each input
-    population, carried through one collision with relaxation factor below 2
-    into at most 19 terms) plus one ulp of the output and the arithmetic bound."""
+@pytest.mark.parametrize("workload,store,collision,named", FULL + FULL_MRT)
+def test_two_steps_sampled(P, orc, workload, store, collision, named):
+    """Step 1 (odd kernel) at sampled cells against the oracle evaluated cell by
+    cell from the analytic initial state; tolerance: the initial rounding to
+    the store (half an ulp of each input population, carried through one
+    collision with relaxation factor below 2 into at most 19 terms) plus one
+    ulp of the output and the arithmetic bound.  Step 2 (even kernel, in its
+    full-size launch shape) at the same cells against the oracle's step from
+    the GPU's own step-1 state of the cells around them, with the one-step
+    tolerance (one ulp of the store at the result, the arithmetic bound and the
+    oracle's own rounding)."""
     from paper_2009_04352_amd import workloads as W
-    print("full-size sampled step: %s %s %s" % (workload, store, collision), flush=True)
+    print("full-size sampled steps: %s %s %s named=%s" % (workload, store, collision, named), flush=True)
     vd = 26.0 if collision == "mrt" else 0.0
-    ch, p = _channel(P, store, workload=workload, collision=collision, van_driest=vd)
+    ch, p = _channel(P, store, named=named, workload=workload, collision=collision, van_driest=vd)
     cells = W.sample_cells(p["grid"], 3000, seed=1)
     nx, ny, nz = p["grid"]
     op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB,
@@ -72,6 +82,14 @@ def test_one_step_sampled(P, orc, workload, store, collision):
     hmax = np.abs(h_init).max()
     tol = ulp(store, want) + 4.0 * ulp(store, hmax) + MATH_EPS[store] + 8.0 * np.spacing(1.0 / 3.0)
     assert np.all(np.abs(got - want) <= tol), np.abs(got - want).max()
+    # step 2: the even kernel, from the GPU's step-1 state around the samples
+    tab = orc.neighbourhood(p["grid"], cells)
+    h1 = ch.get_state_cells(tab)
+    ch.step(1)
+    want2, _ = orc.step_cells_table(op, tab, h1 + w, cells)
+    want2 -= w
+    got2 = ch.get_state_cells(cells)
+    assert np.all(np.abs(got2 - want2) <= one_step_tol(store, want2, w)), np.abs(got2 - want2).max()
     assert ch.sync()[0] == 0
     _release(ch)
 

@@ -4,6 +4,8 @@ Small grids span several tiles and a ragged tail (nx = 67 = 64 + 3); every
 store format, every boundary, both AA parities.  Comparisons are element by
 element on the same seeded inputs with the tolerances of gpu_common.
 """
+import zlib
+
 import numpy as np
 import pytest
 
@@ -40,7 +42,7 @@ def test_one_and_two_steps(P, orc, store, bc, grid):
     """One step from a representable state: each h_a within one ulp of the store
     plus the arithmetic bound; the second step (even kernel) starts from the
     GPU's own state handed to the oracle."""
-    rng = np.random.default_rng(hash((store, bc, grid)) % 2**32)
+    rng = np.random.default_rng(zlib.crc32(repr((store, bc, grid)).encode()))
     nx, ny, nz = grid
     h0 = random_state(orc, (nz, ny, nx), store, rng)
     w = weights(orc)

@@ -33,7 +33,7 @@ def _poiseuille(orc, tau, s_odd, ny, steps, F=1e-6):
 @pytest.mark.parametrize("tau,s_odd", [(0.8, 1.2), (0.7, 1.5)])
 def test_poiseuille_slip(orc, tau, s_odd):
     F = 1e-6
-    u, parabola = _poiseuille(orc, tau, s_odd, 16, 20000, F)
+    u, parabola = _poiseuille(orc, tau, s_odd, 8, 6000, F)
     lp, lm = tau - 0.5, 1.0 / s_odd - 0.5
     slip = F * (16 * lp * lm - 3) / (8 * lp)
     assert np.abs(u - (parabola + slip)).max() <= 1e-10 * parabola.max()
@@ -41,7 +41,7 @@ def test_poiseuille_slip(orc, tau, s_odd):
 
 def test_poiseuille_exact_at_magic_product(orc):
     tau = 0.6                                  # L+ = 0.1: L- = 1.875 gives L = 3/16
-    u, parabola = _poiseuille(orc, tau, 1.0 / (1.875 + 0.5), 16, 30000)
+    u, parabola = _poiseuille(orc, tau, 1.0 / (1.875 + 0.5), 8, 9000)
     assert np.abs(u - parabola).max() <= 1e-10 * parabola.max()
 
 

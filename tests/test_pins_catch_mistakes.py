@@ -14,7 +14,7 @@ SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 # fast pins first: the run stops at the first failure
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_mrt.py", "tests/test_oracle_spalding.py",
              "tests/test_oracle_wfb.py", "tests/test_oracle_paper_numbers.py", "tests/test_oracle_initial_state.py",
-             "tests/test_oracle_flows.py", "tests/test_oracle_mrt_flows.py"]
+             "tests/test_oracle_cells.py", "tests/test_oracle_flows.py", "tests/test_oracle_mrt_flows.py"]
 
 # name: (text in lbm_oracle.c, planted replacement)
 MISTAKES = {
@@ -51,6 +51,7 @@ MISTAKES = {
     "wall velocity without the half force": ("    jx += 0.5 * p->fx;\n    double vx", "    double vx"),
     "statistics sample count": ("o->stats[8 * y + 7] += (double)p->nx * p->nz;", "o->stats[8 * y + 7] += (double)p->nx;"),
     "spanwise streaming from the wrong side": ("int sz = wrap(z - E[a][2], p->nz);", "int sz = wrap(z + E[a][2], p->nz);"),
+    "analytic initial state: wrong direction": ("    return feq(a, 1.0, u);\n}", "    return feq(OPP[a], 1.0, u);\n}"),
     "opposite of a direction": ("E[b][1] == -E[a][1] && E[b][2] == -E[a][2]) OPP[a] = b;",
                                 "E[b][1] == -E[a][1] && E[b][2] == E[a][2]) OPP[a] = b;"),
 }
