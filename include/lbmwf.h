@@ -109,6 +109,18 @@ extern "C" {
                                * (default); the paper's reference uses 26 */
 #define LBM_P_VD_UTAU 25      /* friction velocity u_tau of that y+, >= 0; 0 (default) = sqrt(|Fx| ny / 2), the
                                * force-balance value of the channel */
+#define LBM_P_WALL_NODES 26   /* wall placement, settable before the state is initialised: 0 (default) = link-wise
+                               * walls halfway below row 0 and above row ny - 1, the WFB correction on the first
+                               * fluid layer; 1 = wall nodes, the wall grid of Sec. 2.1-2.2 (Eq. 3, 4, 14 applied
+                               * at the wall grid) as a lattice node one spacing below row 0 and above row
+                               * ny - 1: the populations the first layer sends towards the wall reach the wall
+                               * node of column x + e_b one step later, are reflected there (the boundary:
+                               * bounce-back, mirror reflection or the WFB collision of Eq. 14 with tau_w of
+                               * Eq. 15-17 from the first layer's density and velocity of that previous step)
+                               * and stream into the fluid at the next step.  The wall records of lbm_wall_shear
+                               * are then those of the next wall-node collision; lbm_wall_mass_change is not
+                               * defined (LBM_E_STATE); state transfer restarts the wall nodes from the state
+                               * (lbm_get_wall_nodes).  Not for batches. */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -233,6 +245,18 @@ int lbm_wall_yplus_pdf(lbm_ctx* ctx, int32_t nbins, double lo, double hi, int64_
  * that the mean population is rho / 19.  Zeros for bounce-back and free-slip
  * walls, whose reflections only permute.  Synchronises. */
 int lbm_wall_mass_change(lbm_ctx* ctx, double* dsum, double* rho);
+
+/* Wall-node state (LBM_P_WALL_NODES = 1, else LBM_E_STATE): fw [2][5][nz][nx]
+ * receives, as h = f - w, the populations each wall node sends into the fluid
+ * at the next step (walls w = 0 bottom, 1 top; directions 3, 7, 11, 14, 17
+ * at the bottom and their mirror images 4, 13, 18, 8, 12 at the top); rec
+ * [2][nz][nx][4] the first layer's density, u_x, u_z and friction velocity of
+ * the latest step, from which the next wall-node collision takes its stress.
+ * After a state is set or initialised the wall nodes start from it: the
+ * record from the plain moments of the first layer's post-collision
+ * populations, and one wall-node collision of them.  Either pointer may be
+ * NULL, not both.  Synchronises. */
+int lbm_get_wall_nodes(lbm_ctx* ctx, double* fw, double* rec);
 
 /* Plane statistics (Sec. 3.1 time and plane averages, Fig. 6 moments),
  * accumulated in FP64 on sampled steps from the velocity each sampled step

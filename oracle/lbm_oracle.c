@@ -121,6 +121,9 @@ typedef struct {
     double s_m;          /* MRT rate of the third-order m moments */
     double vd_aplus;     /* van Driest A+; <= 0: no damping */
     double vd_utau;      /* friction velocity for the damping's y+; <= 0: sqrt(|Fx| ny / 2) */
+    int32_t wall_nodes;  /* 0: link-wise walls halfway below row 0 and above row ny - 1, WFB on the
+                          * first fluid layer; 1: wall nodes at y = -1 and y = ny (Sec. 2.1-2.2,
+                          * Eq. 3, 4 and 14 applied at the wall grid) */
 } orc_params;
 
 typedef struct {
@@ -133,6 +136,12 @@ typedef struct {
     int32_t max_newton_iters;
     double *stats;          /* [y][8]: sums of ux uy uz ux^2 uy^2 uz^2 ux*uy, count */
     int64_t nsamples;
+    /* wall nodes (p.wall_nodes): the five populations each wall node sends
+     * into the fluid, [w][k][z][x] with k indexing the directions IN_W[w],
+     * and the first layer's rho, u_x, u_z of the latest step, [w][z][x][3],
+     * from which the next wall-node collision takes its stress */
+    double *fw, *fw_new;
+    double *urec, *urec_new;
 } orc;
 
 /* ------------------------------------------------------------ threads */
@@ -254,6 +263,29 @@ static void moments(const double f[Q], double fx, double* rho, double u[3])
  * wall = 0: bottom (wall below, +y into the flow, the paper's setting);
  * wall = 1: top (the bottom case mirrored in y).
  * rec (may be NULL) receives tau_x, tau_z, u_tau, U. */
+/* The wall stress of Eq. 15-17 for density rho and wall-parallel velocity
+ * (vx, vz): u_tau from Spalding's law by Newton, tau_w = rho u_tau^2, split
+ * against the velocity.  rec receives tau_x, tau_z, u_tau, U. */
+int orc_wall_tau(const orc_params* p, double rho, double vx, double vz, double rec[4], int32_t* iters)
+{
+    double U = sqrt(vx * vx + vz * vz);
+    double taux = 0.0, tauz = 0.0, utau = 0.0;
+    int32_t it = 0;
+    if (iters) *iters = 0;
+    if (U > 0.0) {
+        double nu0 = (p->tau0 - 0.5) / 3.0;
+        utau = orc_wall_utau(U, p->y1, nu0, p->kappa, p->bconst, p->newton_tol,
+                             p->newton_maxit, &it);
+        if (iters) *iters = it;
+        if (utau < 0.0) return ORC_E_NEWTON;
+        double tauw = rho * utau * utau;           /* Eq. 17 */
+        taux = -(vx / U) * tauw;                   /* Eq. 15 */
+        tauz = -(vz / U) * tauw;
+    }
+    rec[0] = taux; rec[1] = tauz; rec[2] = utau; rec[3] = U;
+    return ORC_OK;
+}
+
 int orc_wfb_cell(const orc_params* p, int wall, double f[Q], double rec[4], int32_t* iters)
 {
     tables_init();
@@ -265,21 +297,14 @@ int orc_wfb_cell(const orc_params* p, int wall, double f[Q], double rec[4], int3
     }
     jx += 0.5 * p->fx;
     double vx = jx / rho, vz = jz / rho;          /* free-slip velocity v, Eq. 7-10 */
-    double U = sqrt(vx * vx + vz * vz);
-    double taux = 0.0, tauz = 0.0, utau = 0.0;
+    double r[4];
     int32_t it = 0;
-    if (U > 0.0) {
-        double nu0 = (p->tau0 - 0.5) / 3.0;
-        utau = orc_wall_utau(U, p->y1, nu0, p->kappa, p->bconst, p->newton_tol,
-                             p->newton_maxit, &it);
-        if (utau < 0.0) {
-            if (iters) *iters = it;
-            return ORC_E_NEWTON;
-        }
-        double tauw = rho * utau * utau;           /* Eq. 17 */
-        taux = -(vx / U) * tauw;                   /* Eq. 15 */
-        tauz = -(vz / U) * tauw;
+    int st = orc_wall_tau(p, rho, vx, vz, r, &it);
+    if (st != ORC_OK) {
+        if (iters) *iters = it;
+        return st;
     }
+    double taux = r[0], tauz = r[1], utau = r[2], U = r[3];
     /* Eq. 13 (dt = dy = 1): the in-pointing diagonals of the bottom wall are
      * 7 and 14 (x) and 11 and 17 (z); the top wall uses their mirror images. */
     int a7 = 7, a14 = 14, a11 = 11, a17 = 17;
@@ -291,6 +316,43 @@ int orc_wfb_cell(const orc_params* p, int wall, double f[Q], double rec[4], int3
     if (rec) { rec[0] = taux; rec[1] = tauz; rec[2] = utau; rec[3] = U; }
     if (iters) *iters = it;
     return ORC_OK;
+}
+
+/* Populations a wall node sends into the fluid (e_y = +1 at the bottom
+ * wall, -1 at the top), in the order k = 0..4 of the wall-node arrays. */
+static const int IN_W[2][5] = {{3, 7, 11, 14, 17}, {4, 13, 18, 8, 12}};
+
+/* The collision of a wall node (Sec. 2.1-2.2, applied at the wall grid
+ * itself), literally, on all 19 populations f that reached it:
+ *   bounce-back (Eq. 3 in 3-D form): every population reversed;
+ *   WFB (Eq. 14): the wall-normal and in-plane populations reversed (14c),
+ *     the in-pointing diagonals from their mirror images plus or minus
+ *     tau/2 (14a-b), the out-pointing diagonals equal to the corrected
+ *     in-pointing ones (14c); the rest population unchanged;
+ *   free-slip (Eq. 4 in 3-D form): Eq. 14 with tau = 0.
+ * wall = 1 (top) is the bottom rule mirrored in y. */
+void orc_wall_node_collide(const orc_params* p, int wall, const double f[Q], double taux, double tauz, double out[Q])
+{
+    tables_init();
+    double g[Q], o[Q];
+    for (int a = 0; a < Q; ++a) g[a] = (wall == 0) ? f[a] : f[MIR[a]];   /* the bottom picture */
+    if (p->bc == ORC_BB) {
+        for (int a = 0; a < Q; ++a) o[a] = g[OPP[a]];
+    } else {
+        double tx = (p->bc == ORC_WFB) ? taux : 0.0, tz = (p->bc == ORC_WFB) ? tauz : 0.0;
+        o[0] = g[0];
+        o[7] = g[13] + 0.5 * tx;                       /* 14a */
+        o[14] = g[8] - 0.5 * tx;
+        o[11] = g[18] + 0.5 * tz;                      /* 14b */
+        o[17] = g[12] - 0.5 * tz;
+        o[1] = g[2]; o[2] = g[1]; o[3] = g[4]; o[4] = g[3]; o[5] = g[6]; o[6] = g[5];   /* 14c */
+        o[8] = o[7]; o[9] = g[10]; o[10] = g[9]; o[12] = o[11]; o[13] = o[14];
+        o[15] = g[16]; o[16] = g[15]; o[18] = o[17];
+    }
+    for (int a = 0; a < Q; ++a) {
+        if (wall == 0) out[a] = o[a];
+        else out[MIR[a]] = o[a];
+    }
 }
 
 static double cs_at(const orc_params* p, int y);
@@ -445,6 +507,8 @@ typedef struct {
     const double* tab_f;
     int64_t ntab;
     int* missing;
+    /* wall nodes: their outputs [w][k][z][x] (p->wall_nodes) */
+    const double* fw;
 } src_t;
 
 static int64_t cell_index(const orc_params* p, int x, int y, int z)
@@ -500,11 +564,20 @@ static double src_get(const src_t* s, int a, int x, int y, int z)
 
 static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
+static int in_index(int wall, int a)
+{
+    for (int k = 0; k < 5; ++k)
+        if (IN_W[wall][k] == a) return k;
+    return -1;
+}
+
 /* Streaming by pull (Eq. 1) with the wall rules for links that cross a wall:
  * BB: the population returns on its own link (Eq. 3 in 3-D form);
  * WFB / free-slip: the wall-normal population is bounced back, the
  * diagonal ones are mirror images from the in-plane neighbour (Eq. 4 in
- * 3-D form; pairs 7-13, 14-8, 11-18, 17-12 as listed with Eq. 14). */
+ * 3-D form; pairs 7-13, 14-8, 11-18, 17-12 as listed with Eq. 14).
+ * Wall nodes: a population entering from the wall comes from the wall node
+ * it left, x - e_a in the wall plane. */
 static void gather(const src_t* s, int x, int y, int z, double f[Q])
 {
     const orc_params* p = s->p;
@@ -514,6 +587,9 @@ static void gather(const src_t* s, int x, int y, int z, double f[Q])
         int sz = wrap(z - E[a][2], p->nz);
         if (sy >= 0 && sy < p->ny) {
             f[a] = src_get(s, a, sx, sy, sz);
+        } else if (p->wall_nodes) {
+            int w = sy < 0 ? 0 : 1;
+            f[a] = s->fw[(((int64_t)w * 5 + in_index(w, a)) * p->nz + sz) * p->nx + sx];
         } else if (p->bc == ORC_BB || (E[a][0] == 0 && E[a][2] == 0)) {
             f[a] = src_get(s, OPP[a], x, y, z);
         } else {
@@ -537,7 +613,7 @@ static int precollision(const src_t* s, int x, int y, int z, double f[Q], double
     if (rec) rec[0] = rec[1] = rec[2] = rec[3] = 0.0;
     if (iters) *iters = 0;
     int w = wall_of_row(p, y);
-    if (p->bc == ORC_WFB && w >= 0) {
+    if (p->bc == ORC_WFB && w >= 0 && !p->wall_nodes) {
         if (p->ny == 1) return ORC_E_ARG;
         return orc_wfb_cell(p, w, f, rec, iters);
     }
@@ -553,6 +629,7 @@ static int params_ok(const orc_params* p)
     if (!isfinite(p->tau0) || !isfinite(p->cs) || !isfinite(p->kappa) || !isfinite(p->bconst)) return 0;
     if (!isfinite(p->fx) || !(p->y1 > 0.0) || !(p->newton_tol > 0.0) || p->newton_maxit < 1) return 0;
     if (p->bc < 0 || p->bc > 2 || p->stats_every < 0) return 0;
+    if (p->wall_nodes != 0 && p->wall_nodes != 1) return 0;
     if (p->collision != ORC_BGK && p->collision != ORC_MRT) return 0;
     if (p->collision == ORC_MRT) {
         const double r[5] = {p->s_e, p->s_eps, p->s_q, p->s_pi, p->s_m};
@@ -574,8 +651,18 @@ orc* orc_create(const orc_params* p)
     o->fpost = (double*)calloc((size_t)(Q * o->ncell), sizeof(double));
     o->fnew = (double*)calloc((size_t)(Q * o->ncell), sizeof(double));
     o->stats = (double*)calloc((size_t)p->ny * 8, sizeof(double));
-    if (!o->fpost || !o->fnew || !o->stats) {
-        free(o->fpost); free(o->fnew); free(o->stats); free(o);
+    int ok = o->fpost && o->fnew && o->stats;
+    if (ok && p->wall_nodes) {
+        size_t m = (size_t)2 * p->nx * p->nz;
+        o->fw = (double*)calloc(m * 5, sizeof(double));
+        o->fw_new = (double*)calloc(m * 5, sizeof(double));
+        o->urec = (double*)calloc(m * 3, sizeof(double));
+        o->urec_new = (double*)calloc(m * 3, sizeof(double));
+        ok = o->fw && o->fw_new && o->urec && o->urec_new;
+    }
+    if (!ok) {
+        free(o->fpost); free(o->fnew); free(o->stats);
+        free(o->fw); free(o->fw_new); free(o->urec); free(o->urec_new); free(o);
         return NULL;
     }
     o->first_bad_step = -1;
@@ -588,6 +675,10 @@ void orc_destroy(orc* o)
     free(o->fpost);
     free(o->fnew);
     free(o->stats);
+    free(o->fw);
+    free(o->fw_new);
+    free(o->urec);
+    free(o->urec_new);
     free(o);
 }
 
@@ -598,7 +689,76 @@ int orc_set_param_bc(orc* o, int32_t bc)
     return ORC_OK;
 }
 
-void orc_set_state(orc* o, const double* fpost) { memcpy(o->fpost, fpost, sizeof(double) * Q * o->ncell); }
+/* The wall-node collision of one step for every wall node W = (x, z) of
+ * both walls: the populations the first layer sent towards W on the
+ * previous step (o->fpost, taken from the cells x - e_b in the wall plane)
+ * collide by orc_wall_node_collide with the stress of Eq. 15-17 from the
+ * first layer's density and velocity of the previous step at W's column
+ * (o->urec); the five outputs that stream into the fluid go to fw_out.
+ * Returns ORC_E_NEWTON if a Newton solve fails. */
+static int wall_node_update(const orc* o, double* fw_out, int32_t* maxit)
+{
+    const orc_params* p = &o->p;
+    int bad = 0;
+    int32_t mx = 0;
+    for (int w = 0; w < 2; ++w) {
+        int y = (w == 0) ? 0 : p->ny - 1;
+        for (int z = 0; z < p->nz; ++z)
+            for (int x = 0; x < p->nx; ++x) {
+                double f[Q], out[Q], rec[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int b = 0; b < Q; ++b) {
+                    f[b] = 0.0;   /* populations that never reach the fluid are not tracked */
+                    if ((w == 0 && E[b][1] == -1) || (w == 1 && E[b][1] == 1)) {
+                        int sx = wrap(x - E[b][0], p->nx), sz = wrap(z - E[b][2], p->nz);
+                        f[b] = o->fpost[(int64_t)b * o->ncell + cell_index(p, sx, y, sz)];
+                    }
+                }
+                const double* u = o->urec + 3 * (((int64_t)w * p->nz + z) * p->nx + x);
+                int32_t it = 0;
+                if (p->bc == ORC_WFB && orc_wall_tau(p, u[0], u[1], u[2], rec, &it) != ORC_OK) bad = 1;
+                if (it > mx) mx = it;
+                orc_wall_node_collide(p, w, f, rec[0], rec[1], out);
+                for (int k = 0; k < 5; ++k)
+                    fw_out[(((int64_t)w * 5 + k) * p->nz + z) * p->nx + x] = out[IN_W[w][k]];
+            }
+    }
+    if (maxit && mx > *maxit) *maxit = mx;
+    return bad ? ORC_E_NEWTON : ORC_OK;
+}
+
+/* Wall nodes at a state set from outside (initial state, orc_set_state):
+ * the first layer's density and velocity are the plain moments of its
+ * post-collision populations, and the wall nodes hold what they would send
+ * had the state also been the previous step's (one wall-node collision of
+ * the given populations with that stress). */
+static int wall_node_start(orc* o)
+{
+    const orc_params* p = &o->p;
+    if (!p->wall_nodes) return ORC_OK;
+    for (int w = 0; w < 2; ++w) {
+        int y = (w == 0) ? 0 : p->ny - 1;
+        for (int z = 0; z < p->nz; ++z)
+            for (int x = 0; x < p->nx; ++x) {
+                int64_t c = cell_index(p, x, y, z);
+                double r = 0.0, jx = 0.0, jz = 0.0;
+                for (int a = 0; a < Q; ++a) {
+                    double v = o->fpost[(int64_t)a * o->ncell + c];
+                    r += v;
+                    jx += E[a][0] * v;
+                    jz += E[a][2] * v;
+                }
+                double* u = o->urec + 3 * (((int64_t)w * p->nz + z) * p->nx + x);
+                u[0] = r; u[1] = jx / r; u[2] = jz / r;
+            }
+    }
+    return wall_node_update(o, o->fw, NULL);
+}
+
+void orc_set_state(orc* o, const double* fpost)
+{
+    memcpy(o->fpost, fpost, sizeof(double) * Q * o->ncell);
+    o->status = wall_node_start(o);
+}
 void orc_get_state(const orc* o, double* fpost) { memcpy(fpost, o->fpost, sizeof(double) * Q * o->ncell); }
 int64_t orc_steps(const orc* o) { return o->steps; }
 int32_t orc_max_newton_iters(const orc* o) { return o->max_newton_iters; }
@@ -625,7 +785,7 @@ int orc_init_spalding(orc* o, double u_tau, double noise, uint64_t seed)
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL, NULL};
     for (int z = 0; z < p->nz; ++z)
         for (int y = 0; y < p->ny; ++y)
             for (int x = 0; x < p->nx; ++x) {
@@ -636,9 +796,9 @@ int orc_init_spalding(orc* o, double u_tau, double noise, uint64_t seed)
             }
     free(prof);
     o->steps = 0;
-    o->status = ORC_OK;
+    o->status = wall_node_start(o);
     o->first_bad_step = -1;
-    return ORC_OK;
+    return o->status;
 }
 
 /* Full update of one cell from a source of post-collision populations. */
@@ -662,9 +822,11 @@ int orc_step(orc* o, int64_t n)
     for (int64_t t = 0; t < n; ++t) {
         const int64_t step = o->steps + 1;
         const int sample = p->stats_every > 0 && (step % p->stats_every) == 0;
-        src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
+        src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL, o->fw};
         int bad = 0;
         int32_t maxit = o->max_newton_iters;
+        /* wall nodes: their collision of this step, from the previous step's state */
+        if (p->wall_nodes && wall_node_update(o, o->fw_new, &maxit) != ORC_OK) bad |= 2;
         double* srow = NULL;
         if (sample) {
             srow = (double*)calloc((size_t)p->nz * p->ny * 7, sizeof(double));
@@ -684,6 +846,11 @@ int orc_step(orc* o, int64_t n)
                     }
                     int64_t c = cell_index(p, x, y, z);
                     for (int a = 0; a < Q; ++a) o->fnew[(int64_t)a * nc + c] = out[a];
+                    if (p->wall_nodes && (y == 0 || y == p->ny - 1)) {
+                        /* the first layer's density and velocity for the next wall-node collision */
+                        double* u = o->urec_new + 3 * (((int64_t)(y == 0 ? 0 : 1) * p->nz + z) * p->nx + x);
+                        u[0] = mom[0]; u[1] = mom[1]; u[2] = mom[3];
+                    }
                     if (sample) {
                         double* r = srow + 7 * ((int64_t)z * p->ny + y);
                         r[0] += mom[1]; r[1] += mom[2]; r[2] += mom[3];
@@ -704,6 +871,10 @@ int orc_step(orc* o, int64_t n)
         }
         o->max_newton_iters = maxit;
         double* tmp = o->fpost; o->fpost = o->fnew; o->fnew = tmp;
+        if (p->wall_nodes) {
+            tmp = o->fw; o->fw = o->fw_new; o->fw_new = tmp;
+            tmp = o->urec; o->urec = o->urec_new; o->urec_new = tmp;
+        }
         o->steps = step;
         if (bad) {
             if (o->first_bad_step < 0) o->first_bad_step = step;
@@ -719,7 +890,7 @@ int orc_step(orc* o, int64_t n)
 int orc_observe(const orc* o, double* rho, double* ux, double* uy, double* uz)
 {
     const orc_params* p = &o->p;
-    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
+    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL, o->fw};
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(| : bad)
     for (int z = 0; z < p->nz; ++z)
@@ -745,7 +916,41 @@ int orc_observe(const orc* o, double* rho, double* ux, double* uy, double* uz)
 int orc_wall(const orc* o, double* taux, double* tauz, double* utau, double* uu)
 {
     const orc_params* p = &o->p;
-    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL};
+    src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL, o->fw};
+    if (p->wall_nodes) {
+        /* the stress the next wall-node collision applies, from the first
+         * layer's latest density and velocity (WFB); bounce-back: the momentum
+         * exchange of the populations the first layer sends towards the wall
+         * node; free-slip: no stress */
+        for (int w = 0; w < 2; ++w) {
+            int y = (w == 0) ? 0 : p->ny - 1;
+            for (int z = 0; z < p->nz; ++z)
+                for (int x = 0; x < p->nx; ++x) {
+                    int64_t k = (int64_t)w * p->nx * p->nz + (int64_t)z * p->nx + x;
+                    const double* u = o->urec + 3 * k;
+                    double rec[4] = {0.0, 0.0, 0.0, sqrt(u[1] * u[1] + u[2] * u[2])};
+                    if (p->bc == ORC_WFB) {
+                        if (orc_wall_tau(p, u[0], u[1], u[2], rec, NULL) != ORC_OK) return ORC_E_NEWTON;
+                    } else if (p->bc == ORC_BB) {
+                        double tx = 0.0, tz = 0.0;
+                        for (int b = 0; b < Q; ++b) {
+                            if (!((w == 0 && E[b][1] == -1) || (w == 1 && E[b][1] == 1))) continue;
+                            int sx = wrap(x - E[b][0], p->nx), sz = wrap(z - E[b][2], p->nz);
+                            double fb = o->fpost[(int64_t)b * o->ncell + cell_index(p, sx, y, sz)];
+                            tx += -2.0 * E[b][0] * fb;
+                            tz += -2.0 * E[b][2] * fb;
+                        }
+                        rec[0] = tx; rec[1] = tz;
+                        rec[2] = sqrt(sqrt(tx * tx + tz * tz) / u[0]);
+                    }
+                    if (taux) taux[k] = rec[0];
+                    if (tauz) tauz[k] = rec[1];
+                    if (utau) utau[k] = rec[2];
+                    if (uu) uu[k] = rec[3];
+                }
+        }
+        return ORC_OK;
+    }
     for (int w = 0; w < 2; ++w) {
         int y = (w == 0) ? 0 : p->ny - 1;
         for (int z = 0; z < p->nz; ++z)
@@ -783,6 +988,30 @@ int orc_wall(const orc* o, double* taux, double* tauz, double* utau, double* uu)
     return ORC_OK;
 }
 
+/* Wall-node state: fw [2][5][nz][nx], the populations the wall nodes send
+ * into the fluid at the next step, in the direction order of IN_W (bottom
+ * 3, 7, 11, 14, 17; top 4, 13, 18, 8, 12); urec [2][nz][nx][3], the first
+ * layer's rho, u_x, u_z of the latest step.  ORC_E_ARG without wall nodes. */
+int orc_get_wall_nodes(const orc* o, double* fw, double* urec)
+{
+    if (!o->p.wall_nodes) return ORC_E_ARG;
+    size_t m = (size_t)2 * o->p.nx * o->p.nz;
+    if (fw) memcpy(fw, o->fw, sizeof(double) * 5 * m);
+    if (urec) memcpy(urec, o->urec, sizeof(double) * 3 * m);
+    return ORC_OK;
+}
+
+/* Sets the wall-node state (same layout as orc_get_wall_nodes), e.g. to
+ * continue from another implementation's state after orc_set_state. */
+int orc_set_wall_nodes(orc* o, const double* fw, const double* urec)
+{
+    if (!o->p.wall_nodes) return ORC_E_ARG;
+    size_t m = (size_t)2 * o->p.nx * o->p.nz;
+    if (fw) memcpy(o->fw, fw, sizeof(double) * 5 * m);
+    if (urec) memcpy(o->urec, urec, sizeof(double) * 3 * m);
+    return ORC_OK;
+}
+
 void orc_stats_sums(const orc* o, double* out, int64_t* nsamples)
 {
     memcpy(out, o->stats, sizeof(double) * 8 * o->p.ny);
@@ -803,11 +1032,11 @@ int orc_init_cells(const orc_params* p, double u_tau, double noise, uint64_t see
                    int64_t n, const int64_t* cells, double* fpost_out /* [n][19] */)
 {
     tables_init();
-    if (!params_ok(p)) return ORC_E_ARG;
+    if (!params_ok(p) || p->wall_nodes) return ORC_E_ARG;
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL, NULL};
     for (int64_t i = 0; i < n; ++i) {
         int64_t c = cells[i];
         int x = (int)(c % p->nx), y = (int)((c / p->nx) % p->ny), z = (int)(c / ((int64_t)p->nx * p->ny));
@@ -822,11 +1051,11 @@ int orc_step1_cells(const orc_params* p, double u_tau, double noise, uint64_t se
                     double* mom_out /* [n][4]: observables of the initial state */)
 {
     tables_init();
-    if (!params_ok(p)) return ORC_E_ARG;
+    if (!params_ok(p) || p->wall_nodes) return ORC_E_ARG;
     double* prof = (double*)malloc(sizeof(double) * p->ny);
     if (!prof) return ORC_E_ARG;
     initial_profile(p, u_tau, prof);
-    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL};
+    src_t s = {p, NULL, prof, noise, seed, NULL, NULL, 0, NULL, NULL};
     int st = ORC_OK;
     for (int64_t i = 0; i < n && st == ORC_OK; ++i) {
         int64_t c = cells[i];
@@ -847,11 +1076,11 @@ int orc_step_cells_table(const orc_params* p, int64_t ntab, const int64_t* tab_c
                          double* mom_out /* [n][4]: observables of the table's state, may be NULL */)
 {
     tables_init();
-    if (!params_ok(p)) return ORC_E_ARG;
+    if (!params_ok(p) || p->wall_nodes) return ORC_E_ARG;
     for (int64_t k = 1; k < ntab; ++k)
         if (tab_cells[k] <= tab_cells[k - 1]) return ORC_E_ARG;
     int missing = 0;
-    src_t s = {p, NULL, NULL, 0.0, 0, tab_cells, tab_f, ntab, &missing};
+    src_t s = {p, NULL, NULL, 0.0, 0, tab_cells, tab_f, ntab, &missing, NULL};
     int st = ORC_OK;
     for (int64_t i = 0; i < n && st == ORC_OK; ++i) {
         int64_t c = cells[i];

@@ -32,6 +32,7 @@ class Params(C.Structure):
         ("stats_every", C.c_int32), ("collision", C.c_int32),
         ("s_e", C.c_double), ("s_eps", C.c_double), ("s_q", C.c_double), ("s_pi", C.c_double),
         ("s_m", C.c_double), ("vd_aplus", C.c_double), ("vd_utau", C.c_double),
+        ("wall_nodes", C.c_int32),
     ]
 
 
@@ -63,6 +64,13 @@ def lib():
         L.orc_wall_utau.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int32)]
         L.orc_feq.argtypes = [C.c_double, dp, dp]
+        L.orc_wall_tau.restype = C.c_int
+        L.orc_wall_tau.argtypes = [PP, C.c_double, C.c_double, C.c_double, dp, C.POINTER(C.c_int32)]
+        L.orc_wall_node_collide.argtypes = [PP, C.c_int, dp, C.c_double, C.c_double, dp]
+        L.orc_get_wall_nodes.restype = C.c_int
+        L.orc_get_wall_nodes.argtypes = [C.c_void_p, dp, dp]
+        L.orc_set_wall_nodes.restype = C.c_int
+        L.orc_set_wall_nodes.argtypes = [C.c_void_p, dp, dp]
         L.orc_wfb_cell.restype = C.c_int
         L.orc_wfb_cell.argtypes = [PP, C.c_int, dp, dp, C.POINTER(C.c_int32)]
         L.orc_collide_cell.argtypes = [PP, dp, dp, C.POINTER(C.c_double)]
@@ -121,11 +129,32 @@ def tables():
 
 def make_params(nx, ny, nz, tau0, cs=0.1, kappa=0.41, bconst=5.5, fx=0.0, bc=WFB,
                 y1=1.0, newton_tol=1e-14, newton_maxit=100, stats_every=0, collision=BGK,
-                rates=None, vd_aplus=0.0, vd_utau=0.0):
+                rates=None, vd_aplus=0.0, vd_utau=0.0, wall_nodes=0):
     r = dict(MRT_RATES, **(rates or {}))
     return Params(nx, ny, nz, bc, tau0, cs, kappa, bconst, fx, y1, newton_tol,
                   newton_maxit, stats_every, collision, r["s_e"], r["s_eps"], r["s_q"], r["s_pi"],
-                  r["s_m"], vd_aplus, vd_utau)
+                  r["s_m"], vd_aplus, vd_utau, int(wall_nodes))
+
+
+# populations a wall node sends into the fluid, in the order of the wall-node arrays
+IN_W = ((3, 7, 11, 14, 17), (4, 13, 18, 8, 12))
+
+
+def wall_tau(params, rho, vx, vz):
+    """Eq. 15-17 for a density and wall-parallel velocity: (tau_x, tau_z, u_tau, U), status."""
+    rec = np.zeros(4)
+    it = C.c_int32(0)
+    st = lib().orc_wall_tau(C.byref(params), float(rho), float(vx), float(vz), rec, C.byref(it))
+    return rec, st
+
+
+def wall_node_collide(params, wall, f, taux, tauz):
+    """The literal collision of a wall node (Eq. 14; Eq. 3 for bounce-back; Eq. 4
+    for free-slip) on the 19 populations f that reached it."""
+    out = np.zeros(19)
+    lib().orc_wall_node_collide(C.byref(params), int(wall), np.ascontiguousarray(f, dtype=np.float64),
+                                float(taux), float(tauz), out)
+    return out
 
 
 def spalding_yplus(uplus, kappa=0.41, b=5.5):
@@ -292,6 +321,25 @@ class Oracle:
                     dsum[wall, z, x] = s1 - s0
                     rho[wall, z, x] = s0
         return dsum, rho
+
+    def wall_nodes(self):
+        """(fw [2, 5, nz, nx]: what the wall nodes send into the fluid next step, in
+        the direction order IN_W; urec [2, nz, nx, 3]: the first layer's rho, u_x,
+        u_z of the latest step)."""
+        nx, nz = self.params.nx, self.params.nz
+        fw = np.zeros(2 * 5 * nz * nx)
+        ur = np.zeros(2 * nz * nx * 3)
+        st = lib().orc_get_wall_nodes(self._h, fw, ur)
+        if st != OK:
+            raise RuntimeError("oracle has no wall nodes")
+        return fw.reshape(2, 5, nz, nx), ur.reshape(2, nz, nx, 3)
+
+    def set_wall_nodes(self, fw, urec):
+        """Sets the wall-node state (layouts of wall_nodes())."""
+        st = lib().orc_set_wall_nodes(self._h, np.ascontiguousarray(fw, dtype=np.float64).reshape(-1),
+                                      np.ascontiguousarray(urec, dtype=np.float64).reshape(-1))
+        if st != OK:
+            raise RuntimeError("oracle has no wall nodes")
 
     def stats_sums(self):
         out = np.zeros(8 * self.params.ny)

@@ -68,7 +68,8 @@ class Channel:
 
     def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
                  device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False,
-                 vector=0, brick=0, collision="bgk", mrt_rates=None, van_driest=0.0, van_driest_utau=0.0):
+                 vector=0, brick=0, collision="bgk", mrt_rates=None, van_driest=0.0, van_driest_utau=0.0,
+                 wall_nodes=False):
         import torch
         self.lib = L.lib()
         self.shape = (nz, ny, nx)
@@ -94,6 +95,8 @@ class Channel:
         if brick:
             self._set(L.LBM_P_BRICK, brick)
         set_collision(self._set, collision, mrt_rates, van_driest, van_driest_utau)
+        if wall_nodes:
+            self._set(L.LBM_P_WALL_NODES, 1)
         nbytes = C.c_size_t(0)
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value
@@ -241,6 +244,15 @@ class Channel:
         rho = np.empty(2 * self.nx * self.nz)
         self._chk(self.lib.lbm_wall_mass_change(self._h, L.dptr(ds), L.dptr(rho)))
         return ds.reshape(2, self.nz, self.nx), rho.reshape(2, self.nz, self.nx)
+
+    def wall_nodes(self):
+        """Wall-node state: (fw [2, 5, nz, nx] as h = f - w, what the wall nodes send
+        into the fluid next step; rec [2, nz, nx, 4]: the first layer's rho, u_x,
+        u_z, u_tau of the latest step)."""
+        fw = np.empty(10 * self.nx * self.nz)
+        rec = np.empty(8 * self.nx * self.nz)
+        self._chk(self.lib.lbm_get_wall_nodes(self._h, L.dptr(fw), L.dptr(rec)))
+        return fw.reshape(2, 5, self.nz, self.nx), rec.reshape(2, self.nz, self.nx, 4)
 
     def stats_reset(self):
         self._chk(self.lib.lbm_stats_reset(self._h))

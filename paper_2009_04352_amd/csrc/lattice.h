@@ -43,7 +43,23 @@ constexpr bool enters_top(int a) { return kEy[a] == -1; }
 // every wall-crossing direction except the wall-normal ones.
 constexpr bool is_tangential(int a) { return kEx[a] != 0 || kEz[a] != 0; }
 
+// Wall nodes: the populations the bottom wall node sends into the fluid
+// (e_y = +1), in the order of the wall-node rings; the top wall's are their
+// mirror images.  in_index_b(a): position of a in that list (-1 if absent).
+constexpr int kInB[5] = {3, 7, 11, 14, 17};
+constexpr int in_index_b(int a)
+{
+    for (int k = 0; k < 5; ++k)
+        if (kInB[k] == a) return k;
+    return -1;
+}
+// ring element of the arrival a mirror reflection turns into kInB[k]
+// (opp(mirror_y(kInB[k])) holds it; bounce-back uses element k itself)
+constexpr int node_spec(int k) { return in_index_b(opp(mirror_y(kInB[k]))); }
+
 static_assert(opp(7) == 8 && opp(13) == 14 && opp(17) == 18, "pair numbering");
+static_assert(node_spec(0) == 0 && node_spec(1) == 3 && node_spec(2) == 4 && node_spec(3) == 1 && node_spec(4) == 2,
+              "mirror pairs 7-13, 14-8, 11-18, 17-12 of Eq. 14");
 static_assert(mirror_y(7) == 13 && mirror_y(14) == 8 && mirror_y(11) == 18 && mirror_y(17) == 12,
               "mirror pairs of the WFB collision");
 

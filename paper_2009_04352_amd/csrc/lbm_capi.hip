@@ -57,6 +57,9 @@ struct lbm_ctx {
     double vd_utau = 0.0;        // friction velocity of the damping's y+; 0 = sqrt(|Fx| ny / 2)
     int spread = -1;             // launch order: log2 of the tile chunks that cycle through the bricks; 0 = memory
                                  // order; -1 = by store format (spread_log2)
+    int wall_nodes = 0;          // 1: wall nodes one spacing outside the first and last layer (fixed once initialised)
+    void* dwn = nullptr;         // wall-node rings (wn_index) and first-layer records
+    double* dwn_rec = nullptr;
 
     void* h = nullptr;
     size_t bytes = 0;
@@ -204,7 +207,7 @@ void drop_graphs(lbm_ctx* c)
 bool odd_by_rows(const lbm_ctx* c, int mode)
 {
     const int vw = vector_width(c);
-    if (mode == 0 || !rows_ok(c->nx, vw)) return false;
+    if (mode == 0 || c->wall_nodes || !rows_ok(c->nx, vw)) return false;
     return mode == 2 || (store_bytes(c->store) == 2 && c->nx / vw > c->tile_odd);
 }
 
@@ -251,6 +254,9 @@ StepArgs step_args(const lbm_ctx* c, bool odd, int rows_mode)
     a.newton_tol = c->newton_tol;
     a.flags = c->dflags;
     a.partials = nullptr;
+    a.wall_nodes = c->wall_nodes;
+    a.wn = c->dwn;
+    a.wn_rec = c->dwn_rec;
     return a;
 }
 
@@ -274,6 +280,9 @@ ObsArgs obs_args(const lbm_ctx* c)
     a.bconst = c->bconst;
     a.ekb = std::exp(-c->kappa * c->bconst);
     a.newton_tol = c->newton_tol;
+    a.wall_nodes = c->wall_nodes;
+    a.wn = c->dwn;
+    a.wn_rec = c->dwn_rec;
     return a;
 }
 
@@ -374,16 +383,38 @@ int check_ready(lbm_ctx* c)
 }
 
 // Moves the wall-crossing populations of a streamed layout when the boundary
-// switched between bounce-back and mirror reflection.
+// switched between bounce-back and mirror reflection (halfway walls only:
+// with wall nodes the reflection happens in the wall-node collision).
 int fix_layout(lbm_ctx* c)
 {
-    if (!c->initialized || !c->layout_s) return LBM_OK;
+    if (!c->initialized || !c->layout_s || c->wall_nodes) return LBM_OK;
     const int want = (c->bc != kBB);
     if (want == c->layout_spec) return LBM_OK;
     if (!c->dtmp) LBM_HIP(c, hipMalloc((void**)&c->dtmp, (size_t)2 * c->nx * c->nz * 5 * sizeof(double)));
     LBM_HIP(c, launch_relayout(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->layout_spec, want, c->dtmp,
                                c->stream));
     c->layout_spec = want;
+    return LBM_OK;
+}
+
+// Wall-node rings and records (allocated with the first initialisation in
+// wall-node mode; 4 rings of 10 nx nz elements, 2 nx nz records of 4 doubles).
+int ensure_wall_nodes(lbm_ctx* c)
+{
+    if (!c->wall_nodes || c->dwn) return LBM_OK;
+    const size_t ring = (size_t)10 * c->nx * c->nz * (size_t)store_bytes(c->store);
+    LBM_HIP(c, hipMalloc(&c->dwn, 4 * ring));
+    LBM_HIP(c, hipMalloc((void**)&c->dwn_rec, (size_t)2 * c->nx * c->nz * 4 * sizeof(double)));
+    return LBM_OK;
+}
+
+// After a state set from outside (layout P): the wall nodes start from it.
+int start_wall_nodes(lbm_ctx* c)
+{
+    if (!c->wall_nodes) return LBM_OK;
+    int st = ensure_wall_nodes(c);
+    if (st != LBM_OK) return st;
+    LBM_HIP(c, launch_node_start(c->store, step_args(c, false, 0), c->stream));
     return LBM_OK;
 }
 
@@ -477,6 +508,8 @@ void lbm_destroy(lbm_ctx* c)
     if (c->dpart) (void)hipFree(c->dpart);
     if (c->dtmp) (void)hipFree(c->dtmp);
     if (c->dcs2) (void)hipFree(c->dcs2);
+    if (c->dwn) (void)hipFree(c->dwn);
+    if (c->dwn_rec) (void)hipFree(c->dwn_rec);
     delete c;
 }
 
@@ -583,6 +616,19 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
                 if (!(v >= 0.0)) return fail(c, LBM_E_ARG, "van Driest friction velocity must be >= 0");
                 c->vd_utau = v;
                 break;
+            case LBM_P_WALL_NODES:
+                if (c->initialized)
+                    return fail(c, LBM_E_STATE, "the wall placement is fixed once the state is initialised");
+                if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "wall nodes is 0 (halfway walls) or 1");
+                if (c->wall_nodes != (int)v && c->dwn) {
+                    drop_graphs(c);
+                    (void)hipFree(c->dwn);
+                    (void)hipFree(c->dwn_rec);
+                    c->dwn = nullptr;
+                    c->dwn_rec = nullptr;
+                }
+                c->wall_nodes = (int)v;
+                break;
             default:
                 return fail(c, LBM_E_ARG, "unknown or read-only parameter key");
         }
@@ -618,6 +664,7 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
             case LBM_P_MRT_S_M: *v = c->mrt_s[key - LBM_P_MRT_S_E]; break;
             case LBM_P_VD_APLUS: *v = c->vd_aplus; break;
             case LBM_P_VD_UTAU: *v = c->vd_utau; break;
+            case LBM_P_WALL_NODES: *v = c->wall_nodes; break;
             case LBM_P_GRAPH_STEPS: *v = c->graph_steps; break;
             case LBM_P_BC: *v = c->bc; break;
             case LBM_P_TAU0: *v = c->tau0; break;
@@ -724,6 +771,7 @@ static int init_spalding_impl(lbm_ctx* c, double u_tau, double noise, uint64_t s
     c->layout_spec = (c->bc != kBB);
     c->initialized = true;
     int st = reset_flags(c);
+    if (st == LBM_OK) st = start_wall_nodes(c);
     if (st != LBM_OK) return st;
     LBM_HIP(c, hipStreamSynchronize(c->stream));  // the profile lives on the host stack
     return LBM_OK;
@@ -767,6 +815,7 @@ int lbm_init_moments(lbm_ctx* c, const double* rho, const double* u)
         c->layout_spec = (c->bc != kBB);
         c->initialized = true;
         st = reset_flags(c);
+        if (st == LBM_OK) st = start_wall_nodes(c);
         if (st != LBM_OK) return st;
         LBM_HIP(c, hipStreamSynchronize(c->stream));
         return LBM_OK;
@@ -806,6 +855,7 @@ int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
         c->layout_spec = (c->bc != kBB);
         c->initialized = true;
         st = reset_flags(c);
+        if (st == LBM_OK) st = start_wall_nodes(c);
         if (st != LBM_OK) return st;
         LBM_HIP(c, hipStreamSynchronize(c->stream));
         return LBM_OK;
@@ -840,7 +890,8 @@ static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, dou
                                c->stream);
         if (e == hipSuccess)
             e = launch_get_state(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->layout_s, c->layout_spec,
-                                 cells ? dcells : nullptr, cells ? 0 : first, cnt, tmp, c->stream);
+                                 cells ? dcells : nullptr, cells ? 0 : first, cnt, tmp, c->wall_nodes ? c->dwn : nullptr,
+                                 c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(stage.data(), tmp, (size_t)cnt * 19 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1124,6 +1175,7 @@ int lbm_wall_mass_change(lbm_ctx* c, double* dsum, double* rho)
     return guard(c, [&]() -> int {
         if (!c) return fail(nullptr, LBM_E_ARG, "null context");
         if (!dsum && !rho) return fail(c, LBM_E_ARG, "null argument");
+        if (c->wall_nodes) return fail(c, LBM_E_STATE, "the mass check is defined for the first-layer correction of halfway walls");
         const long long m = 2ll * c->nx * c->nz;
         std::vector<double> buf((size_t)m * 4), dm((size_t)m * 2);
         int st = observe_impl(c, 1, m, nullptr, buf.data(), nullptr, dm.data());
@@ -1181,6 +1233,36 @@ int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t*
         for (size_t i = 0; i < hc.size(); ++i) counts[i] = (int64_t)hc[i];
         mean_std[0] = hms[0];
         mean_std[1] = hms[1];
+        return LBM_OK;
+    });
+}
+
+int lbm_get_wall_nodes(lbm_ctx* c, double* fw, double* rec)
+{
+    return guard(c, [&]() -> int {
+        int st = check_ready(c);
+        if (st != LBM_OK) return st;
+        if (!c->wall_nodes) return fail(c, LBM_E_STATE, "the context has no wall nodes");
+        if (!fw && !rec) return fail(c, LBM_E_ARG, "null argument");
+        DeviceGuard dg(c->dev);
+        if ((st = sync_check(c)) != LBM_OK) return st;
+        const size_t m = (size_t)2 * c->nx * c->nz;
+        std::vector<double> hf(fw ? 5 * m : 0), hr(rec ? 4 * m : 0);
+        double* tmp = nullptr;
+        hipError_t e = hipSuccess;
+        if (fw) {
+            e = hipMalloc((void**)&tmp, 5 * m * sizeof(double));
+            if (e == hipSuccess) e = launch_node_get(c->store, c->dwn, c->layout_s, c->nx, c->nz, tmp, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(hf.data(), tmp, 5 * m * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        }
+        if (e == hipSuccess && rec)
+            e = hipMemcpyAsync(hr.data(), c->dwn_rec, 4 * m * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (tmp) (void)hipFree(tmp);
+        if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("wall nodes: ") + hipGetErrorString(e));
+        if (fw) std::memcpy(fw, hf.data(), hf.size() * sizeof(double));
+        if (rec) std::memcpy(rec, hr.data(), hr.size() * sizeof(double));
         return LBM_OK;
     });
 }

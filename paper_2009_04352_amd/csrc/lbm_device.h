@@ -621,6 +621,25 @@ struct Lane {
         if constexpr (kBytes == 4) *(unsigned int*)p = b;
         else *(unsigned short*)p = (unsigned short)b;
     }
+    // element j of a group of 2- or 4-byte elements (V >= 2), as raw bits
+    __device__ __forceinline__ static unsigned int elem(u32x2 v, int j)
+    {
+        static_assert(V >= 2 && kBytes <= 4, "groups of several elements");
+        if constexpr (kBytes == 4) {
+            return j == 0 ? v.x : v.y;
+        } else {
+            const unsigned int word = (j < 2) ? v.x : v.y;
+            return (j & 1) ? (word >> 16) : (word & 0xffffu);
+        }
+    }
+    // the group of V raw elements
+    __device__ __forceinline__ static u32x2 from_elems(const unsigned int (&e)[V])
+    {
+        static_assert(V >= 2 && kBytes <= 4, "groups of several elements");
+        if constexpr (kBytes == 4) return u32x2{e[0], e[1]};
+        else if constexpr (V == 2) return u32x2{e[0] | (e[1] << 16), 0u};
+        else return u32x2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+    }
     __device__ __forceinline__ static unsigned int first(u32x2 v)
     {
         if constexpr (kBytes == 4) return v.x;

@@ -103,7 +103,27 @@ struct StepArgs {
     double newton_tol;
     DevFlags* flags;
     double* partials;     // [nz][ny][ntx][7] statistics partial sums; nullptr on steps not sampled
+    // wall nodes (wall_nodes = 1): the wall grid as a lattice node one spacing
+    // outside the first fluid layer (see wn_index); bc is then the reflection
+    // made at the wall nodes
+    int wall_nodes;
+    void* wn;             // four rings of the store type, wn_index
+    double* wn_rec;       // [2 walls][nz][nx][4]: first layer's rho, u_x, u_z and u_tau of the latest step
 };
+
+// Wall-node rings, each [2 walls][5][nz][nx] elements of the store type:
+//   ring s (s = 0, 1): the populations the first layer sent towards the wall
+//     nodes, written by the step kernel of parity s (odd kernel: 1, even: 0;
+//     initialisation: 0), element k of wall node (x, z) holding the
+//     population arriving from direction opp(IN_k) (its reversal is IN_k);
+//   ring 2 + s: what the wall nodes send into the fluid, written by the
+//     kernel of parity s, element k being direction IN_k.
+// IN_k = 3, 7, 11, 14, 17 at the bottom wall (e_y = +1), their mirror images
+// 4, 13, 18, 8, 12 at the top.
+__host__ __device__ inline long long wn_index(int ring, int w, int k, int z, int x, int nx, int nz)
+{
+    return ((((long long)ring * 2 + w) * 5 + k) * nz + z) * (long long)nx + x;
+}
 
 struct ObsArgs {
     const void* h;
@@ -125,6 +145,9 @@ struct ObsArgs {
     double* dmass;        // optional, mode 1: [count][2] = change of the population sum made
                           // by the wall correction, rho before it (Eq. B-1)
     int mode;
+    int wall_nodes;       // the state has wall nodes (StepArgs::wall_nodes)
+    const void* wn;       // their rings (wn_index) and records
+    const double* wn_rec;
 };
 
 // launchers (lbm_kernels.hip); each returns the launch status
@@ -147,13 +170,20 @@ hipError_t launch_init_moments(int store, void* h, long long n, int nx, int ny, 
                                long long count, const double* in, hipStream_t s);
 hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int brick, int layout_s,
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
-                            hipStream_t s);
+                            const void* wn, hipStream_t s);
 hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s);
 hipError_t launch_yplus_pdf(const double* rec, long long m, double y1, double nu0, double* ms, double lo, double scale,
                             int nbins, unsigned long long* counts, hipStream_t s);
 hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int brick, int from_spec,
                            int to_spec, double* tmp, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+// wall nodes of a state set from outside (layout P): the first layer's plain
+// moments and friction velocity, its wall-bound populations in arrival ring 0
+// and one wall-node collision of them in output ring 2 (bc: the reflection)
+hipError_t launch_node_start(int store, const StepArgs& a, hipStream_t s);
+// the wall-node state for observation: outputs of ring 2 + slot as h = f - w,
+// [2][5][nz][nx] doubles
+hipError_t launch_node_get(int store, const void* wn, int slot, int nx, int nz, double* out, hipStream_t s);
 hipError_t launch_codec(int store, const float* in, float* out, long long n, hipStream_t s);
 // per-store step launchers (lbm_step.h), dispatched by launch_step / launch_batch_step
 template <typename S>

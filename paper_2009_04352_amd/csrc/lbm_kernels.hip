@@ -108,6 +108,7 @@ void set_spread(StepArgs& a, int log2)
 static bool step_args_ok(int store, const StepArgs& a)
 {
     if (a.tile_x < 64 || a.tile_x > kMaxBlock || (a.tile_x & 63) || a.ntiles < 1) return false;
+    if (a.wall_nodes && (!a.wn || !a.wn_rec || a.nseg > 0)) return false;
     if (!step_vector_width_ok(store, a.nx, a.vw)) return false;
     // the thread part of an address is (row in tile * nx + x) * bytes < 32 bits
     if ((long long)a.nx * a.ny * store_bytes(store) > 0xffffffffll) return false;
@@ -301,7 +302,8 @@ __device__ __forceinline__ long long cell_at(int x, int y, int z, int nx, int ny
 template <typename S>
 __global__ __launch_bounds__(256) void k_get_state(const void* hv, long long n, int nx, int ny, int nz, int brick,
                                                    int layout_s, int layout_spec, const long long* __restrict__ cells,
-                                                   long long first, long long count, double* __restrict__ out)
+                                                   long long first, long long count, double* __restrict__ out,
+                                                   const void* __restrict__ wn)
 {
     using T = typename S::T;
     const T* h = (const T*)hv;
@@ -312,6 +314,19 @@ __global__ __launch_bounds__(256) void k_get_state(const void* hv, long long n, 
     const long long m = cell_index(q.x, q.y, q.z, nx, ny, nz, brick);
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
+        if (wn) {
+            // wall nodes: a first-layer population bound for the wall node at x + e_a waits
+            // in the arrival ring of the latest step
+            const int dy = q.y + kEy[a];
+            if (dy < 0 || dy >= ny) {
+                const bool tp = dy >= ny;
+                const int k = tp ? in_index_b(mirror_y(opp(a))) : in_index_b(opp(a));
+                const long long r = wn_index(layout_s, tp ? 1 : 0, k, (q.z + kEz[a] + nz) % nz, (q.x + kEx[a] + nx) % nx,
+                                             nx, nz);
+                out[(long long)a * count + i] = S::to_double(((const T*)wn)[r]);
+                return;
+            }
+        }
         long long src;
         int slot;
         if (!layout_s) {
@@ -367,10 +382,18 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
         constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
+        const int sy = y - ey;
+        if (p.wall_nodes && (sy < 0 || sy >= p.ny)) {
+            // what the wall node at x - e_a sends into the fluid next step
+            const bool tp = sy >= p.ny;
+            const int k = tp ? in_index_b(mirror_y(a)) : in_index_b(a);
+            f[a] = S::load((const T*)p.wn + wn_index(2 + p.layout_s, tp ? 1 : 0, k, (z - ez + p.nz) % p.nz,
+                                                     (x - ex + p.nx) % p.nx, p.nx, p.nz));
+            return;
+        }
         if (p.layout_s) {
             f[a] = S::load(h + (long long)a * n + c);
         } else {
-            const int sy = y - ey;
             if (sy >= 0 && sy < p.ny) {
                 f[a] = S::load(h + (long long)opp(a) * n + cell_at(x - ex, sy, z - ez, p.nx, p.ny, p.nz, p.brick));
             } else if (p.bc == kBB || !is_tangential(a)) {
@@ -387,7 +410,7 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
     // over the deviations h_a = f_a - w_a the step holds (the weights cancel)
     R sum0 = R(0);
     if (p.dmass) for_each_dir([&](auto A) { sum0 += f[decltype(A)::value]; });
-    if (p.bc == kWFB && (bot || top)) {
+    if (p.bc == kWFB && (bot || top) && !p.wall_nodes) {
         bool fail = false;
         rec = wfb_correct<R>(f, top, p.fx, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, iters,
                           fail);
@@ -421,7 +444,32 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
         }
         return;
     }
-    if (p.bc == kBB) {
+    if (p.wall_nodes) {
+        // the stress the next wall-node collision applies (WFB, from the first
+        // layer's record), the momentum exchange of the populations waiting to be
+        // reversed there (bounce-back), nothing for free-slip
+        const int wl = top ? 1 : 0;
+        const double* r = p.wn_rec + (((long long)wl * p.nz + z) * p.nx + x) * 4;
+        const double U = sqrt(r[1] * r[1] + r[2] * r[2]);
+        rec = WallRecord{0.0, 0.0, 0.0, U};
+        if (p.bc == kWFB) {
+            rec = wall_record(r[0], r[1], r[2], U, r[3]);
+        } else if (p.bc == kBB) {
+            double tx = 0.0, tz = 0.0;
+            for_each_dir([&](auto B) {
+                constexpr int b = decltype(B)::value;
+                if ((kEy[b] == -1 && !top) || (kEy[b] == 1 && top)) {
+                    const int k = top ? in_index_b(mirror_y(opp(b))) : in_index_b(opp(b));
+                    const double fb = S::to_double(((const T*)p.wn)[wn_index(p.layout_s, wl, k, z, x, p.nx, p.nz)]);
+                    tx += -2.0 * kEx[b] * fb;
+                    tz += -2.0 * kEz[b] * fb;
+                }
+            });
+            rec.taux = tx;
+            rec.tauz = tz;
+            rec.utau = sqrt(sqrt(tx * tx + tz * tz) / r[0]);
+        }
+    } else if (p.bc == kBB) {
         // force on the fluid by momentum exchange: every population leaving through the
         // wall comes back reversed; f*_b sits in slot opp(b) of the cell in both layouts
         double tx = 0.0, tz = 0.0;
@@ -441,6 +489,7 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
     } else if (p.bc == kFreeSlip) {
         rec.U = sqrt((double)ux * (double)ux + (double)uz * (double)uz);
     }
+    if (p.wall_nodes) iters = 0;
     double* o = p.out + 4 * i;
     o[0] = rec.taux; o[1] = rec.tauz; o[2] = rec.utau; o[3] = rec.U;
     if (p.iters) p.iters[i] = iters;
@@ -524,6 +573,86 @@ __global__ __launch_bounds__(256) void k_codec(const float* __restrict__ in, flo
         if (g * V + k < n) out[g * V + k] = (float)Ln::get(w, k);
 }
 
+// ------------------------------------------------------------- wall nodes
+
+// Wall nodes of a state set from outside (layout P), one thread per wall
+// node (x, z) of wall w = i / (nx nz): the record of the first-layer cell
+// below (above) it, from the plain moments of its post-collision populations
+// (rho = sum f, u = sum e f / rho) and Spalding's law; the populations its
+// in-plane neighbours x - e_b send towards it (arrival ring 0); and one
+// wall-node collision of them (output ring 2), as if the state had also been
+// the previous step's.
+template <typename S>
+__global__ __launch_bounds__(256) void k_node_start(StepArgs p)
+{
+    using T = typename S::T;
+    const T* h = (const T*)p.h;
+    T* wn = (T*)p.wn;
+    const long long per = (long long)p.nx * p.nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * per) return;
+    const int wl = (int)(i / per);
+    const int z = (int)((i % per) / p.nx), x = (int)(i % p.nx);
+    const int y = wl ? p.ny - 1 : 0;
+    const long long n = p.n;
+    const long long c = cell_index(x, y, z, p.nx, p.ny, p.nz, p.brick);
+    double drho = 0.0, jx = 0.0, jz = 0.0;
+    for_each_dir([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        const double v = S::to_double(h[(long long)opp(a) * n + c]);
+        drho += v;
+        if constexpr (kEx[a] != 0) jx += kEx[a] * v;
+        if constexpr (kEz[a] != 0) jz += kEz[a] * v;
+    });
+    const double rho = 1.0 + drho, ux = jx / rho, uz = jz / rho;
+    const double U[1] = {sqrt(ux * ux + uz * uz)};
+    double ut[1];
+    int it = 0;
+    bool fail = false;
+    wall_utau_n<1>(U, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, ut, it, fail);
+    if (fail) {
+        atomicOr(&p.flags->status, 2);
+        atomicMin(&p.flags->first_bad, 0ull);
+    }
+    double* r = p.wn_rec + (((long long)wl * p.nz + z) * p.nx + x) * 4;
+    r[0] = rho; r[1] = ux; r[2] = uz; r[3] = ut[0];
+    double arr[5];
+    for_each_dir([&](auto B) {
+        constexpr int b = decltype(B)::value;
+        if ((kEy[b] == -1 && wl == 0) || (kEy[b] == 1 && wl == 1)) {
+            const int k = wl ? in_index_b(mirror_y(opp(b))) : in_index_b(opp(b));
+            const long long src = cell_index((x - kEx[b] + p.nx) % p.nx, y, (z - kEz[b] + p.nz) % p.nz, p.nx, p.ny,
+                                             p.nz, p.brick);
+            const T v = h[(long long)opp(b) * n + src];
+            wn[wn_index(0, wl, k, z, x, p.nx, p.nz)] = v;
+            arr[k] = S::to_double(v);
+        }
+    });
+    const WallRecord rec = wall_record(rho, ux, uz, U[0], ut[0]);
+    const bool wfb = (p.bc == kWFB), bb = (p.bc == kBB);
+    for (int k = 0; k < 5; ++k) {
+        double v = arr[bb ? k : node_spec(k)];
+        if (wfb) {
+            if (k == 1) v += 0.5 * rec.taux;
+            else if (k == 3) v -= 0.5 * rec.taux;
+            else if (k == 2) v += 0.5 * rec.tauz;
+            else if (k == 4) v -= 0.5 * rec.tauz;
+        }
+        wn[wn_index(2, wl, k, z, x, p.nx, p.nz)] = S::from_double(v);
+    }
+}
+
+// out[w][k][z][x] = output ring 2 + slot as doubles
+template <typename S>
+__global__ __launch_bounds__(256) void k_node_get(const void* wn, int slot, int nx, int nz, double* __restrict__ out)
+{
+    using T = typename S::T;
+    const long long m = 10ll * nx * nz;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    out[i] = S::to_double(((const T*)wn)[wn_index(2 + slot, 0, 0, 0, 0, nx, nz) + i]);
+}
+
 // ---------------------------------------------------------------- launchers
 
 template <template <typename> class K, typename... Args>
@@ -546,6 +675,8 @@ template <typename S> struct GetK { static constexpr auto fn = k_get_state<S>; }
 template <typename S> struct ObsK { static constexpr auto fn = k_observe<S>; };
 template <typename S> struct RelK { static constexpr auto fn = k_relayout<S>; };
 template <typename S> struct CodecK { static constexpr auto fn = k_codec<S>; };
+template <typename S> struct NodeStartK { static constexpr auto fn = k_node_start<S>; };
+template <typename S> struct NodeGetK { static constexpr auto fn = k_node_get<S>; };
 
 static dim3 blocks_for(long long n, int bs) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
@@ -575,11 +706,24 @@ hipError_t launch_init_moments(int store, void* h, long long n, int nx, int ny, 
 
 hipError_t launch_get_state(int store, const void* h, long long n, int nx, int ny, int nz, int brick, int layout_s,
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
-                            hipStream_t s)
+                            const void* wn, hipStream_t s)
 {
     if (count <= 0) return hipSuccess;
     return dispatch_store<GetK>(store, blocks_for(count, 256), dim3(256), s, h, n, nx, ny, nz, brick, layout_s,
-                                layout_spec, cells, first, count, out);
+                                layout_spec, cells, first, count, out, wn);
+}
+
+hipError_t launch_node_start(int store, const StepArgs& a, hipStream_t s)
+{
+    if (!a.wall_nodes || !a.wn || !a.wn_rec) return hipErrorInvalidValue;
+    const long long m = 2ll * a.nx * a.nz;
+    return dispatch_store<NodeStartK>(store, blocks_for(m, 256), dim3(256), s, a);
+}
+
+hipError_t launch_node_get(int store, const void* wn, int slot, int nx, int nz, double* out, hipStream_t s)
+{
+    if (!wn || slot < 0 || slot > 1) return hipErrorInvalidValue;
+    return dispatch_store<NodeGetK>(store, blocks_for(10ll * nx * nz, 256), dim3(256), s, wn, slot, nx, nz, out);
 }
 
 hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s)

@@ -201,6 +201,149 @@ __device__ __forceinline__ void collide_group(u32x2 (&w)[kQ], const StepArgs& p,
 // from the instance table for batched launches (instances differ).
 constexpr int kBCRuntime = 3;
 
+// ------------------------------------------------------------ wall nodes
+//
+// The wall grid of Sec. 2.1-2.2 taken literally: a lattice node one spacing
+// outside each wall layer of fluid (y = -1 and y = ny), where the reflection
+// happens (bounce-back, Eq. 3; mirror reflection, Eq. 4; WFB, Eq. 14).  A
+// population the first layer sends towards the wall reaches the wall node
+// of its column x + e_b one step later, is reflected there with the stress
+// of Eq. 15-17 from the first layer's velocity of that (previous) step, and
+// streams into the first layer at x + e_b + e_a one step after that: a lag of
+// one step and twice the tangential shift of the halfway walls.  The kernel
+// of the first-layer cell at column (x, z) also does the wall node's
+// collision at (x, z); the rings that carry the populations in flight are
+// described at wn_index.  (kBCNode: the reflection, StepArgs::bc, is read at
+// run time.)
+constexpr int kBCNode = 4;
+// element k of a wall node holding direction A, which enters the fluid from wall `top`
+template <int A>
+__device__ __forceinline__ int node_k(bool top)
+{
+    return top ? in_index_b(mirror_y(A)) : in_index_b(A);
+}
+
+__device__ __forceinline__ int wrap_x(int x, int nx) { return x < 0 ? x + nx : (x >= nx ? x - nx : x); }
+
+// The group of cells x0 .. x0 + V - 1 of a ring row, shifted by sh (the
+// elements x0 + j + sh, x periodic).
+template <typename S, int V>
+__device__ __forceinline__ u32x2 ring_load(const typename S::T* row, int x0, int sh, int nx)
+{
+    using Ln = Lane<S, V>;
+    if (sh == 0) return Ln::template load<false>(row + x0);
+    if constexpr (V == 1) {
+        return Ln::template load<false>(row + wrap_x(x0 + sh, nx));
+    } else {
+        unsigned int e[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) e[j] = Ln::load_elem(row + wrap_x(x0 + j + sh, nx));
+        return Ln::from_elems(e);
+    }
+}
+
+template <typename S, int V>
+__device__ __forceinline__ void ring_store(typename S::T* row, int x0, int sh, int nx, u32x2 g)
+{
+    using Ln = Lane<S, V>;
+    if (sh == 0) {
+        Ln::template store<false>(row + x0, g);
+        return;
+    }
+    if constexpr (V == 1) {
+        Ln::template store<false>(row + wrap_x(x0 + sh, nx), g);
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) Ln::store_elem(row + wrap_x(x0 + j + sh, nx), Ln::elem(g, j));
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ typename S::T* ring_row(const StepArgs& p, int ring, int wl, int k, int zz)
+{
+    return (typename S::T*)p.wn + wn_index(ring, wl, k, zz, 0, p.nx, p.nz);
+}
+
+// The wall-node collision of the V nodes below (above) this thread's cells:
+// the arrivals of the previous step (ring `prev`) reflected by the boundary
+// p.bc, with +-tau/2 on the four diagonals for WFB (Eq. 14a-b; tau from the
+// first layer's record of the previous step, Eq. 15-17), into output ring
+// 2 + cur.
+template <typename S, int V>
+__device__ __forceinline__ void node_collide(const StepArgs& p, bool top, int z, int x0, int prev, int cur)
+{
+    using R = typename S::R;
+    using Ln = Lane<S, V>;
+    const int wl = top ? 1 : 0;
+    const bool wfb = (p.bc == kWFB), bb = (p.bc == kBB);
+    R hx[V], hz[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        hx[j] = R(0);
+        hz[j] = R(0);
+        if (wfb) {
+            const double* r = p.wn_rec + (((long long)wl * p.nz + z) * p.nx + x0 + j) * 4;
+            const double rho = r[0], ux = r[1], uz = r[2], ut = r[3];
+            const double U = sqrt(ux * ux + uz * uz);
+            const WallRecord rec = wall_record(rho, ux, uz, U, ut);
+            hx[j] = (R)(0.5 * rec.taux);
+            hz[j] = (R)(0.5 * rec.tauz);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int ka = bb ? k : node_spec(k);
+        u32x2 g = Ln::template load<false>(ring_row<S>(p, prev, wl, ka, z) + x0);
+        if (wfb && k > 0) {
+            // k = 1, 3: +-tau_x / 2 (directions 7, 14); k = 2, 4: +-tau_z / 2 (11, 17)
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const R d = (k == 1) ? hx[j] : (k == 3) ? -hx[j] : (k == 2) ? hz[j] : -hz[j];
+                Ln::set(g, j, Ln::get(g, j) + d);
+            }
+        }
+        Ln::template store<false>(ring_row<S>(p, 2 + cur, wl, k, z) + x0, g);
+    }
+}
+
+// The record of the first-layer cells for the next wall-node collision:
+// density, wall-parallel velocity and the friction velocity of Spalding's law
+// (solved in FP64 as for the halfway walls), one solve per cell.
+template <int V>
+__device__ __forceinline__ void node_record(const StepArgs& p, bool top, int z, int x0, const double (&rho)[V],
+                                            const double (&ux)[V], const double (&uz)[V], int& iters, bool& fail)
+{
+    double U[V], ut[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) U[j] = sqrt(ux[j] * ux[j] + uz[j] * uz[j]);
+    iters = 0;
+    fail = false;
+#pragma unroll 1
+    for (int j = 0; j < V; ++j) {
+        double u1[1] = {U[0]}, t1[1];
+#pragma unroll
+        for (int i = 1; i < V; ++i)
+            if (j == i) u1[0] = U[i];
+        int it;
+        bool fl;
+        wall_utau_n<1>(u1, p.y1, p.nu0, p.kappa, p.bconst, p.ekb, p.newton_tol, p.newton_maxit, t1, it, fl);
+        iters = max(iters, it);
+        fail = fail || fl;
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+            if (j == i) ut[i] = t1[0];
+    }
+    const int wl = top ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        double* r = p.wn_rec + (((long long)wl * p.nz + z) * p.nx + x0 + j) * 4;
+        r[0] = rho[j];
+        r[1] = ux[j];
+        r[2] = uz[j];
+        r[3] = ut[j];
+    }
+}
+
 // One time step for V consecutive cells per thread.  A block holds one tile
 // of an instance: either `rpb` whole x-rows of one z-plane (nx / V threads
 // per row) or one segment of a single x-row (tile_x threads).  Every global
@@ -247,8 +390,16 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     tile = spread_tile(tile, p);
     const bool spec = BATCH ? (p.bc != kBB) : (BCT != kBB);
     const bool wfb = BATCH ? (p.bc == kWFB) : (BCT == kWFB);
+    constexpr bool NODE = (BCT == kBCNode);          // wall nodes instead of halfway walls
     constexpr bool MAYBE_WFB = BATCH || BCT == kWFB;
-    constexpr bool MAYBE_SPEC = BATCH || BCT != kBB;
+    constexpr bool MAYBE_SPEC = BATCH || (BCT != kBB && !NODE);
+    constexpr int cur = ODD ? 1 : 0, prev = 1 - cur; // wall-node rings written / read by this kernel
+    // One cell per thread: the odd step's x-shifts are plain address offsets
+    // (every load and store of a wavefront still covers consecutive elements;
+    // the AA rule that a cell reads exactly the slots it writes makes this
+    // race-free without an exchange or a barrier).  Groups of V > 1 cells
+    // shift through LDS so that every access stays group-aligned.
+    constexpr bool DIRECT = ODD && (V == 1);
 
     const long long N = p.n;
     const int t = (int)threadIdx.x;
@@ -325,13 +476,25 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int ey = kEy[a], ez = kEz[a];
+            if constexpr (NODE) {
+                if ((ey == 1 && bot) || (ey == -1 && top)) {
+                    // from the wall node at x - e_a: what it sent on the previous step
+                    const int zz = ez > 0 ? zm : (ez < 0 ? zp : z);
+                    w[a] = ring_load<S, V>(ring_row<S>(p, 2 + prev, top ? 1 : 0, node_k<a>(top), zz), L.x0, -kEx[a],
+                                           p.nx);
+                    return;
+                }
+            }
             if constexpr (ODD) {
                 const bool from_wall = (ey == 1 && bot) || (ey == -1 && top);
+                // one cell per thread: the x-shifted source element is loaded directly
+                const unsigned soff = DIRECT ? xoff(L.wrapx(L.x0 - kEx[a])) : lane_off;
                 if (from_wall) {
-                    if (MAYBE_SPEC && spec && is_tangential(a)) w[a] = ld(base(opp(mirror_y(a)), 0, -ez));
+                    if (MAYBE_SPEC && spec && is_tangential(a))
+                        w[a] = Ln::template load<true>(at(base(opp(mirror_y(a)), 0, -ez), soff));
                     else w[a] = ld(base(a, 0, 0));
                 } else {
-                    w[a] = ld(base(opp(a), -ey, -ez));
+                    w[a] = Ln::template load<true>(at(base(opp(a), -ey, -ez), soff));
                 }
             } else {
                 w[a] = ld(base(a, 0, 0));
@@ -340,7 +503,7 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
     } else {
         for_each_dir([&](auto A) { w[decltype(A)::value] = u32x2{0u, 0u}; });
     }
-    if constexpr (ODD) {
+    if constexpr (ODD && !DIRECT) {
         // the x-shifted groups hold cells x0 .. x0 + V - 1 of the source row; shift by -e_x
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
@@ -379,9 +542,14 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         }
     }
 
+    if constexpr (NODE) {
+        if (L.active && (bot || top)) node_collide<S, V>(p, top, z, L.x0, prev, cur);
+    }
+
     double sm[7] = {0, 0, 0, 0, 0, 0, 0};
     int iters = 0;
     bool bad = false, newton_fail = false;
+    double nrho[V], nux[V], nuz[V];   // wall nodes: the first layer's moments for the next wall-node collision
     // a3-a6 (the same steps as collide_group, written out here: the register
     // allocation of this kernel came out tighter this way)
     constexpr bool PAIRS = (sizeof(T) == 2) && (V >= 2);
@@ -407,6 +575,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         const R cs2 = (R)((p.cs2_row && L.active) ? p.cs2_row[y] : p.cs2_18);
         const Moments<R> m = collide<R, MRT>(f, (R)p.tau0, cs2, (R)p.fx, &mr);
         bad = bad || !(m.rho > R(0)) || !(m.rho < R(INFINITY));
+        if constexpr (NODE) {
+            nrho[k] = (double)m.rho;
+            nux[k] = (double)m.ux;
+            nuz[k] = (double)m.uz;
+        }
         if constexpr (STATS) {
             const double ux = (double)m.ux, uy = (double)m.uy, uz = (double)m.uz;
             sm[0] += ux; sm[1] += uy; sm[2] += uz;
@@ -435,6 +608,15 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
             });
         }
     }
+    if constexpr (NODE) {
+        if (L.active && (bot || top)) {
+            int it = 0;
+            bool fl = false;
+            node_record<V>(p, top, z, L.x0, nrho, nux, nuz, it, fl);
+            iters = max(iters, it);
+            newton_fail = newton_fail || fl;
+        }
+    }
     if (L.active && (bad || newton_fail)) {
         atomicOr(&p.flags->status, (bad ? 1 : 0) | (newton_fail ? 2 : 0));
         atomicMin(&p.flags->first_bad, (unsigned long long)p.flags->cnt[ODD ? 1 : 0]);
@@ -442,22 +624,34 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
 
     // a7: store.  Odd: push to neighbours with wall reflections; even: own opposite slots.
     if constexpr (ODD) {
-        __syncthreads();  // every thread is done reading the exchange buffer
-        for_each_dir([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            if constexpr (kEx[a] != 0) xbuf[xslot(a) * nthr + t] = w[a];
-        });
-        __syncthreads();
+        if constexpr (!DIRECT) {
+            __syncthreads();  // every thread is done reading the exchange buffer
+            for_each_dir([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                if constexpr (kEx[a] != 0) xbuf[xslot(a) * nthr + t] = w[a];
+            });
+            __syncthreads();
+        }
         if (L.active) {
             for_each_dir([&](auto A) {
                 constexpr int a = decltype(A)::value;
                 constexpr int ex = kEx[a], ey = kEy[a], ez = kEz[a];
                 const bool to_wall = (ey == -1 && bot) || (ey == 1 && top);
+                if constexpr (NODE) {
+                    if (to_wall) {   // towards the wall node at x + e_a
+                        const int zz = ez > 0 ? zp : (ez < 0 ? zm : z);
+                        ring_store<S, V>(ring_row<S>(p, cur, top ? 1 : 0, node_k<opp(a)>(top), zz), L.x0, ex, p.nx, w[a]);
+                        return;
+                    }
+                }
                 const bool mirrored = to_wall && MAYBE_SPEC && spec && is_tangential(a);
                 if (to_wall && !mirrored) {
                     st(base(opp(a), 0, 0), w[a]);  // bounce-back into the cell's own slot
                 } else if constexpr (ex == 0) {
                     st(mirrored ? base(mirror_y(a), 0, ez) : base(a, ey, ez), w[a]);
+                } else if constexpr (DIRECT) {   // cell x goes to x + e_x
+                    char* dst = mirrored ? base(mirror_y(a), 0, ez) : base(a, ey, ez);
+                    Ln::template store<true>(at(dst, xoff(L.wrapx(L.x0 + ex))), w[a]);
                 } else {
                     char* dst = mirrored ? base(mirror_y(a), 0, ez) : base(a, ey, ez);
                     const u32x2* xb = xbuf + xslot(a) * nthr;
@@ -489,12 +683,21 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         if (L.active) {
             for_each_dir([&](auto A) {
                 constexpr int a = decltype(A)::value;
+                if constexpr (NODE) {
+                    constexpr int ey = kEy[a], ez = kEz[a];
+                    if ((ey == -1 && bot) || (ey == 1 && top)) {   // towards the wall node at x + e_a
+                        const int zz = ez > 0 ? zp : (ez < 0 ? zm : z);
+                        ring_store<S, V>(ring_row<S>(p, cur, top ? 1 : 0, node_k<opp(a)>(top), zz), L.x0, kEx[a],
+                                         p.nx, w[a]);
+                        return;
+                    }
+                }
                 st(base(opp(a), 0, 0), w[a]);
             });
         }
     }
 
-    if constexpr (MAYBE_WFB) {
+    if constexpr (MAYBE_WFB || NODE) {
         const int mx = wave_max(L.active ? iters : 0);
         if (lane == 0 && mx > 0) atomicMax(&p.flags->max_newton_iters, mx);
     }
@@ -850,9 +1053,12 @@ template <typename S, int V, bool ODD, bool MRT>
 static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
 {
     if constexpr (ODD)
-        if (a.nseg > 0) return launch_odd_rows<S, V, MRT>(bc, a, s);
+        if (a.nseg > 0) {
+            if (a.wall_nodes) return hipErrorInvalidValue;   // wall nodes run the block kernel
+            return launch_odd_rows<S, V, MRT>(bc, a, s);
+        }
     const dim3 grid((unsigned)a.ntiles), block((unsigned)a.tile_x);
-    const size_t lds = ODD ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
+    const size_t lds = (ODD && V > 1) ? (size_t)kNX * a.tile_x * sizeof(u32x2) : 0;
 #define LBM_STEP_W(BCT, W)                                                                                          \
     do {                                                                                                            \
         if (a.partials)                                                                                             \
@@ -866,7 +1072,8 @@ static hipError_t launch_step_bc(int bc, const StepArgs& a, hipStream_t s)
         if (whole_row_blocks(a)) LBM_STEP_W(BCT, true);       \
         else LBM_STEP_W(BCT, false);                          \
     } while (0)
-    if (bc == kBB) LBM_STEP(kBB);
+    if (a.wall_nodes) LBM_STEP(kBCNode);
+    else if (bc == kBB) LBM_STEP(kBB);
     else if (bc == kWFB) LBM_STEP(kWFB);
     else LBM_STEP(kFreeSlip);
 #undef LBM_STEP
@@ -879,7 +1086,7 @@ static hipError_t launch_batch_v(bool odd, const StepArgs& a0, const StepArgs* t
                                  hipStream_t s)
 {
     const dim3 grid((unsigned)ntiles), block((unsigned)a0.tile_x);
-    const size_t lds = odd ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
+    const size_t lds = (odd && V > 1) ? (size_t)kNX * a0.tile_x * sizeof(u32x2) : 0;
     if (odd && a0.nseg > 0)
         hipLaunchKernelGGL((k_odd_rows<S, V, kBCRuntime, false, MRT>), grid, block, 0, s, a0, table, tile_inst, ntiles);
     else if (odd)

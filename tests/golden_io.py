@@ -58,9 +58,17 @@ def eq14():
         parts = line.split()
         if parts[0] == "R":
             reversed_.append((int(parts[1]), int(parts[2])))
+        elif parts[0] == "C":
+            continue
         else:
             shifted.append((int(parts[0]), int(parts[1]), 1 if parts[2] == "+" else -1, parts[3]))
     return shifted, reversed_
+
+
+def eq14_copies():
+    """Eq. 14c's out-pointing diagonals: [(a, b)] meaning f_a* = ~f_b*."""
+    return [(int(p[1]), int(p[2])) for p in (line.split() for line in _rows("eq14_wfb_collision.txt"))
+            if p[0] == "C"]
 
 
 def table1():

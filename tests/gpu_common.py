@@ -71,12 +71,12 @@ def random_state(orc, shape, store, rng, u_scale=0.05, noise=2e-3):
 
 
 def oracle_for(orc, grid, tau, cs, fx, bc, y1=1.0, stats_every=0, collision="bgk", mrt_rates=None, van_driest=0.0,
-               van_driest_utau=0.0):
+               van_driest_utau=0.0, wall_nodes=False):
     nx, ny, nz = grid
     bcs = {"bb": orc.BB, "wfb": orc.WFB, "freeslip": orc.FREESLIP}
     p = orc.make_params(nx, ny, nz, tau, cs=cs, fx=fx, bc=bcs[bc], y1=y1, stats_every=stats_every,
                         collision={"bgk": orc.BGK, "mrt": orc.MRT}[collision], rates=mrt_rates,
-                        vd_aplus=van_driest, vd_utau=van_driest_utau)
+                        vd_aplus=van_driest, vd_utau=van_driest_utau, wall_nodes=int(wall_nodes))
     return orc.Oracle(p)
 
 

@@ -180,3 +180,33 @@ def test_workload_parameters_match_oracle_mapping(orc):
         q = orc.rule_m(w["grid"][1], w["re_tau"], w["ma"])
         for k in ("u_tau", "nu0", "tau0", "fx", "yplus1"):
             assert abs(p[k] - q[k]) <= 1e-13 * abs(q[k]), (name, k)
+
+
+def test_wall_node_parameter(L):
+    """The wall placement key: 0 or 1, read back; state calls without storage
+    are state errors; batches do not take it."""
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(L.Grid(8, 6, 4)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(h)) == 0
+    try:
+        v = C.c_double()
+        assert lib.lbm_get_param(h, L.LBM_P_WALL_NODES, C.byref(v)) == 0 and v.value == 0.0
+        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 0.5) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 2) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 1) == 0
+        assert lib.lbm_get_param(h, L.LBM_P_WALL_NODES, C.byref(v)) == 0 and v.value == 1.0
+        fw = np.zeros(10 * 8 * 4)
+        assert lib.lbm_get_wall_nodes(h, L.dptr(fw), None) == L.LBM_E_STATE
+        assert lib.lbm_moments_device(h, None, None, None, None) == L.LBM_E_STATE
+    finally:
+        lib.lbm_destroy(h)
+    b = C.c_void_p()
+    grids = (L.Grid * 1)(L.Grid(8, 6, 4))
+    one = np.array([0.6]), np.array([0.1]), np.array([1e-6])
+    bc = np.array([1], dtype=np.int32)
+    assert lib.lbm_batch_create(1, grids, L.dptr(one[0]), L.dptr(one[1]), L.dptr(one[2]),
+                                bc.ctypes.data_as(C.POINTER(C.c_int32)), 0.41, 5.5, C.byref(b)) == 0
+    try:
+        assert lib.lbm_batch_set_param(b, L.LBM_P_WALL_NODES, 1) == L.LBM_E_ARG
+    finally:
+        lib.lbm_batch_destroy(b)

@@ -14,7 +14,8 @@ SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 # fast pins first: the run stops at the first failure
 PIN_TESTS = ["tests/test_oracle_lattice.py", "tests/test_oracle_mrt.py", "tests/test_oracle_spalding.py",
              "tests/test_oracle_wfb.py", "tests/test_oracle_paper_numbers.py", "tests/test_oracle_initial_state.py",
-             "tests/test_oracle_cells.py", "tests/test_oracle_flows.py", "tests/test_oracle_mrt_flows.py"]
+             "tests/test_oracle_cells.py", "tests/test_oracle_wall_nodes.py", "tests/test_oracle_flows.py",
+             "tests/test_oracle_mrt_flows.py"]
 
 # name: (text in lbm_oracle.c, planted replacement)
 MISTAKES = {
@@ -52,6 +53,13 @@ MISTAKES = {
     "statistics sample count": ("o->stats[8 * y + 7] += (double)p->nx * p->nz;", "o->stats[8 * y + 7] += (double)p->nx;"),
     "spanwise streaming from the wrong side": ("int sz = wrap(z - E[a][2], p->nz);", "int sz = wrap(z + E[a][2], p->nz);"),
     "analytic initial state: wrong direction": ("    return feq(a, 1.0, u);\n}", "    return feq(OPP[a], 1.0, u);\n}"),
+    "wall node gather without the in-plane shift": ("f[a] = s->fw[(((int64_t)w * 5 + in_index(w, a)) * p->nz + sz) * p->nx + sx];", "f[a] = s->fw[(((int64_t)w * 5 + in_index(w, a)) * p->nz + z) * p->nx + x];"),
+    "wall node arrivals without the in-plane shift": ("int sx = wrap(x - E[b][0], p->nx), sz = wrap(z - E[b][2], p->nz);\n                        f[b] = o->fpost", "int sx = x, sz = z;\n                        f[b] = o->fpost"),
+    "wall node 14a sign": ("o[7] = g[13] + 0.5 * tx;", "o[7] = g[13] - 0.5 * tx;"),
+    "wall node 14c copy of the uncorrected value": ("o[8] = o[7];", "o[8] = g[13];"),
+    "bounce-back node mirrored": ("for (int a = 0; a < Q; ++a) o[a] = g[OPP[a]];", "for (int a = 0; a < Q; ++a) o[a] = g[MIR[a]];"),
+    "wall node velocity u_y for u_z": ("u[0] = mom[0]; u[1] = mom[1]; u[2] = mom[3];", "u[0] = mom[0]; u[1] = mom[1]; u[2] = mom[2];"),
+    "wall node start without the plain moments": ("u[0] = r; u[1] = jx / r; u[2] = jz / r;", "u[0] = r; u[1] = jx; u[2] = jz / r;"),
     "opposite of a direction": ("E[b][1] == -E[a][1] && E[b][2] == -E[a][2]) OPP[a] = b;",
                                 "E[b][1] == -E[a][1] && E[b][2] == E[a][2]) OPP[a] = b;"),
 }
