@@ -69,7 +69,11 @@ class Channel:
     def __init__(self, nx, ny, nz, tau, cs=0.1, kappa=0.41, B=5.5, fx=0.0, store="f64", bc="wfb", y1=1.0,
                  device="cuda", stream=None, tiles=None, graph_steps=None, stats_every=0, autotune=False,
                  vector=0, brick=0, collision="bgk", mrt_rates=None, van_driest=0.0, van_driest_utau=0.0,
-                 wall_nodes=False):
+                 wall_nodes=False, storage=None):
+        """storage: an optional contiguous uint8 torch tensor on the device to bind
+        instead of a fresh allocation (at least the required bytes; its data
+        pointer 256-byte aligned), e.g. one buffer shared by channels run one
+        after the other."""
         import torch
         self.lib = L.lib()
         self.shape = (nz, ny, nx)
@@ -101,7 +105,13 @@ class Channel:
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value
         self.device = torch.device(device)
-        self.storage = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        if storage is None:
+            self.storage = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        else:
+            if storage.dtype != torch.uint8 or not storage.is_contiguous() or storage.numel() < self.nbytes:
+                raise ValueError("storage must be a contiguous uint8 tensor of at least %d bytes" % self.nbytes)
+            self.storage = storage
+            self.device = storage.device
         L.check(self.lib.lbm_bind_storage(self._h, C.c_void_p(self.storage.data_ptr()), self.nbytes), self._h)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         L.check(self.lib.lbm_set_stream(self._h, C.c_void_p(self.stream.cuda_stream)), self._h)

@@ -535,10 +535,32 @@ __global__ __launch_bounds__(256) void k_relayout(void* hv, long long n, int nx,
 
 // ----------------------------------------------------------- misc kernels
 
-__global__ __launch_bounds__(256) void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, long long n)
+// The bandwidth reference: a plain copy, 16 bytes per lane per access,
+// non-temporal both ways.  A block copies contiguous chunks of 16 KB (four
+// 4 KB rows of the block, all four loads in flight before the stores),
+// striding over the chunks.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, long long n)
 {
-    const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const long long per = 4ll * blockDim.x;
+    for (long long base = (long long)blockIdx.x * per; base < n; base += (long long)gridDim.x * per) {
+        const long long i = base + threadIdx.x;
+        if (base + per <= n) {
+            const u32x4 a = __builtin_nontemporal_load(src + i);
+            const u32x4 b = __builtin_nontemporal_load(src + i + blockDim.x);
+            const u32x4 c = __builtin_nontemporal_load(src + i + 2 * blockDim.x);
+            const u32x4 d = __builtin_nontemporal_load(src + i + 3 * blockDim.x);
+            __builtin_nontemporal_store(a, dst + i);
+            __builtin_nontemporal_store(b, dst + i + blockDim.x);
+            __builtin_nontemporal_store(c, dst + i + 2 * blockDim.x);
+            __builtin_nontemporal_store(d, dst + i + 3 * blockDim.x);
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                const long long j = i + (long long)k * blockDim.x;
+                if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + j), dst + j);
+            }
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_wall_utau(const double* __restrict__ U, int n, double y1, double nu,
@@ -819,9 +841,10 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
     if (bytes % 16 != 0) return hipErrorInvalidValue;
     const long long n = (long long)(bytes / 16);
     if (n == 0) return hipSuccess;
-    long long blocks = (n + 255) / 256;
-    if (blocks > 256 * 1024) blocks = 256 * 1024;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n);
+    // one 16 KB chunk per block up to 32 blocks per CU of the 256
+    long long blocks = (n + 1023) / 1024;
+    if (blocks > 256 * 32) blocks = 256 * 32;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
     return hipGetLastError();
 }
 

@@ -74,7 +74,7 @@ def mass_check(ch, steps):
 
 def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, develop=400000, sample=400000,
         stats_every=20, report_every=50000, pdf_bins=40, pdf_range=4.0, mass_steps=0, mrt_rates=None,
-        out=sys.stderr):
+        wall_nodes=False, out=sys.stderr):
     """Develop the channel from its Spalding initial state, then sample the
     plane statistics every stats_every steps; progress lines every
     report_every steps, at which the sampling phase also takes a snapshot of
@@ -82,8 +82,11 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     deviations).  mrt_rates: dict of MRT rates overriding the defaults
     (keys s_e, s_eps, s_q, s_pi, s_m).  With mass_steps > 0, the Appendix B
     mass check runs over
-    that many steps between the two phases.  Returns the metrics with the
-    run's parameters."""
+    that many steps between the two phases.  wall_nodes: the wall grid as a
+    lattice node (LBM_P_WALL_NODES); the channel then has ny - 1 fluid layers
+    between wall nodes ny spacings apart, so that D = ny / 2 and the
+    parameters are those of the halfway channel of ny layers.  Returns the
+    metrics with the run's parameters and the sampled mean profile."""
     import torch
 
     from . import Channel
@@ -91,10 +94,13 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     p = W.params(workload)
     nx, ny, nz = p["grid"]
     tiles = W.launch_tiles(workload, store, collision) if workload in W.LAUNCH_TILES else None
+    if wall_nodes:
+        ny -= 1
+        tiles = None
     ch = Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
-                 tiles=tiles, collision=collision, van_driest=van_driest, mrt_rates=mrt_rates)
+                 tiles=tiles, collision=collision, van_driest=van_driest, mrt_rates=mrt_rates, wall_nodes=wall_nodes)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
-    T = (ny / 2.0) / p["u_tau"]            # D / u_tau in steps
+    T = (p["grid"][1] / 2.0) / p["u_tau"]  # D / u_tau in steps
     t0 = time.time()
     done = 0
     pdf_counts, pdf_mean, pdf_std, pdf_snaps = None, 0.0, 0.0, 0
@@ -128,9 +134,11 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     if sample > 0:
         stats, nsamp = ch.stats()
         m = profile_metrics(stats[:, 0], p["u_tau"], p["nu0"])
+        m.update(mean_ux=stats[:, 0].tolist(), mean_uxuy=stats[:, 6].tolist(), mean_ux2=stats[:, 3].tolist())
     m.update(workload=workload, grid=[nx, ny, nz], store=store, bc=bc, collision=collision,
-             van_driest_aplus=van_driest, re_tau=W.case(workload)["re_tau"], u_tau=p["u_tau"],
-             develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
+             van_driest_aplus=van_driest, re_tau=W.case(workload)["re_tau"], u_tau=p["u_tau"], tau0=p["tau0"],
+             fx=p["fx"], wall_nodes=bool(wall_nodes), develop_steps=develop, sample_steps=sample,
+             stats_every=stats_every, develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
              seconds=time.time() - t0)
     if mass is not None:
         m.update(mass_check=mass)
@@ -156,12 +164,18 @@ def main():
     ap.add_argument("--report-every", type=int, default=50000)
     ap.add_argument("--mass-steps", type=int, default=0)
     ap.add_argument("--mrt-rates", default="", help="e.g. s_e=1.19,s_q=1.2 (MRT rates to override)")
+    ap.add_argument("--wall-nodes", action="store_true", help="the wall grid as a lattice node (LBM_P_WALL_NODES)")
+    ap.add_argument("--out", default="", help="also write the record to this JSON file")
     a = ap.parse_args()
     rates = {k: float(v) for k, v in (kv.split("=") for kv in a.mrt_rates.split(",") if kv)} or None
     m = run(a.workload, a.store, a.bc, a.collision, a.van_driest, a.develop, a.sample, a.stats_every,
-            a.report_every, mass_steps=a.mass_steps, mrt_rates=rates)
+            a.report_every, mass_steps=a.mass_steps, mrt_rates=rates, wall_nodes=a.wall_nodes)
     if rates:
         m.update(mrt_rates=rates)
+    m.update(command=" ".join(["python -m paper_2009_04352_amd.validation"] + sys.argv[1:]))
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(m, fh, indent=1)
     print(json.dumps(m))
 
 

@@ -105,15 +105,17 @@ def params(name, named_tau=False):
 
 # Launch shapes used by the benchmark and by the full-size parity tests, per
 # workload and store format: (threads per block of the odd kernel, of the even
-# kernel, cells per thread), measured on MI355X.  On the 128-cell rows of the
-# 128 x 64 x 64 channel and the 512-cell rows of the 512 x 128 x 256 channel a
-# block covers one whole row; on the 2048-cell rows of the large channel FP64
-# rows are split in 256-thread segments, and FP16/BF16 odd steps walk rows one
-# wavefront each.
+# kernel, cells per thread), measured on MI355X.  FP64 and FP32 run one cell
+# per thread: in row segments their odd step shifts by plain address offsets
+# (FP32 on the 512 x 128 x 256 channel: 128-thread odd segments, whole-row
+# even blocks; on the 2,048-cell rows of the large channel 512- and 256-cell
+# segments), on whole rows through LDS (FP64 on 512-cell rows).  FP16/BF16 run
+# four cells per thread (8-byte groups); their odd step walks rows one
+# wavefront each on the large channel.
 LAUNCH_TILES = {
     "c2": {"f64": (128, 128, 1), "f32": (64, 64, 2), "f16": (64, 64, 2), "bf16": (64, 64, 2)},
-    "c3": {"f64": (512, 512, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
-    "c5": {"f64": (256, 256, 1), "f32": (256, 256, 2), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
+    "c3": {"f64": (512, 512, 1), "f32": (128, 256, 1), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
+    "c5": {"f64": (512, 256, 1), "f32": (256, 256, 1), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
 }
 # With the MRT collision the 2-byte odd step needs more registers than three
 # wavefronts per SIMD allow at 4 cells per thread; at 2 cells per thread it
