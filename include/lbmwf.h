@@ -233,6 +233,23 @@ int lbm_wall_shear(lbm_ctx* ctx, double* tau_x, double* tau_z, double* u_tau, do
  * lo < hi, else LBM_E_ARG.  Synchronises. */
 int lbm_wall_yplus_pdf(lbm_ctx* ctx, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * distribution as lbm_wall_yplus_pdf, from the same kernels, with no
+ * allocation.  counts[nbins + 2] and mean_std[2] are caller-owned DEVICE
+ * memory on the context's device; the call only enqueues kernels on the
+ * context's stream and returns (read the results after synchronising it).
+ * The per-wall-cell friction velocities go to a fixed work area of 2^22
+ * doubles (32 MiB) that the library holds on each device until the process
+ * ends: grids with 2 nx nz > 2^22 wall cells get LBM_E_ARG.  Every call on a
+ * device shares that work area, so calls that overlap on one device (other
+ * streams, other contexts, other threads) race; calls in order on one stream
+ * do not.  The step's failure flags are not checked (lbm_sync does that).
+ * After a switch between bounce-back and mirror reflection the state may need
+ * a re-layout that takes a buffer: then LBM_E_STATE until lbm_step or
+ * lbm_wall_yplus_pdf has run. */
+int lbm_wall_yplus_pdf_noalloc(lbm_ctx* ctx, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std);
+
 /* Mass check of the wall correction (Appendix B, Eq. B-1): for every wall cell
  * the sum of the 19 populations after the WFB correction (Eq. 14) the next
  * step would make, minus the sum before it, as the step kernel computes them

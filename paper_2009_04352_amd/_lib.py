@@ -53,6 +53,7 @@ SIGNATURES = {
     "lbm_moments_device": (C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_wall_shear": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbm_wall_yplus_pdf": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, C.c_void_p, _dp]),
+    "lbm_wall_yplus_pdf_noalloc": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "lbm_init_moments": (C.c_int, [_vp, _dp, _dp]),
     "lbm_wall_mass_change": (C.c_int, [_vp, _dp, _dp]),
     "lbm_get_wall_nodes": (C.c_int, [_vp, _dp, _dp]),

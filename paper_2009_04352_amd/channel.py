@@ -246,6 +246,17 @@ class Channel:
                                               L.dptr(ms)))
         return counts, np.linspace(lo, hi, nbins + 1), ms[0], ms[1]
 
+    def wall_yplus_pdf_noalloc(self, counts, mean_std, nbins=40, lo=-4.0, hi=4.0):
+        """wall_yplus_pdf into caller-owned device tensors (int64 counts of
+        nbins + 2 elements, float64 mean_std of 2), enqueued on the channel's
+        stream with no allocation by the library."""
+        import torch
+        if (counts.dtype != torch.int64 or counts.numel() < nbins + 2 or not counts.is_contiguous()
+                or mean_std.dtype != torch.float64 or mean_std.numel() < 2 or not mean_std.is_contiguous()):
+            raise ValueError("counts: contiguous int64 of nbins + 2; mean_std: contiguous float64 of 2")
+        self._chk(self.lib.lbm_wall_yplus_pdf_noalloc(self._h, nbins, lo, hi, C.c_void_p(counts.data_ptr()),
+                                                      C.c_void_p(mean_std.data_ptr())))
+
     def wall_mass_change(self):
         """Eq. B-1 per wall cell: (change of the population sum made by the WFB
         correction the next step would apply, density before it), each of

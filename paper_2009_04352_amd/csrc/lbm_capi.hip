@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -31,6 +32,53 @@ struct GraphKey {
         return std::tie(layout_s, len, stats_every, phase) < std::tie(o.layout_s, o.len, o.stats_every, o.phase);
     }
 };
+
+}  // namespace
+
+// Work area of lbm_wall_yplus_pdf_noalloc: the friction velocity of each wall
+// cell (2 nx nz of them, at most kScratchWallCells = 2^22, 32 MiB).  Every
+// device the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address scratch_address() looked up on that
+// device, never through this name.
+constexpr long long kScratchWallCells = 1ll << 22;
+static __device__ __align__(256) double scratch[kScratchWallCells];
+
+namespace {
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+bool g_scratch_done[kMaxDevices];
+
+// Device address of the work area on device dev, which must be current; the
+// first call per device looks it up (hipGetSymbolAddress) and keeps the result.
+hipError_t scratch_address(int dev, double** out)
+{
+    *out = nullptr;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? (double*)p : nullptr;
+        g_scratch_done[dev] = true;
+    }
+    *out = g_scratch_ptr[dev];
+    return g_scratch_err[dev];
+}
+
+// Device of a device-memory pointer, or -1 (host or unknown memory).  A failed
+// query leaves no error behind for the next launch check to pick up.
+int device_of(const void* p)
+{
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    return attr.type == hipMemoryTypeDevice ? attr.device : -1;
+}
 
 }  // namespace
 
@@ -385,11 +433,17 @@ int check_ready(lbm_ctx* c)
 // Moves the wall-crossing populations of a streamed layout when the boundary
 // switched between bounce-back and mirror reflection (halfway walls only:
 // with wall nodes the reflection happens in the wall-node collision).
+// Whether the state must be re-laid out before it is read: a streamed layout
+// whose wall reflections were made by the other rule than the current boundary's.
+bool layout_stale(const lbm_ctx* c)
+{
+    return c->initialized && c->layout_s && !c->wall_nodes && (int)(c->bc != kBB) != c->layout_spec;
+}
+
 int fix_layout(lbm_ctx* c)
 {
-    if (!c->initialized || !c->layout_s || c->wall_nodes) return LBM_OK;
+    if (!layout_stale(c)) return LBM_OK;
     const int want = (c->bc != kBB);
-    if (want == c->layout_spec) return LBM_OK;
     if (!c->dtmp) LBM_HIP(c, hipMalloc((void**)&c->dtmp, (size_t)2 * c->nx * c->nz * 5 * sizeof(double)));
     LBM_HIP(c, launch_relayout(c->store, c->h, c->n, c->nx, c->ny, c->nz, c->brick, c->layout_spec, want, c->dtmp,
                                c->stream));
@@ -693,13 +747,17 @@ int lbm_bind_storage(lbm_ctx* c, void* ptr, size_t bytes)
         lbm_required_bytes(c, &need);
         if (bytes < need) return fail(c, LBM_E_ARG, "storage too small: need " + std::to_string(need) + " bytes");
         if (((uintptr_t)ptr) % 256 != 0) return fail(c, LBM_E_ARG, "storage must be 256-byte aligned");
-        hipPointerAttribute_t attr;
-        hipError_t e = hipPointerGetAttributes(&attr, ptr);
-        if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
-            return fail(c, LBM_E_ARG, "storage is not device memory");
-        if (c->h && attr.device != c->dev) return fail(c, LBM_E_STATE, "storage must stay on the same device");
-        c->dev = attr.device;
+        const int dev = device_of(ptr);
+        if (dev < 0) return fail(c, LBM_E_ARG, "storage is not device memory");
+        if (c->h && dev != c->dev) return fail(c, LBM_E_STATE, "storage must stay on the same device");
+        c->dev = dev;
         DeviceGuard dg(c->dev);
+        {
+            // set-up of the device's work area for lbm_wall_yplus_pdf_noalloc (a failed
+            // look-up is kept and reported by that call)
+            double* ws = nullptr;
+            (void)scratch_address(c->dev, &ws);
+        }
         if (!c->dflags) {
             LBM_HIP(c, hipMalloc((void**)&c->dflags, sizeof(DevFlags)));
             LBM_HIP(c, hipMalloc((void**)&c->dacc, (size_t)c->ny * 8 * sizeof(double)));
@@ -1121,9 +1179,7 @@ int lbm_moments_device(lbm_ctx* c, double* rho, double* ux, double* uy, double* 
         for (double* p : outs) {
             if (!p) continue;
             any = true;
-            hipPointerAttribute_t attr;
-            if (hipPointerGetAttributes(&attr, p) != hipSuccess || attr.type != hipMemoryTypeDevice ||
-                attr.device != c->dev)
+            if (device_of(p) != c->dev)
                 return fail(c, LBM_E_ARG, "moment arrays must be device memory on the context's device");
         }
         if (!any) return fail(c, LBM_E_ARG, "no output array given");
@@ -1188,6 +1244,28 @@ int lbm_wall_mass_change(lbm_ctx* c, double* dsum, double* rho)
     });
 }
 
+// The y+ distribution's kernels on the context's stream: the wall records'
+// friction velocities into ut[2 nx nz], then the moments into ms[2] and the
+// histogram into counts[nbins + 2] (cleared by the kernels).
+static hipError_t enqueue_yplus_pdf(lbm_ctx* c, int nbins, double lo, double hi, double* ut, double* ms,
+                                    unsigned long long* counts)
+{
+    const long long m = 2ll * c->nx * c->nz;
+    ObsArgs a = obs_args(c);
+    a.mode = 1;
+    a.cells = nullptr;
+    a.first = 0;
+    a.count = m;
+    a.out = nullptr;
+    a.soa[2] = ut;
+    a.iters = nullptr;
+    a.dmass = nullptr;
+    hipError_t e = launch_observe(c->store, a, c->stream);
+    if (e != hipSuccess) return e;
+    const double nu0 = (c->tau0 - 0.5) / 3.0;
+    return launch_yplus_pdf(ut, m, c->y1, nu0, ms, lo, (double)nbins / (hi - lo), nbins, counts, c->stream);
+}
+
 int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std)
 {
     return guard(c, [&]() -> int {
@@ -1200,39 +1278,55 @@ int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t*
         if ((st = fix_layout(c)) != LBM_OK) return st;
         if ((st = sync_check(c)) != LBM_OK) return st;
         const long long m = 2ll * c->nx * c->nz;
-        double* rec = nullptr;
+        double* ut = nullptr;
         double* ms = nullptr;
         unsigned long long* dcnt = nullptr;
-        hipError_t e = hipMalloc((void**)&rec, (size_t)m * 4 * sizeof(double));
+        hipError_t e = hipMalloc((void**)&ut, (size_t)m * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void**)&ms, 2 * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void**)&dcnt, (size_t)(nbins + 2) * sizeof(unsigned long long));
         std::vector<unsigned long long> hc((size_t)nbins + 2);
         double hms[2] = {0.0, 0.0};
-        if (e == hipSuccess) e = hipMemsetAsync(dcnt, 0, (size_t)(nbins + 2) * sizeof(unsigned long long), c->stream);
-        if (e == hipSuccess) {
-            ObsArgs a = obs_args(c);
-            a.mode = 1;
-            a.cells = nullptr;
-            a.first = 0;
-            a.count = m;
-            a.out = rec;
-            a.iters = nullptr;
-            e = launch_observe(c->store, a, c->stream);
-        }
-        const double nu0 = (c->tau0 - 0.5) / 3.0;
-        if (e == hipSuccess)
-            e = launch_yplus_pdf(rec, m, c->y1, nu0, ms, lo, (double)nbins / (hi - lo), nbins, dcnt, c->stream);
+        if (e == hipSuccess) e = enqueue_yplus_pdf(c, nbins, lo, hi, ut, ms, dcnt);
         if (e == hipSuccess) e = hipMemcpyAsync(hms, ms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(hc.data(), dcnt, hc.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        if (rec) (void)hipFree(rec);
+        if (ut) (void)hipFree(ut);
         if (ms) (void)hipFree(ms);
         if (dcnt) (void)hipFree(dcnt);
         if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("wall y+ distribution: ") + hipGetErrorString(e));
         for (size_t i = 0; i < hc.size(); ++i) counts[i] = (int64_t)hc[i];
         mean_std[0] = hms[0];
         mean_std[1] = hms[1];
+        return LBM_OK;
+    });
+}
+
+int lbm_wall_yplus_pdf_noalloc(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t* counts, double* mean_std)
+{
+    return guard(c, [&]() -> int {
+        if (!c || !counts || !mean_std) return fail(c, LBM_E_ARG, "null argument");
+        if (nbins < 1 || nbins > (1 << 20) || !(hi > lo) || !std::isfinite(lo) || !std::isfinite(hi))
+            return fail(c, LBM_E_ARG, "need 1 <= nbins <= 2^20 and finite lo < hi");
+        const long long m = 2ll * c->nx * c->nz;
+        if (m > kScratchWallCells)
+            return fail(c, LBM_E_ARG, "2 nx nz = " + std::to_string(m) + " wall cells exceed the fixed work area of " +
+                                          std::to_string(kScratchWallCells) + "; use lbm_wall_yplus_pdf");
+        int st = check_ready(c);
+        if (st != LBM_OK) return st;
+        if (layout_stale(c))
+            return fail(c, LBM_E_STATE, "the boundary changed since the last step and the state must be re-laid "
+                                        "out first (lbm_step or lbm_wall_yplus_pdf does it)");
+        const void* outs[2] = {counts, mean_std};
+        for (const void* p : outs) {
+            if (device_of(p) != c->dev)
+                return fail(c, LBM_E_ARG, "counts and mean_std must be device memory on the context's device");
+        }
+        DeviceGuard dg(c->dev);
+        double* ws = nullptr;
+        const hipError_t e = scratch_address(c->dev, &ws);
+        if (e != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("work area look-up: ") + hipGetErrorString(e));
+        LBM_HIP(c, enqueue_yplus_pdf(c, nbins, lo, hi, ws, mean_std, (unsigned long long*)counts));
         return LBM_OK;
     });
 }

@@ -137,10 +137,9 @@ struct ObsArgs {
     double fx, y1, nu0, kappa, bconst, ekb, newton_tol;
     const long long* cells;  // optional cell list (nullptr: cells first .. first + count)
     long long first, count;
-    double* out;          // [count][4]: rho, ux, uy, uz      (mode 0)
-    double* soa[4];       // mode 0 without out: rho, ux, uy, uz of cell first + i at index i of each
-                          // non-null array (device memory)
-                          // [count][4]: tau_x, tau_z, u_tau, U (mode 1, wall cells)
+    double* out;          // [count][4]: rho, ux, uy, uz (mode 0); tau_x, tau_z, u_tau, U (mode 1, wall cells)
+    double* soa[4];       // without out: the same four values of item i at index i of each non-null
+                          // array (device memory)
     int* iters;           // optional, mode 1: Newton iterations per wall cell
     double* dmass;        // optional, mode 1: [count][2] = change of the population sum made
                           // by the wall correction, rho before it (Eq. B-1)
@@ -172,7 +171,9 @@ hipError_t launch_get_state(int store, const void* h, long long n, int nx, int n
                             int layout_spec, const long long* cells, long long first, long long count, double* out,
                             const void* wn, hipStream_t s);
 hipError_t launch_observe(int store, const ObsArgs& a, hipStream_t s);
-hipError_t launch_yplus_pdf(const double* rec, long long m, double y1, double nu0, double* ms, double lo, double scale,
+// y+ distribution of m >= 1 wall cells from their friction velocities ut[m];
+// clears counts[nbins + 2] itself, writes ms[2] = mean, standard deviation
+hipError_t launch_yplus_pdf(const double* ut, long long m, double y1, double nu0, double* ms, double lo, double scale,
                             int nbins, unsigned long long* counts, hipStream_t s);
 hipError_t launch_relayout(int store, void* h, long long n, int nx, int ny, int nz, int brick, int from_spec,
                            int to_spec, double* tmp, hipStream_t s);

@@ -490,8 +490,15 @@ __global__ __launch_bounds__(256) void k_observe(ObsArgs p)
         rec.U = sqrt((double)ux * (double)ux + (double)uz * (double)uz);
     }
     if (p.wall_nodes) iters = 0;
-    double* o = p.out + 4 * i;
-    o[0] = rec.taux; o[1] = rec.tauz; o[2] = rec.utau; o[3] = rec.U;
+    if (p.out) {
+        double* o = p.out + 4 * i;
+        o[0] = rec.taux; o[1] = rec.tauz; o[2] = rec.utau; o[3] = rec.U;
+    } else {
+        if (p.soa[0]) p.soa[0][i] = rec.taux;
+        if (p.soa[1]) p.soa[1][i] = rec.tauz;
+        if (p.soa[2]) p.soa[2][i] = rec.utau;
+        if (p.soa[3]) p.soa[3][i] = rec.U;
+    }
     if (p.iters) p.iters[i] = iters;
 }
 
@@ -773,23 +780,26 @@ hipError_t launch_codec(int store, const float* in, float* out, long long n, hip
 }
 
 // First-layer y+ of the wall records (Fig. 7): y+ = y1 u_tau / nu0 per wall
-// cell.  k_yplus_moments: one block forms the mean and then the mean square
-// deviation in FP64 in a fixed order (thread t takes records t, t + 256, ...;
-// then a tree over the threads) and writes the mean and the population
-// standard deviation.  k_yplus_hist counts
-// z = (y+ - mean) / std into nbins bins of width (hi - lo) / nbins from lo,
-// with an underflow bin first and an overflow bin last.
-__global__ __launch_bounds__(256) void k_yplus_moments(const double* __restrict__ rec, long long m, double y1,
-                                                       double nu0, double* __restrict__ ms)
+// cell, from the friction velocities ut[m].  k_yplus_moments: one block clears
+// the nbins + 2 counters, then forms the mean and the mean square deviation
+// in FP64 in a fixed order (thread t takes cells t, t + 256, ...; then a tree
+// over the threads) and writes the mean and the population standard
+// deviation.  k_yplus_hist counts z = (y+ - mean) / std into nbins bins of
+// width (hi - lo) / nbins from lo, with an underflow bin first and an overflow
+// bin last.
+__global__ __launch_bounds__(256) void k_yplus_moments(const double* __restrict__ ut, long long m, double y1,
+                                                       double nu0, double* __restrict__ ms, int nbins,
+                                                       unsigned long long* __restrict__ counts)
 {
     __shared__ double sh[256];
     const int t = (int)threadIdx.x;
+    for (int b = t; b < nbins + 2; b += 256) counts[b] = 0ull;
     // two passes: the mean, then the mean square deviation from it
     double mean = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
         double a = 0.0;
         for (long long i = t; i < m; i += 256) {
-            const double yp = (y1 * rec[4 * i + 2]) / nu0;
+            const double yp = (y1 * ut[i]) / nu0;
             a += pass == 0 ? yp : (yp - mean) * (yp - mean);
         }
         sh[t] = a;
@@ -809,13 +819,13 @@ __global__ __launch_bounds__(256) void k_yplus_moments(const double* __restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void k_yplus_hist(const double* __restrict__ rec, long long m, double y1, double nu0,
+__global__ __launch_bounds__(256) void k_yplus_hist(const double* __restrict__ ut, long long m, double y1, double nu0,
                                                     const double* __restrict__ ms, double lo, double scale, int nbins,
                                                     unsigned long long* __restrict__ counts)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
-    const double yp = (y1 * rec[4 * i + 2]) / nu0;
+    const double yp = (y1 * ut[i]) / nu0;
     const double z = (yp - ms[0]) / ms[1];
     const double u = (z - lo) * scale;
     int bin;
@@ -825,13 +835,14 @@ __global__ __launch_bounds__(256) void k_yplus_hist(const double* __restrict__ r
     atomicAdd(&counts[bin], 1ull);
 }
 
-hipError_t launch_yplus_pdf(const double* rec, long long m, double y1, double nu0, double* ms, double lo, double scale,
+hipError_t launch_yplus_pdf(const double* ut, long long m, double y1, double nu0, double* ms, double lo, double scale,
                             int nbins, unsigned long long* counts, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_yplus_moments, dim3(1), dim3(256), 0, s, rec, m, y1, nu0, ms);
+    if (m <= 0 || nbins < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_yplus_moments, dim3(1), dim3(256), 0, s, ut, m, y1, nu0, ms, nbins, counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_yplus_hist, blocks_for(m, 256), dim3(256), 0, s, rec, m, y1, nu0, ms, lo, scale, nbins,
+    hipLaunchKernelGGL(k_yplus_hist, blocks_for(m, 256), dim3(256), 0, s, ut, m, y1, nu0, ms, lo, scale, nbins,
                        counts);
     return hipGetLastError();
 }

@@ -210,3 +210,27 @@ def test_wall_node_parameter(L):
         assert lib.lbm_batch_set_param(b, L.LBM_P_WALL_NODES, 1) == L.LBM_E_ARG
     finally:
         lib.lbm_batch_destroy(b)
+
+
+def test_yplus_pdf_noalloc_argument_checks(L):
+    """The allocation-free y+ distribution checks its arguments before any GPU
+    work: null outputs, the bin count, the fixed work area of 2^22 wall cells,
+    and a context without storage."""
+    lib = L.lib()
+    dummy = np.zeros(64)
+    p = L.dptr(dummy)
+    big = C.c_void_p()
+    assert lib.lbm_create(C.byref(L.Grid(2048, 2, 1025)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(big)) == 0
+    small = C.c_void_p()
+    assert lib.lbm_create(C.byref(L.Grid(2048, 2, 1024)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(small)) == 0
+    try:
+        assert lib.lbm_wall_yplus_pdf_noalloc(big, 8, -4.0, 4.0, None, p) == L.LBM_E_ARG
+        assert lib.lbm_wall_yplus_pdf_noalloc(big, 0, -4.0, 4.0, p, p) == L.LBM_E_ARG
+        assert lib.lbm_wall_yplus_pdf_noalloc(big, 8, 4.0, 4.0, p, p) == L.LBM_E_ARG
+        assert lib.lbm_wall_yplus_pdf_noalloc(big, 8, -4.0, 4.0, p, p) == L.LBM_E_ARG
+        assert b"work area" in lib.lbm_last_error(big)
+        # 2 * 2048 * 1024 = 2^22 wall cells fit; without storage the context is not ready
+        assert lib.lbm_wall_yplus_pdf_noalloc(small, 8, -4.0, 4.0, p, p) == L.LBM_E_STATE
+    finally:
+        lib.lbm_destroy(big)
+        lib.lbm_destroy(small)
