@@ -111,22 +111,37 @@ def step_profile(per, first_step):
     return out
 
 
-def run_store(P, W, name, store, bc, steps, warmup, coll, acc_steps, ref):
+def run_store(P, W, name, store, bc, steps, warmup, coll, acc_steps, ref, tune_steps):
     """Times one store on one workload, then continues (untimed) to the
     workload's own step count and compares the velocity field on the device
     with the FP64 run's (ref; None for the FP64 run itself, whose fields it
-    returns)."""
+    returns).  The launch shapes start from the measured table of workloads.py;
+    with tune_steps > 0 the library's autotuner (lbm_autotune) then searches
+    from there, timing each candidate over tune_steps steps, and the timed run
+    uses its choice."""
     import torch
     p = W.params(name)
     nx, ny, nz = p["grid"]
     n = nx * ny * nz
-    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc,
-                   tiles=W.launch_tiles(name, store, coll["collision"]), graph_steps=0, **coll)
+    table = W.launch_tiles(name, store, coll["collision"])
+    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc=bc, tiles=table, graph_steps=0,
+                   **coll)
+    t0 = time.perf_counter()
+    launch = ch.autotune(steps=tune_steps) if tune_steps > 0 else None
+    tune_s = time.perf_counter() - t0
+    if launch is None:
+        from paper_2009_04352_amd import _lib as L
+        launch = dict(tile_odd=int(ch.get_param(L.LBM_P_TILE_ODD)), tile_even=int(ch.get_param(L.LBM_P_TILE_EVEN)),
+                      vector=int(ch.get_param(L.LBM_P_VECTOR)), brick=int(ch.get_param(L.LBM_P_BRICK)),
+                      spread=int(ch.get_param(L.LBM_P_SPREAD)), odd_rows=int(ch.get_param(L.LBM_P_ODD_BY_ROWS)),
+                      cached=0)
+    launch.update(source="autotuned from the measured table" if tune_steps > 0 else "measured table",
+                  table=list(table), tune_seconds=round(tune_s, 2))
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     total_ms, odd_ms, even_ms, per = timed_steps(torch, ch.step, ch.stream, steps, warmup, 1)
     out = dict(ms_per_step=total_ms / steps, mlups=n * steps / (total_ms * 1e-3) / 1e6,
                odd_kernel_ms=odd_ms, even_kernel_ms=even_ms, odd_by_rows=int(ch.get_param(17)),
-               steps_profile=step_profile(per, 1 + warmup))
+               steps_profile=step_profile(per, 1 + warmup), launch=launch)
     done = warmup + steps
     # the accuracy figures belong to the workload's own step count, whatever K and W were
     ch.set_param(8, 32)                      # LBM_P_GRAPH_STEPS: the untimed remainder runs in graphs
@@ -262,7 +277,8 @@ def store_record(r, s, n, copy_gbs):
              odd_kernel_ms=r["odd_kernel_ms"], even_kernel_ms=r["even_kernel_ms"], dominant_kernel=kern,
              kernel_gbs=gbs, hbm_frac=gbs / HBM_PEAK_GBS, odd_by_rows=r.get("odd_by_rows", 0),
              step_gbs=bytes_cell * n / (r["ms_per_step"] * 1e-3) / 1e9, status=r["status"])
-    for k in ("first_bad_step", "accuracy_steps", "max_du_over_utau_vs_f64", "eps_uplus_vs_f64", "steps_profile"):
+    for k in ("first_bad_step", "accuracy_steps", "max_du_over_utau_vs_f64", "eps_uplus_vs_f64", "steps_profile",
+              "launch"):
         if k in r:
             d[k] = r[k]
     if copy_gbs:
@@ -287,7 +303,7 @@ def bench_single(P, W, args, copy_gbs):
         per_store = {}
         for s in stores:
             r, fields, p = run_store(P, W, args.workload, s, bc, args.steps, args.warmup, collision_kw(args),
-                                     acc_steps, ref)
+                                     acc_steps, ref, 0 if args.no_autotune else args.tune_steps)
             if s == "f64":
                 ref = dict(fields=fields, profile=r.get("profile")) if fields is not None else None
             print("[bench] %s %s: %.1f MLUPS, odd %.4f ms, even %.4f ms, status %d, max|du|/u_tau %s after %d steps"
@@ -308,7 +324,7 @@ def bench_single(P, W, args, copy_gbs):
     config = {"workload": "%s: %s; %d steps timed per store after %d warm-up steps, accuracy after %d steps"
                           % (args.workload, wl["desc"], args.steps, args.warmup, acc_steps),
               "grid": [nx, ny, nz], "store": head, "boundary": bcs[0], "re_tau": wl["re_tau"], "tau0": p["tau0"],
-              "fx": p["fx"], "launch": list(W.launch_tiles(args.workload, head, args.collision)),
+              "fx": p["fx"], "launch": hd["launch"],
               "collision": args.collision, "van_driest_aplus": args.van_driest, "parallelism": "single GPU",
               "timed_steps": args.steps, "accuracy_steps": acc_steps}
     if args.workload in CACHE_RESIDENT:
@@ -366,6 +382,8 @@ def main():
     ap.add_argument("--stores", default=None, help="comma list (default f64,f32,f16,bf16; c2: f64,f32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="time the measured launch table as it is")
+    ap.add_argument("--tune-steps", type=int, default=4, help="steps timed per autotuner candidate")
     ap.add_argument("--collision", default="bgk", choices=("bgk", "mrt"),
                     help="collision operator (mrt: the paper's LES collision)")
     ap.add_argument("--van-driest", type=float, default=0.0, help="van Driest A+ (0: no damping)")

@@ -285,13 +285,26 @@ int lbm_stats_reset(lbm_ctx* ctx);
 int lbm_stats_sums(lbm_ctx* ctx, double* out, int64_t* nsamples);
 int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
 
-/* Picks the block sizes of the odd and even step kernels and the cells per
- * thread by timing each candidate for `steps` steps (>= 2) on the bound
- * storage.  Valid only before the state is initialised (it writes the initial
- * profile the body force implies); afterwards the state is undefined until
- * lbm_init_* / lbm_set_state.  Synchronises.  tiles (may be NULL) receives
- * three values: the odd and even block sizes and the cells per thread. */
-int lbm_autotune(lbm_ctx* ctx, int steps, int32_t* tiles);
+/* Picks the launch shapes of the step kernels by timing them on the bound
+ * storage: the block sizes of the odd and even kernels (64, 128, 256, 512),
+ * the cells per thread (1, 2, 4 where the store and nx allow), the rows per
+ * brick of the layout (4, 8, 16, 32), the launch order (LBM_P_SPREAD: memory
+ * order or chunks of 2^5, 2^7, 2^9 tiles) and whether the odd step walks
+ * rows (LBM_P_ODD_ROWS).  Coordinate descent from the context's current
+ * shapes, one setting at a time, each candidate timed over `steps` steps
+ * (>= 2) after one warm-up pair; a change is kept only when it is more than
+ * 1 % faster (the odd-step settings judged on the odd kernel, the even block
+ * size on the even kernel, the rest on both).  The result is kept for the
+ * life of the process per (device, grid, store, boundary, collision, wall
+ * placement): a later call with the same key applies it without timing.
+ * None of these settings changes a result bit.  Valid only before the state
+ * is initialised (it writes the initial profile the body force implies);
+ * afterwards the state is undefined until lbm_init_* / lbm_set_state.
+ * Synchronises.  choice (may be NULL) receives seven values: the odd and even
+ * block sizes, the cells per thread, the rows per brick in use, the launch
+ * order's chunk log2 (0: memory order), 1 if the odd step walks rows, and 1
+ * if the result came from the cache. */
+int lbm_autotune(lbm_ctx* ctx, int steps, int32_t* choice);
 
 /* Spalding's law inverted on the host (Eq. 16): u+ for a given y+ >= 0. */
 int lbm_spalding_uplus(double yplus, double kappa, double B, double* uplus);

@@ -152,11 +152,16 @@ class Channel:
         self._chk(self.lib.lbm_set_boundary(self._h, BOUNDARIES[bc] if isinstance(bc, str) else int(bc)))
 
     def autotune(self, steps=6):
-        """Returns (odd block size, even block size, cells per thread)."""
-        t = (C.c_int32 * 3)()
+        """Tunes the launch shapes from the current ones (lbm_autotune); returns
+        a dict: tile_odd, tile_even, vector (cells per thread), brick (rows per
+        brick in use), spread (launch-order chunk log2, 0 = memory order),
+        odd_rows (1 if the odd step walks rows), cached (1 if taken from the
+        process's cache of earlier results for this grid, store and boundary)."""
+        t = (C.c_int32 * 7)()
         self._chk(self.lib.lbm_autotune(self._h, int(steps), t))
+        keys = ("tile_odd", "tile_even", "vector", "brick", "spread", "odd_rows", "cached")
         self.tiles = (t[0], t[1], t[2])
-        return self.tiles
+        return dict(zip(keys, list(t)))
 
     def init_spalding(self, u_tau, noise=0.05, seed=0):
         self._chk(self.lib.lbm_init_spalding(self._h, float(u_tau), float(noise), int(seed)))

@@ -1415,7 +1415,74 @@ int lbm_stats_get(lbm_ctx* c, double* out, int64_t* nsamples)
     });
 }
 
-int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
+namespace {
+
+// Launch shapes of a single channel: block sizes of the odd and even kernels,
+// cells per thread, rows per brick requested (0 = automatic), launch order
+// (LBM_P_SPREAD) and the odd-step mode (LBM_P_ODD_ROWS).
+struct Shapes {
+    int tile_odd, tile_even, vw, brick, spread, odd_rows;
+    bool operator==(const Shapes& o) const
+    {
+        return std::tie(tile_odd, tile_even, vw, brick, spread, odd_rows) ==
+               std::tie(o.tile_odd, o.tile_even, o.vw, o.brick, o.spread, o.odd_rows);
+    }
+};
+
+// The tuner's results, kept for the life of the process per device, grid,
+// store, boundary, collision and wall placement.
+struct TuneKey {
+    int dev, nx, ny, nz, store, bc, coll, wall_nodes;
+    bool operator<(const TuneKey& o) const
+    {
+        return std::tie(dev, nx, ny, nz, store, bc, coll, wall_nodes) <
+               std::tie(o.dev, o.nx, o.ny, o.nz, o.store, o.bc, o.coll, o.wall_nodes);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Shapes> g_tune_cache;
+
+Shapes shapes_of(const lbm_ctx* c)
+{
+    return Shapes{c->tile_odd, c->tile_even, vector_width(c), c->brick_req, spread_log2(c), c->odd_rows};
+}
+
+void apply_shapes(lbm_ctx* c, const Shapes& v)
+{
+    c->tile_odd = v.tile_odd;
+    c->tile_even = v.tile_even;
+    c->vw_req = v.vw;
+    c->brick_req = v.brick;
+    c->spread = v.spread;
+    c->odd_rows = v.odd_rows;
+}
+
+// What the odd and even launches of shapes v look like (geometry, order and
+// kernel variant); two shapes with the same signature run the same kernels.
+std::vector<long long> launch_signature(lbm_ctx* c, const Shapes& v)
+{
+    const Shapes keep = shapes_of(c);
+    apply_shapes(c, v);
+    std::vector<long long> sig;
+    for (bool odd : {true, false}) {
+        const StepArgs a = step_args(c, odd, c->odd_rows);
+        for (long long x : {(long long)a.brick, (long long)a.spread, (long long)a.spread_rot, (long long)a.nseg,
+                            (long long)a.tile_x, (long long)a.vw, (long long)a.ntx, (long long)a.rpb,
+                            (long long)a.nyt, (long long)a.ntiles})
+            sig.push_back(x);
+    }
+    apply_shapes(c, keep);
+    return sig;
+}
+
+bool same_launch(lbm_ctx* c, const Shapes& a, const Shapes& b)
+{
+    return launch_signature(c, a) == launch_signature(c, b);
+}
+
+}  // namespace
+
+int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
 {
     return guard(c, [&]() -> int {
         if (!c) return fail(nullptr, LBM_E_ARG, "null context");
@@ -1424,68 +1491,147 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* tiles)
         if (c->initialized) return fail(c, LBM_E_STATE, "autotune runs before the state is initialised");
         if (steps < 2) return fail(c, LBM_E_ARG, "steps must be >= 2");
         DeviceGuard dg(c->dev);
-        // a representative state: the initial profile the body force implies
-        const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
-        int st = init_spalding_impl(c, ut, 0.05, 0);
-        if (st != LBM_OK) return st;
-        c->initialized = false;  // a timing state only: each candidate takes the layout its shapes want
-        const int tcand[4] = {64, 128, 256, 512};
-        const int vcand[3] = {1, 2, 4};
-        hipEvent_t ev[3];
-        for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
-        // the odd and even kernels are timed separately; the group width is shared
-        float best = 1e30f;
-        int bo = c->tile_odd, be = c->tile_even, bv = vector_width(c);
-        hipError_t err = hipSuccess;
-        for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
-            if (!step_vector_width_ok(c->store, c->nx, vcand[iv])) continue;
-            c->vw_req = vcand[iv];
-            float bo_t = 1e30f, be_t = 1e30f;
-            int bo_k = 256, be_k = 256;
-            for (int k = 0; k < 4 && err == hipSuccess; ++k) {
-                c->tile_odd = c->tile_even = tcand[k];
-                float to = 0.f, te = 0.f;
-                // one warm-up pair, then timed pairs
-                for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
-                    const StepArgs ao = step_args(c, true, c->odd_rows), ae = step_args(c, false, c->odd_rows);
-                    err = hipEventRecord(ev[0], c->stream);
-                    if (err == hipSuccess) err = launch_step(c->store, true, c->bc, ao, c->stream);
-                    if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
-                    if (err == hipSuccess) err = launch_step(c->store, false, c->bc, ae, c->stream);
-                    if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
-                    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
-                    float a = 0.f, b = 0.f;
-                    if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
-                    if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
-                    if (r > 0) {
-                        to += a;
-                        te += b;
-                    }
-                }
-                if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
-                if (te < be_t) { be_t = te; be_k = tcand[k]; }
+        const TuneKey key{c->dev, c->nx, c->ny, c->nz, c->store, c->bc, c->coll, c->wall_nodes};
+        auto report = [&](const Shapes& v, bool cached) {
+            if (out) {
+                out[0] = v.tile_odd;
+                out[1] = v.tile_even;
+                out[2] = v.vw;
+                out[3] = brick_for_tiles(c);
+                out[4] = v.spread;
+                out[5] = odd_by_rows(c, v.odd_rows) ? 1 : 0;
+                out[6] = cached ? 1 : 0;
             }
-            if (bo_t + be_t < best) {
-                best = bo_t + be_t;
-                bo = bo_k;
-                be = be_k;
-                bv = vcand[iv];
+        };
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                apply_shapes(c, it->second);
+                drop_graphs(c);
+                report(it->second, true);
+                return LBM_OK;
             }
         }
+        // a representative state: the initial profile the body force implies,
+        // written again whenever a candidate's rows per brick change the layout
+        const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
+        int state_brick = -1;
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
+        const Shapes start = shapes_of(c);
+        int st = LBM_OK;
+        hipError_t err = hipSuccess;
+        // mean odd and even kernel times (ms) of shapes v: one warm-up step pair,
+        // then steps / 2 timed pairs
+        auto measure = [&](const Shapes& v, float* to, float* te) -> bool {
+            apply_shapes(c, v);
+            if (brick_for_tiles(c) != state_brick) {
+                if ((st = init_spalding_impl(c, ut, 0.05, 0)) != LBM_OK) return false;
+                c->initialized = false;  // a timing state only: each candidate takes the layout its shapes want
+                state_brick = c->brick;
+            }
+            const int pairs = std::max(1, steps / 2);
+            *to = *te = 0.f;
+            for (int r = 0; r <= pairs && err == hipSuccess; ++r) {
+                const StepArgs ao = step_args(c, true, c->odd_rows), ae = step_args(c, false, c->odd_rows);
+                err = hipEventRecord(ev[0], c->stream);
+                if (err == hipSuccess) err = launch_step(c->store, true, c->bc, ao, c->stream);
+                if (err == hipSuccess) err = hipEventRecord(ev[1], c->stream);
+                if (err == hipSuccess) err = launch_step(c->store, false, c->bc, ae, c->stream);
+                if (err == hipSuccess) err = hipEventRecord(ev[2], c->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                float a = 0.f, b = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&a, ev[0], ev[1]);
+                if (err == hipSuccess) err = hipEventElapsedTime(&b, ev[1], ev[2]);
+                if (r > 0) {
+                    *to += a / pairs;
+                    *te += b / pairs;
+                }
+            }
+            return err == hipSuccess;
+        };
+        // Coordinate descent from the current shapes: one setting at a time, a
+        // change kept only when it is faster by more than kMargin (timing noise);
+        // the odd-step settings are judged on the odd kernel, the even block size
+        // on the even kernel, the shared settings on the pair.
+        constexpr float kMargin = 0.01f;
+        Shapes best = start;
+        float bo = 0.f, be = 0.f;
+        bool ok = measure(best, &bo, &be);
+        const int tiles[4] = {64, 128, 256, 512};
+        const int widths[3] = {1, 2, 4};
+        const int bricks[4] = {4, 8, 16, 32};
+        const int spreads[4] = {0, 5, 7, 9};
+        enum Judge { kPair, kOdd, kEven };
+        auto consider = [&](Shapes v, Judge j) -> bool {
+            if (!ok || same_launch(c, v, best)) return false;
+            float to = 0.f, te = 0.f;
+            if (!(ok = measure(v, &to, &te))) return false;
+            const float was = j == kOdd ? bo : j == kEven ? be : bo + be;
+            const float now = j == kOdd ? to : j == kEven ? te : to + te;
+            if (now < was * (1.f - kMargin)) {
+                best = v;
+                if (j == kOdd) {
+                    bo = to;
+                } else if (j == kEven) {
+                    be = te;
+                } else {
+                    bo = to;
+                    be = te;
+                }
+                return true;
+            }
+            return false;
+        };
+        for (int round = 0; round < 2 && ok; ++round) {
+            bool changed = false;
+            for (int w : widths) {
+                if (!step_vector_width_ok(c->store, c->nx, w)) continue;
+                Shapes v = best;
+                v.vw = w;
+                changed |= consider(v, kPair);
+            }
+            for (int t : tiles) {
+                Shapes v = best;
+                v.tile_odd = t;
+                changed |= consider(v, kOdd);
+            }
+            for (int m : {0, 2}) {
+                Shapes v = best;
+                v.odd_rows = m;
+                changed |= consider(v, kOdd);
+            }
+            for (int t : tiles) {
+                Shapes v = best;
+                v.tile_even = t;
+                changed |= consider(v, kEven);
+            }
+            for (int b : bricks) {
+                Shapes v = best;
+                v.brick = b;
+                changed |= consider(v, kPair);
+            }
+            for (int sp : spreads) {
+                Shapes v = best;
+                v.spread = sp;
+                changed |= consider(v, kPair);
+            }
+            if (!changed) break;
+        }
         for (auto& e : ev) (void)hipEventDestroy(e);
-        c->tile_odd = bo;
-        c->tile_even = be;
-        c->vw_req = bv;
+        apply_shapes(c, ok ? best : start);
         c->initialized = false;
         drop_graphs(c);
+        if (st != LBM_OK) return st;
         if (err != hipSuccess) return fail(c, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
         DevFlags f;
         if ((st = read_flags(c, &f)) != LBM_OK) return st;
-        if (tiles) {
-            tiles[0] = bo;
-            tiles[1] = be;
-            tiles[2] = bv;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = best;
         }
+        report(best, false);
         return LBM_OK;
     });
 }

@@ -55,13 +55,35 @@ def test_block_size_and_remap_invariance(P, orc, store):
             assert np.array_equal(s, ref), (tiles, remap)
 
 
-def test_autotune_picks_valid_tiles(P):
-    ch = P.Channel(256, 16, 16, 0.51, fx=1e-6, store="f32", bc="wfb")
+def test_autotune_picks_valid_shapes_and_caches_them(P):
+    """The tuner's choice is a valid set of launch shapes that the context
+    reads back, a second context of the same grid, store and boundary gets it
+    from the cache, and the tuned shapes give the default shapes' bits."""
+    from paper_2009_04352_amd import _lib as L
+    grid = (256, 24, 16)
+    ch = P.Channel(*grid, 0.51, fx=1e-6, store="f32", bc="wfb")
     t = ch.autotune(steps=4)
-    assert t[0] in (64, 128, 256, 512) and t[1] in (64, 128, 256, 512)
+    assert t["cached"] == 0
+    assert t["tile_odd"] in (64, 128, 256, 512) and t["tile_even"] in (64, 128, 256, 512)
+    assert t["vector"] in (1, 2) and t["spread"] in (0, 5, 7, 9) and t["odd_rows"] in (0, 1)
+    assert 1 <= t["brick"] <= grid[1]
+    for key, name in ((L.LBM_P_TILE_ODD, "tile_odd"), (L.LBM_P_TILE_EVEN, "tile_even"), (L.LBM_P_VECTOR, "vector"),
+                      (L.LBM_P_BRICK, "brick"), (L.LBM_P_SPREAD, "spread"), (L.LBM_P_ODD_BY_ROWS, "odd_rows")):
+        assert ch.get_param(key) == t[name], name
+    again = P.Channel(*grid, 0.51, fx=1e-6, store="f32", bc="wfb")
+    t2 = again.autotune(steps=4)
+    assert t2["cached"] == 1 and {k: v for k, v in t2.items() if k != "cached"} == \
+        {k: v for k, v in t.items() if k != "cached"}
+    plain = P.Channel(*grid, 0.51, fx=1e-6, store="f32", bc="wfb")
+    for c in (ch, plain):
+        c.init_spalding(0.01, 0.05, 3)
+        c.step(9)
+        assert c.sync()[0] == 0
+    np.testing.assert_array_equal(ch.get_state(), plain.get_state())
     with pytest.raises(P.LbmError):
-        ch.init_spalding(1e-3)
         ch.autotune()           # only before the state is initialised
+    for c in (ch, again, plain):
+        c.close()
 
 
 @pytest.mark.parametrize("k", (3, 4))
