@@ -802,13 +802,17 @@ struct Edge {
 //     with the segment (for the last segment: the row's first element, kept
 //     from the first segment);
 //   store, e_x = +1: the first segment's first group waits for the row's last
-//     post-collision element and is written after the walk;
+//     post-collision element; the row's first 128-byte line is held in LDS and
+//     written whole after the walk;
 //   store, e_x = -1: each segment's last group waits for the next segment's
-//     first post-collision element (the last one for the row's first).
-// Every element a cell reads is read before any cell writes it: an AA cell
-// reads exactly the slots it writes, and carried elements are taken from the
-// loads of their own segment.  No LDS, no barrier, and no memory line is
-// written in parts by two wavefronts.
+//     first post-collision element (the row's first one for the last
+//     segment); the segment's last 128-byte line is held in LDS and written
+//     whole one segment later.
+// So every line is written by one store of one wavefront: no partial lines
+// reach the memory.  Every element a cell reads is read before any cell
+// writes it: an AA cell reads exactly the slots it writes, and carried
+// elements are taken from the loads of their own segment.  No barrier: the
+// lines held in LDS are only ever read by the wavefront that wrote them.
 template <typename S, int V, int BCT, bool STATS, bool MRT>
 __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepArgs* __restrict__ table,
                                                         const int* __restrict__ tile_inst, int ntiles_all)
@@ -913,11 +917,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
     const int nseg = p.nseg;
     const unsigned sbytes = (unsigned)sizeof(T);
     E gcar[kNX], gwrap[kNX], scar[kNX], swrap[kNX];
-    // groups waiting for an element of another segment, per wavefront: [0]
-    // e_x = +1, written by lane 0 (first segment), [1] e_x = -1, written by
-    // lane 63 and read by lane 0 one segment later (same wavefront, so the
-    // LDS accesses stay in program order)
-    __shared__ u32x2 dfr[kMaxBlock / 64][2][kNX];
+    // lanes whose groups fill one 128-byte line
+    constexpr int G = 128 / (V * (int)sizeof(T));
+    static_assert(G >= 16 && G <= 64 && 128 % (V * (int)sizeof(T)) == 0, "groups of 2, 4 or 8 bytes");
+    // lines held back per wavefront and shifted direction: e_x = +1, the row's
+    // first line (lanes 0 .. G - 1 of the first segment, written after the
+    // walk); e_x = -1, the current segment's last line (lanes 64 - G .. 63,
+    // written by lanes 0 .. G - 1 of the next segment or after the walk).
+    // A wavefront reads only what it wrote itself; the wave barriers keep the
+    // compiler from moving these LDS accesses across each other.
+    __shared__ u32x2 hold[kMaxBlock / 64][kNX][G];
     // the row's last element for the first segment's e_x = +1 gather
     for_each_dir([&](auto A) {
         constexpr int a = decltype(A)::value;
@@ -982,37 +991,49 @@ __global__ __launch_bounds__(kMaxBlock) void k_odd_rows(StepArgs p0, const StepA
                         const E mine = Ed::last(w[a]);
                         E pv = Ed::up(mine);
                         if (lane == 0) pv = scar[j];
-                        if (k == 0 && lane == 0) dfr[wave][0][j] = w[a];
                         scar[j] = Ed::lane_value(mine, 63);
-                        if (k > 0 || lane != 0) Ln::template store<true>(at(dst, off), Ed::join_left(w[a], pv));
+                        if (k == 0 && lane < G)       // the row's first line waits for the row's last element
+                            hold[wave][j][lane] = (lane == 0) ? w[a] : Ed::join_left(w[a], pv);
+                        else
+                            Ln::template store<true>(at(dst, off), Ed::join_left(w[a], pv));
                     } else {                          // the group at x0 ends with x0 + V's value
                         const E mine = Ed::first(w[a]);
                         const E pv = Ed::down(mine);
                         const E first0 = Ed::lane_value(mine, 0);
-                        if (k == 0) swrap[j] = first0;
-                        else if (lane == 0)           // the previous segment's last group, now complete
-                            Ln::template store<true>(at(dst, off - 64u * V * sbytes + (unsigned)(63 * V) * sbytes),
-                                                     Ed::join_right(dfr[wave][1][j], first0));
-                        if (lane == 63) dfr[wave][1][j] = w[a];
-                        if (lane != 63) Ln::template store<true>(at(dst, off), Ed::join_right(w[a], pv));
+                        if (k == 0) {
+                            swrap[j] = first0;
+                        } else if (lane < G) {        // the previous segment's last line, now complete
+                            u32x2 g = hold[wave][j][lane];
+                            if (lane == G - 1) g = Ed::join_right(g, first0);
+                            Ln::template store<true>(at(dst, off - (unsigned)(G * V) * sbytes), g);
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                        if (lane >= 64 - G)           // this segment's last line waits for the next segment
+                            hold[wave][j][lane - (64 - G)] = (lane == 63) ? w[a] : Ed::join_right(w[a], pv);
+                        else
+                            Ln::template store<true>(at(dst, off), Ed::join_right(w[a], pv));
                     }
                 }
             }
         });
     }
-    // the groups that waited for the other end of the periodic row
-    if (lane == 0) {
+    // the lines that waited for the other end of the periodic row
+    __builtin_amdgcn_wave_barrier();
+    if (lane < G) {
         for_each_dir([&](auto A) {
             constexpr int a = decltype(A)::value;
             if constexpr (kEx[a] != 0) {
                 if (shifted_out(A)) {
                     constexpr int j = xslot(a);
                     char* dst = dst_of(A);
-                    if constexpr (kEx[a] == 1)
-                        Ln::template store<true>(at(dst, 0u), Ed::join_left(dfr[wave][0][j], scar[j]));
-                    else
-                        Ln::template store<true>(at(dst, (unsigned)(p.nx - V) * sbytes),
-                                                 Ed::join_right(dfr[wave][1][j], swrap[j]));
+                    u32x2 g = hold[wave][j][lane];
+                    if constexpr (kEx[a] == 1) {
+                        if (lane == 0) g = Ed::join_left(g, scar[j]);
+                        Ln::template store<true>(at(dst, (unsigned)(lane * V) * sbytes), g);
+                    } else {
+                        if (lane == G - 1) g = Ed::join_right(g, swrap[j]);
+                        Ln::template store<true>(at(dst, (unsigned)(p.nx - (G - lane) * V) * sbytes), g);
+                    }
                 }
             }
         });
