@@ -321,7 +321,11 @@ int lbm_device_wall_utau(int32_t n, const double* U, double y1, double nu, doubl
 int lbm_codec_roundtrip(int store, int64_t n, const float* in, float* out);
 
 /* Streams `bytes` (a multiple of 16) from src to dst on the device with a
- * plain copy kernel; a probe of the achievable HBM bandwidth. */
+ * plain copy kernel (16-byte non-temporal accesses, one 16 KB chunk per block,
+ * blocks handed to the XCDs in chunks like the step kernels'); a probe of the
+ * achievable HBM bandwidth.  dst may equal src (an in-place pass, the AA
+ * step's access form); otherwise the ranges must not overlap.  Asynchronous
+ * on hip_stream. */
 int lbm_copy_probe(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------------

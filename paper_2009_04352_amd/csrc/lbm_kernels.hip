@@ -542,31 +542,28 @@ __global__ __launch_bounds__(256) void k_relayout(void* hv, long long n, int nx,
 
 // ----------------------------------------------------------- misc kernels
 
-// The bandwidth reference: a plain copy, 16 bytes per lane per access,
-// non-temporal both ways.  A block copies contiguous chunks of 16 KB (four
-// 4 KB rows of the block, all four loads in flight before the stores),
-// striding over the chunks.
+// The bandwidth reference: a streaming copy, 16 bytes per lane per access,
+// non-temporal both ways.  Each block copies one contiguous 16 KB chunk (four
+// accesses per lane, all loads before the stores); the blocks go to the XCDs
+// in chunks of consecutive tiles, as the step kernels' do (measured on
+// MI355X: 6.0-6.3 TB/s against 5.3 for chunks striding over the buffer and
+// 5.9 for the plain block order).  dst may equal src: the in-place pass is the
+// AA step's own access form.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, long long n)
+__global__ __launch_bounds__(256) void k_copy(const u32x4* src, u32x4* dst, long long n)
 {
-    const long long per = 4ll * blockDim.x;
-    for (long long base = (long long)blockIdx.x * per; base < n; base += (long long)gridDim.x * per) {
-        const long long i = base + threadIdx.x;
-        if (base + per <= n) {
-            const u32x4 a = __builtin_nontemporal_load(src + i);
-            const u32x4 b = __builtin_nontemporal_load(src + i + blockDim.x);
-            const u32x4 c = __builtin_nontemporal_load(src + i + 2 * blockDim.x);
-            const u32x4 d = __builtin_nontemporal_load(src + i + 3 * blockDim.x);
-            __builtin_nontemporal_store(a, dst + i);
-            __builtin_nontemporal_store(b, dst + i + blockDim.x);
-            __builtin_nontemporal_store(c, dst + i + 2 * blockDim.x);
-            __builtin_nontemporal_store(d, dst + i + 3 * blockDim.x);
-        } else {
-            for (int k = 0; k < 4; ++k) {
-                const long long j = i + (long long)k * blockDim.x;
-                if (j < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + j), dst + j);
-            }
-        }
+    const long long base = (long long)tile_of_block((int)blockIdx.x, (int)gridDim.x, kXcdChunkLog2 + 1) * 1024;
+    const long long i = base + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long j = i + k * 256;
+        if (j < n) v[k] = __builtin_nontemporal_load(src + j);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long j = i + k * 256;
+        if (j < n) __builtin_nontemporal_store(v[k], dst + j);
     }
 }
 
@@ -852,9 +849,9 @@ hipError_t launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s)
     if (bytes % 16 != 0) return hipErrorInvalidValue;
     const long long n = (long long)(bytes / 16);
     if (n == 0) return hipSuccess;
-    // one 16 KB chunk per block up to 32 blocks per CU of the 256
-    long long blocks = (n + 1023) / 1024;
-    if (blocks > 256 * 32) blocks = 256 * 32;
+    // one 16 KB chunk per block
+    const long long blocks = (n + 1023) / 1024;
+    if (blocks >= (1ll << 31)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n);
     return hipGetLastError();
 }
