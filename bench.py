@@ -7,6 +7,8 @@ Workloads (synthetic inputs generated on the device, see workloads.py):
   c5 (default)  2048 x 512 x 1024 channel (1.07G cells), Re_tau 2003, WFB
                 walls, Smagorinsky Cs = 0.1, Spalding profile + 5 % seeded
                 noise; accuracy after 500 steps;
+  c5s           256 x 512 x 1024 (134M cells): one GPU's x-slab of c5 split over
+                8 GPUs, at its real shape (periodic in x; no halo exchange);
   c3            512 x 128 x 256 channel (16.8M cells), same physics; 2,000 steps;
   c2            128 x 64 x 64 channel, Re_tau 640, FP32 with WFB and with
                 bounce-back walls; 10,000 steps (40 MB of populations: it lives
@@ -20,7 +22,7 @@ after every launch (per-kernel durations for the roofline), then untimed
 steps up to the workload's step count, after which the velocity field (on the
 device) is compared with the FP64 run's.  Prints one JSON line.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c3|c2|c4]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c5s|c3|c2|c4]
                 [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
                 [--collision bgk|mrt] [--van-driest A+]
 The headline line is the BGK step (the default); --collision mrt with
@@ -42,7 +44,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 STORE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 DTYPE = {"f64": "f64", "f32": "f32", "f16": "f32", "bf16": "f32"}   # arithmetic of each store
 # per workload: headline store, default timed steps and warm-up
-DEFAULTS = {"c5": ("f64", 100, 20), "c3": ("f64", 1000, 200), "c2": ("f32", 2000, 200), "c4": ("f32", 1000, 100)}
+DEFAULTS = {"c5": ("f64", 100, 20), "c5s": ("f64", 200, 20), "c3": ("f64", 1000, 200), "c2": ("f32", 2000, 200),
+            "c4": ("f32", 1000, 100)}
 CACHE_RESIDENT = {"c2"}        # populations fit the 256 MB Infinity Cache
 
 
@@ -384,7 +387,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps per store (default per workload)")
     ap.add_argument("--warmup", type=int, default=None, help="untimed warm-up steps (default per workload)")
-    ap.add_argument("--workload", default="c5", choices=("c5", "c3", "c2", "c4"))
+    ap.add_argument("--workload", default="c5", choices=("c5", "c5s", "c3", "c2", "c4"))
     ap.add_argument("--stores", default=None, help="comma list (default f64,f32,f16,bf16; c2: f64,f32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")

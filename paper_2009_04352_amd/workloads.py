@@ -37,6 +37,12 @@ WORKLOADS = {
                bcs=("wfb",), tau=0.503, desc="single channel 512x128x256 (16.8M cells), Re_tau 2003, WFB, 2k steps"),
     "c5": dict(grid=(2048, 512, 1024), re_tau=2003.0, ma=0.069, steps=500, stores=("f16", "f32"), bcs=("wfb",),
                tau=None, desc="large channel 2048x512x1024 (1.07B cells), Re_tau 2003, WFB, 500 steps"),
+    # one GPU's share of c5 split into 8 x-slabs, at its real shape (periodic
+    # in x here: the halo exchange of a multi-GPU run is not built)
+    "c5s": dict(grid=(256, 512, 1024), re_tau=2003.0, ma=0.069, steps=500, stores=("f64", "f32", "f16", "bf16"),
+                bcs=("wfb",), tau=None,
+                desc="one GPU's x-slab of the 2048x512x1024 channel over 8 GPUs, 256x512x1024 (134M cells), "
+                     "Re_tau 2003, WFB, 500 steps"),
 }
 
 # The paper's own cases (Table 1): grid, Re_tau, Ma_LB; used by the wall-law
@@ -118,6 +124,7 @@ LAUNCH_TILES = {
     "c2": {"f64": (128, 128, 1), "f32": (64, 64, 2), "f16": (64, 64, 2), "bf16": (64, 64, 2)},
     "c3": {"f64": (512, 512, 1), "f32": (128, 256, 1), "f16": (128, 128, 4), "bf16": (128, 128, 4)},
     "c5": {"f64": (512, 256, 1), "f32": (256, 256, 1), "f16": (128, 256, 4), "bf16": (128, 256, 4)},
+    "c5s": {"f64": (256, 256, 1), "f32": (256, 256, 1), "f16": (64, 64, 4), "bf16": (64, 64, 4)},
 }
 # With the MRT collision the 2-byte odd step needs more registers than three
 # wavefronts per SIMD allow at 4 cells per thread; at 2 cells per thread it

@@ -38,11 +38,13 @@ def _release(ch):
 
 # the benchmark's workloads and stores: the 2048 x 512 x 1024 channel (1.07 G
 # cells) in all four formats, the 512 x 128 x 256 channel in all four formats
-# and at its named relaxation time tau = 0.503 (FP64)
+# and at its named relaxation time tau = 0.503 (FP64 and FP16), and one GPU's
+# 256 x 512 x 1024 x-slab of the large channel (FP64, FP16)
 FULL = [("c5", "f64", "bgk", False), ("c5", "f32", "bgk", False), ("c5", "f16", "bgk", False),
         ("c5", "bf16", "bgk", False),
         ("c3", "f64", "bgk", False), ("c3", "f32", "bgk", False), ("c3", "f16", "bgk", False),
-        ("c3", "bf16", "bgk", False), ("c3", "f64", "bgk", True), ("c3", "f16", "bgk", True)]
+        ("c3", "bf16", "bgk", False), ("c3", "f64", "bgk", True), ("c3", "f16", "bgk", True),
+        ("c5s", "f64", "bgk", False), ("c5s", "f16", "bgk", False)]
 
 
 # the MRT line of the benchmark (--collision mrt --van-driest 26) on the
