@@ -293,8 +293,8 @@ int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
  * rows (LBM_P_ODD_ROWS).  Coordinate descent from the context's current
  * shapes, one setting at a time, each candidate timed over `steps` steps
  * (>= 2) after one warm-up pair; a change is kept only when it is more than
- * 1 % faster (the odd-step settings judged on the odd kernel, the even block
- * size on the even kernel, the rest on both).  The result is kept for the
+ * 1 % faster (the odd-step settings decided by the odd kernel's time, the even
+ * block size by the even kernel's, the rest by both).  The result is kept for the
  * life of the process per (device, grid, store, boundary, collision, wall
  * placement): a later call with the same key applies it without timing.
  * None of these settings changes a result bit.  Valid only before the state

@@ -1553,8 +1553,8 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
         };
         // Coordinate descent from the current shapes: one setting at a time, a
         // change kept only when it is faster by more than kMargin (timing noise);
-        // the odd-step settings are judged on the odd kernel, the even block size
-        // on the even kernel, the shared settings on the pair.
+        // the odd-step settings are decided by the odd kernel's time, the even block
+        // size by the even kernel's, the shared settings by the pair's.
         constexpr float kMargin = 0.01f;
         Shapes best = start;
         float bo = 0.f, be = 0.f;
@@ -1563,8 +1563,8 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
         const int widths[3] = {1, 2, 4};
         const int bricks[4] = {4, 8, 16, 32};
         const int spreads[4] = {0, 5, 7, 9};
-        enum Judge { kPair, kOdd, kEven };
-        auto consider = [&](Shapes v, Judge j) -> bool {
+        enum Criterion { kPair, kOdd, kEven };
+        auto consider = [&](Shapes v, Criterion j) -> bool {
             if (!ok || same_launch(c, v, best)) return false;
             float to = 0.f, te = 0.f;
             if (!(ok = measure(v, &to, &te))) return false;
