@@ -370,8 +370,13 @@ int lbm_batch_sync(lbm_batch* batch, int64_t* first_bad_step, int32_t* first_bad
  * lbm_get_state, ...); stepping, setting state or parameters through it
  * returns LBM_E_STATE.  Owned by the batch.  NULL when i is out of range. */
 lbm_ctx* lbm_batch_instance(lbm_batch* batch, int32_t i);
-/* As lbm_autotune, over the batched launch; tiles receives the odd and even
- * block sizes and the cells per thread. */
+/* Picks the launch shapes of the batched launch by timing them (valid only
+ * before the state is initialised, as lbm_autotune): every cells-per-thread
+ * width the instances allow with every block size (64-512 threads; the odd
+ * and even kernels timed apart, the width shared), then the odd step's row
+ * walk switched off or forced (LBM_P_ODD_ROWS 0, 2), kept when more than 1 %
+ * faster.  tiles (may be NULL) receives the odd and even block sizes and the
+ * cells per thread. */
 int lbm_batch_autotune(lbm_batch* batch, int steps, int32_t* tiles);
 const char* lbm_batch_last_error(const lbm_batch* batch);
 

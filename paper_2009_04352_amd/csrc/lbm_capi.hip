@@ -2190,53 +2190,84 @@ int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
         const int vcand[3] = {1, 2, 4};
         hipEvent_t ev[3];
         for (auto& e : ev) LBM_BHIP(b, hipEventCreate(&e));
+        hipError_t err = hipSuccess;
+        // mean odd and even step times (ms) of the current settings: one warm-up
+        // pair, then steps / 2 timed pairs
+        auto measure = [&](float* to, float* te) -> bool {
+            b->tables_ready = false;
+            if ((st = batch_tables(b)) != LBM_OK) return false;
+            const int pairs = std::max(1, steps / 2);
+            *to = *te = 0.f;
+            for (int r = 0; r <= pairs && err == hipSuccess; ++r) {
+                err = hipEventRecord(ev[0], b->stream);
+                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 0, 1);
+                if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
+                if (err == hipSuccess) err = batch_enqueue(b, b->stream, 1, 1);
+                if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
+                if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
+                float x = 0.f, y = 0.f;
+                if (err == hipSuccess) err = hipEventElapsedTime(&x, ev[0], ev[1]);
+                if (err == hipSuccess) err = hipEventElapsedTime(&y, ev[1], ev[2]);
+                if (r > 0) {
+                    *to += x / pairs;
+                    *te += y / pairs;
+                }
+            }
+            return err == hipSuccess;
+        };
+        // every cells-per-thread width with every block size (the odd and even
+        // kernels timed apart, the width shared), then the odd step's row walk
         float best = 1e30f;
         int bo = b->tile_odd, be = b->tile_even, bv = batch_width(b);
-        hipError_t err = hipSuccess;
-        const int save_req = b->vw_req;
-        for (int iv = 0; iv < 3 && err == hipSuccess; ++iv) {
+        const int save_req = b->vw_req, save_rows = b->odd_rows;
+        bool ok = true;
+        for (int iv = 0; iv < 3 && ok; ++iv) {
             b->vw_req = vcand[iv];
             if (batch_width(b) != vcand[iv]) continue;
             float bo_t = 1e30f, be_t = 1e30f;
             int bo_k = 256, be_k = 256;
-            for (int k = 0; k < 4 && err == hipSuccess; ++k) {
+            for (int k = 0; k < 4 && ok; ++k) {
                 b->tile_odd = b->tile_even = tcand[k];
-                b->tables_ready = false;
-                if ((st = batch_tables(b)) != LBM_OK) return st;
                 float to = 0.f, te = 0.f;
-                for (int r = 0; r <= steps / 2 && err == hipSuccess; ++r) {
-                    err = hipEventRecord(ev[0], b->stream);
-                    if (err == hipSuccess) err = batch_enqueue(b, b->stream, 0, 1);
-                    if (err == hipSuccess) err = hipEventRecord(ev[1], b->stream);
-                    if (err == hipSuccess) err = batch_enqueue(b, b->stream, 1, 1);
-                    if (err == hipSuccess) err = hipEventRecord(ev[2], b->stream);
-                    if (err == hipSuccess) err = hipEventSynchronize(ev[2]);
-                    float x = 0.f, y = 0.f;
-                    if (err == hipSuccess) err = hipEventElapsedTime(&x, ev[0], ev[1]);
-                    if (err == hipSuccess) err = hipEventElapsedTime(&y, ev[1], ev[2]);
-                    if (r > 0) {
-                        to += x;
-                        te += y;
-                    }
-                }
+                if (!(ok = measure(&to, &te))) break;
                 if (to < bo_t) { bo_t = to; bo_k = tcand[k]; }
                 if (te < be_t) { be_t = te; be_k = tcand[k]; }
             }
-            if (bo_t + be_t < best) {
+            if (ok && bo_t + be_t < best) {
                 best = bo_t + be_t;
                 bo = bo_k;
                 be = be_k;
                 bv = vcand[iv];
             }
         }
+        int brows = save_rows;
+        if (ok) {
+            b->vw_req = bv;
+            b->tile_odd = bo;
+            b->tile_even = be;
+            float to0 = 0.f, te0 = 0.f;
+            ok = measure(&to0, &te0);
+            for (int m : {0, 2}) {
+                if (!ok || m == save_rows) continue;
+                b->odd_rows = m;
+                float to = 0.f, te = 0.f;
+                if (!(ok = measure(&to, &te))) break;
+                if (to < to0 * 0.99f) {
+                    to0 = to;
+                    brows = m;
+                }
+            }
+        }
         for (auto& e : ev) (void)hipEventDestroy(e);
-        b->vw_req = (err == hipSuccess) ? bv : save_req;
+        b->vw_req = ok ? bv : save_req;
+        b->odd_rows = ok ? brows : save_rows;
         b->tile_odd = bo;
         b->tile_even = be;
         b->tables_ready = false;
         b->initialized = false;
         for (lbm_ctx* c : b->inst) c->initialized = false;
         batch_drop_graphs(b);
+        if (st != LBM_OK) return st;
         if (err != hipSuccess) return bfail(b, LBM_E_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
         if (tiles) {
             tiles[0] = bo;

@@ -103,3 +103,23 @@ def test_ensemble_workload_runs(P):
         ch.init_spalding(e["u_tau"], 0.05, e["seed"])
         ch.step(20)
         assert np.array_equal(b.instance(i).get_state(), ch.get_state()), i
+
+
+def test_batch_autotune_picks_valid_shapes(P):
+    """The batch tuner's choice is a valid launch shape (block sizes, cells per
+    thread, odd-step mode) and the tuned batch evolves bit for bit as the
+    batch with its default shapes."""
+    specs = [dict(nx=128, ny=6, nz=3, tau=0.51, cs=0.1, fx=1e-6, bc="wfb"),
+             dict(nx=256, ny=5, nz=4, tau=0.52, cs=0.1, fx=2e-6, bc="bb")]
+    u_tau = [1e-2, 2e-2]
+    tuned = P.Batch(specs, store="f32", graph_steps=0)
+    t = tuned.autotune(steps=4)
+    assert t[0] in (64, 128, 256, 512) and t[1] in (64, 128, 256, 512) and t[2] in (1, 2)
+    out = []
+    for b in (tuned, P.Batch(specs, store="f32", graph_steps=0)):
+        b.init_spalding(u_tau, 0.05, seeds=[3, 4])
+        b.step(5)
+        assert b.sync()[0] == 0
+        out.append([b.instance(i).get_state() for i in range(len(specs))])
+    for a, c in zip(*out):
+        np.testing.assert_array_equal(a, c)

@@ -48,3 +48,23 @@ def test_codec_nan_and_inf(P):
         assert got[0] == np.inf and got[1] == -np.inf and np.isnan(got[2])
     got = P.codec_roundtrip("f16", np.array([7e4, -7e4], dtype=np.float32))
     assert np.all(np.isinf(got))   # beyond the binary16 range
+
+
+@pytest.mark.parametrize("nbytes", (16, 16 * 1023, 16 * 1024 * 33 + 48, (1 << 26) + 16 * 7))
+def test_copy_probe_copies_and_runs_in_place(P, nbytes):
+    """The bandwidth probe copies exactly nbytes (ragged last chunk included)
+    between two buffers, leaves the bytes after them alone, and an in-place
+    pass (dst == src) leaves the data unchanged."""
+    import torch
+    print("copy probe %d bytes" % nbytes, flush=True)
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    P.copy_probe(dst, src, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert int(dst[nbytes:].abs().sum()) == 0
+    ref = src.clone()
+    P.copy_probe(src, src, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(src, ref)
