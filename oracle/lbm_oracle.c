@@ -123,7 +123,10 @@ typedef struct {
     double vd_utau;      /* friction velocity for the damping's y+; <= 0: sqrt(|Fx| ny / 2) */
     int32_t wall_nodes;  /* 0: link-wise walls halfway below row 0 and above row ny - 1, WFB on the
                           * first fluid layer; 1: wall nodes at y = -1 and y = ny (Sec. 2.1-2.2,
-                          * Eq. 3, 4 and 14 applied at the wall grid) */
+                          * Eq. 3, 4 and 14 applied at the wall grid), the stress of a step's
+                          * wall-node collision from the first layer's velocity of the previous
+                          * step; 2: the same wall nodes, the stress from the first layer's
+                          * velocity of the same step */
 } orc_params;
 
 typedef struct {
@@ -629,7 +632,7 @@ static int params_ok(const orc_params* p)
     if (!isfinite(p->tau0) || !isfinite(p->cs) || !isfinite(p->kappa) || !isfinite(p->bconst)) return 0;
     if (!isfinite(p->fx) || !(p->y1 > 0.0) || !(p->newton_tol > 0.0) || p->newton_maxit < 1) return 0;
     if (p->bc < 0 || p->bc > 2 || p->stats_every < 0) return 0;
-    if (p->wall_nodes != 0 && p->wall_nodes != 1) return 0;
+    if (p->wall_nodes < 0 || p->wall_nodes > 2) return 0;
     if (p->collision != ORC_BGK && p->collision != ORC_MRT) return 0;
     if (p->collision == ORC_MRT) {
         const double r[5] = {p->s_e, p->s_eps, p->s_q, p->s_pi, p->s_m};
@@ -693,10 +696,11 @@ int orc_set_param_bc(orc* o, int32_t bc)
  * both walls: the populations the first layer sent towards W on the
  * previous step (o->fpost, taken from the cells x - e_b in the wall plane)
  * collide by orc_wall_node_collide with the stress of Eq. 15-17 from the
- * first layer's density and velocity of the previous step at W's column
- * (o->urec); the five outputs that stream into the fluid go to fw_out.
- * Returns ORC_E_NEWTON if a Newton solve fails. */
-static int wall_node_update(const orc* o, double* fw_out, int32_t* maxit)
+ * first layer's density and velocity at W's column in urec (those of the
+ * previous step, or of this step with wall_nodes = 2); the five outputs
+ * that stream into the fluid go to fw_out.  Returns ORC_E_NEWTON if a
+ * Newton solve fails. */
+static int wall_node_update(const orc* o, const double* urec, double* fw_out, int32_t* maxit)
 {
     const orc_params* p = &o->p;
     int bad = 0;
@@ -713,7 +717,7 @@ static int wall_node_update(const orc* o, double* fw_out, int32_t* maxit)
                         f[b] = o->fpost[(int64_t)b * o->ncell + cell_index(p, sx, y, sz)];
                     }
                 }
-                const double* u = o->urec + 3 * (((int64_t)w * p->nz + z) * p->nx + x);
+                const double* u = urec + 3 * (((int64_t)w * p->nz + z) * p->nx + x);
                 int32_t it = 0;
                 if (p->bc == ORC_WFB && orc_wall_tau(p, u[0], u[1], u[2], rec, &it) != ORC_OK) bad = 1;
                 if (it > mx) mx = it;
@@ -751,7 +755,7 @@ static int wall_node_start(orc* o)
                 u[0] = r; u[1] = jx / r; u[2] = jz / r;
             }
     }
-    return wall_node_update(o, o->fw, NULL);
+    return wall_node_update(o, o->urec, o->fw, NULL);
 }
 
 void orc_set_state(orc* o, const double* fpost)
@@ -825,8 +829,10 @@ int orc_step(orc* o, int64_t n)
         src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL, o->fw};
         int bad = 0;
         int32_t maxit = o->max_newton_iters;
-        /* wall nodes: their collision of this step, from the previous step's state */
-        if (p->wall_nodes && wall_node_update(o, o->fw_new, &maxit) != ORC_OK) bad |= 2;
+        /* wall nodes: their collision of this step, of the populations the first
+         * layer sent on the previous step, with the stress from the first
+         * layer's velocity of the previous step (after the cells: of this step) */
+        if (p->wall_nodes == 1 && wall_node_update(o, o->urec, o->fw_new, &maxit) != ORC_OK) bad |= 2;
         double* srow = NULL;
         if (sample) {
             srow = (double*)calloc((size_t)p->nz * p->ny * 7, sizeof(double));
@@ -860,6 +866,7 @@ int orc_step(orc* o, int64_t n)
                 }
             }
         }
+        if (p->wall_nodes == 2 && wall_node_update(o, o->urec_new, o->fw_new, &maxit) != ORC_OK) bad |= 2;
         if (sample) {
             for (int y = 0; y < p->ny; ++y) {
                 for (int z = 0; z < p->nz; ++z)
@@ -918,8 +925,9 @@ int orc_wall(const orc* o, double* taux, double* tauz, double* utau, double* uu)
     const orc_params* p = &o->p;
     src_t s = {p, o->fpost, NULL, 0.0, 0, NULL, NULL, 0, NULL, o->fw};
     if (p->wall_nodes) {
-        /* the stress the next wall-node collision applies, from the first
-         * layer's latest density and velocity (WFB); bounce-back: the momentum
+        /* the stress from the first layer's latest density and velocity (WFB:
+         * what the next wall-node collision applies, or with wall_nodes = 2 what
+         * the latest one applied); bounce-back: the momentum
          * exchange of the populations the first layer sends towards the wall
          * node; free-slip: no stress */
         for (int w = 0; w < 2; ++w) {

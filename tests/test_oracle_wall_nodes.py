@@ -17,6 +17,12 @@ previous step).
   Poiseuille solution of halfway bounce-back (the lag does not matter in a
   steady state); uniform flow is a fixed point of free-slip wall nodes; the
   laminar WFB channel balances the body force with the wall stress.
+
+wall_nodes = 2 takes the wall-node stress from the first layer's velocity of
+the same step (the moments of the populations it gathers in that step)
+instead of the previous one: the brute-force check recomputes that gather,
+and the budgets and the steady state hold as for mode 1; for bounce-back and
+free-slip, which apply no stress, the two modes agree bit for bit.
 """
 import math
 
@@ -26,8 +32,8 @@ import pytest
 import golden_io
 
 
-def _node_params(orc, nx, ny, nz, tau, bc, **kw):
-    return orc.make_params(nx, ny, nz, tau, bc=bc, wall_nodes=1, **kw)
+def _node_params(orc, nx, ny, nz, tau, bc, mode=1, **kw):
+    return orc.make_params(nx, ny, nz, tau, bc=bc, wall_nodes=mode, **kw)
 
 
 @pytest.mark.parametrize("wall", (0, 1))
@@ -83,16 +89,18 @@ def _random_state(orc, shape, rng, u_scale=0.05):
     return f * (1 + rng.uniform(-2e-3, 2e-3, f.shape))
 
 
-def test_lag_and_doubled_shift_on_a_tiny_grid(orc):
+@pytest.mark.parametrize("mode", (1, 2))
+def test_lag_and_doubled_shift_on_a_tiny_grid(orc, mode):
     """Brute force: the wall nodes' outputs after one step are the reflected
     first-layer populations of the initial state from x - e_b, with the stress
-    of the initial first layer at the node's column; the first layer then
-    gathers them from x - e_a."""
+    of the first layer at the node's column: its initial record (mode 1), or
+    the moments of the populations it gathered in that step (mode 2); the
+    first layer then gathers them from x - e_a."""
     e, _, opp, mir = orc.tables()
     nx, ny, nz = 5, 3, 4
     rng = np.random.default_rng(8)
     f0 = _random_state(orc, (nz, ny, nx), rng)
-    p = _node_params(orc, nx, ny, nz, 0.52, orc.WFB, cs=0.1, fx=2e-6)
+    p = _node_params(orc, nx, ny, nz, 0.52, orc.WFB, mode=mode, cs=0.1, fx=2e-6)
     o = orc.Oracle(p)
     o.set_state(f0)
     fw0, ur0 = o.wall_nodes()
@@ -104,14 +112,30 @@ def test_lag_and_doubled_shift_on_a_tiny_grid(orc):
         np.testing.assert_allclose(ur0[w, :, :, 1], np.tensordot(e[:, 0], col, 1) / r, rtol=0, atol=1e-16)
         np.testing.assert_allclose(ur0[w, :, :, 2], np.tensordot(e[:, 2], col, 1) / r, rtol=0, atol=1e-16)
     assert o.step(1) == 0
-    fw1, _ = o.wall_nodes()
+    fw1, ur1 = o.wall_nodes()
     f1 = o.state()
+    if mode == 2:
+        # the record of step 1: moments (with the half force) of what the first
+        # layer gathered, the fluid from f0 and the wall nodes' start outputs fw0
+        for w, y in ((0, 0), (1, ny - 1)):
+            for z in range(nz):
+                for x in range(nx):
+                    f = np.empty(19)
+                    for a in range(19):
+                        sy = y - e[a, 1]
+                        sx, sz = (x - e[a, 0]) % nx, (z - e[a, 2]) % nz
+                        f[a] = f0[a, sz, sy, sx] if 0 <= sy < ny else fw0[w, list(orc.IN_W[w]).index(a), sz, sx]
+                    r = f.sum()
+                    assert abs(ur1[w, z, x, 0] - r) <= 1e-15
+                    assert abs(ur1[w, z, x, 1] - (e[:, 0] @ f + 0.5 * p.fx) / r) <= 1e-16
+                    assert abs(ur1[w, z, x, 2] - (e[:, 2] @ f) / r) <= 1e-16
+    urs = ur0 if mode == 1 else ur1
     shifted, _ = golden_io.eq14()
     sgn = {a: (s, c) for a, _, s, c in shifted}
     for w, y in ((0, 0), (1, ny - 1)):
         for z in range(nz):
             for x in range(nx):
-                rec, st = orc.wall_tau(p, *ur0[w, z, x])
+                rec, st = orc.wall_tau(p, *urs[w, z, x])
                 assert st == 0
                 for k, a in enumerate(orc.IN_W[w]):
                     b = int(mir[a])                                  # the arrival reflected into a
@@ -153,11 +177,16 @@ def _totals(orc, o):
     return m, px
 
 
+@pytest.mark.parametrize("mode", (1, 2))
 @pytest.mark.parametrize("bc", (0, 1, 2))
-def test_mass_and_x_momentum_of_fluid_and_wall_nodes(orc, bc):
+def test_mass_and_x_momentum_of_fluid_and_wall_nodes(orc, bc, mode):
+    """x-momentum of fluid plus wall nodes changes by N Fx plus the stress of
+    the step's wall-node collisions: for WFB from the record before the step
+    (mode 1) or from the one the step computed (mode 2); for bounce-back the
+    momentum exchange of the populations waiting at the nodes."""
     nx, ny, nz = 6, 5, 4
     rng = np.random.default_rng(30 + bc)
-    p = _node_params(orc, nx, ny, nz, 0.5003, bc, cs=0.1, fx=3e-6)
+    p = _node_params(orc, nx, ny, nz, 0.5003, bc, mode=mode, cs=0.1, fx=3e-6)
     o = orc.Oracle(p)
     o.set_state(_random_state(orc, (nz, ny, nx), rng))
     m0, _ = _totals(orc, o)
@@ -165,6 +194,8 @@ def test_mass_and_x_momentum_of_fluid_and_wall_nodes(orc, bc):
         _, p0 = _totals(orc, o)
         taux, _, _, _ = o.wall()
         assert o.step(1) == 0
+        if mode == 2 and bc == orc.WFB:
+            taux, _, _, _ = o.wall()   # the WFB stress of the step's own record
         m1, p1 = _totals(orc, o)
         want = nx * ny * nz * p.fx + math.fsum(taux.ravel())
         assert abs((p1 - p0) - want) <= 1e-9 * abs(want) + 1e-13 * abs(p0)
@@ -207,12 +238,13 @@ def test_uniform_flow_is_a_fixed_point_of_free_slip_nodes(orc):
             assert d <= 1e-15
 
 
-def test_wfb_nodes_laminar_force_balance(orc):
+@pytest.mark.parametrize("mode", (1, 2))
+def test_wfb_nodes_laminar_force_balance(orc, mode):
     """The steady laminar channel with WFB wall nodes: the wall stress of both
     walls balances the body force on the ny fluid layers, mean tau_x = -F ny / 2,
     and the stress is Spalding's law at the first layer (y+ = y1 u_tau / nu)."""
     ny, F, tau = 8, 1e-6, 0.8
-    o = orc.Oracle(_node_params(orc, 1, ny, 1, tau, orc.WFB, cs=0.0, fx=F))
+    o = orc.Oracle(_node_params(orc, 1, ny, 1, tau, orc.WFB, mode=mode, cs=0.0, fx=F))
     f0 = np.stack([orc.feq(1.0, np.zeros(3))] * ny, axis=1)
     o.set_state(f0.reshape(19, 1, ny, 1))
     assert o.step(8000) == 0
@@ -234,3 +266,19 @@ def test_cell_paths_reject_wall_nodes(orc):
     p = _node_params(orc, 4, 4, 4, 0.52, orc.WFB)
     with pytest.raises(RuntimeError):
         orc.step1_cells(p, 0.01, 0.05, 0, np.arange(4, dtype=np.int64))
+
+
+@pytest.mark.parametrize("bc", (0, 2))
+def test_modes_agree_without_stress(orc, bc):
+    """Bounce-back and free-slip wall nodes apply no stress: the two stress
+    timings give the same states and wall nodes bit for bit."""
+    nx, ny, nz = 6, 5, 4
+    f0 = _random_state(orc, (nz, ny, nx), np.random.default_rng(40 + bc))
+    out = []
+    for mode in (1, 2):
+        o = orc.Oracle(_node_params(orc, nx, ny, nz, 0.51, bc, mode=mode, cs=0.1, fx=2e-6))
+        o.set_state(f0)
+        assert o.step(9) == 0
+        out.append((o.state(), o.wall_nodes()[0]))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])

@@ -60,6 +60,9 @@ MISTAKES = {
     "bounce-back node mirrored": ("for (int a = 0; a < Q; ++a) o[a] = g[OPP[a]];", "for (int a = 0; a < Q; ++a) o[a] = g[MIR[a]];"),
     "wall node velocity u_y for u_z": ("u[0] = mom[0]; u[1] = mom[1]; u[2] = mom[3];", "u[0] = mom[0]; u[1] = mom[1]; u[2] = mom[2];"),
     "wall node start without the plain moments": ("u[0] = r; u[1] = jx / r; u[2] = jz / r;", "u[0] = r; u[1] = jx; u[2] = jz / r;"),
+    "same-step wall node stress from the previous record": (
+        "if (p->wall_nodes == 2 && wall_node_update(o, o->urec_new, o->fw_new, &maxit)",
+        "if (p->wall_nodes == 2 && wall_node_update(o, o->urec, o->fw_new, &maxit)"),
     "opposite of a direction": ("E[b][1] == -E[a][1] && E[b][2] == -E[a][2]) OPP[a] = b;",
                                 "E[b][1] == -E[a][1] && E[b][2] == E[a][2]) OPP[a] = b;"),
 }
