@@ -120,7 +120,10 @@ extern "C" {
                                * and stream into the fluid at the next step.  The wall records of lbm_wall_shear
                                * are then those of the next wall-node collision; lbm_wall_mass_change is not
                                * defined (LBM_E_STATE); state transfer restarts the wall nodes from the state
-                               * (lbm_get_wall_nodes).  Not for batches. */
+                               * (lbm_get_wall_nodes).  2 = the same wall nodes with tau_w from the first
+                               * layer's density and velocity of the same step (the moments of what it gathers
+                               * in that step), the wall records then those of the latest wall-node collision.
+                               * Not for batches. */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -263,7 +266,7 @@ int lbm_wall_yplus_pdf_noalloc(lbm_ctx* ctx, int32_t nbins, double lo, double hi
  * walls, whose reflections only permute.  Synchronises. */
 int lbm_wall_mass_change(lbm_ctx* ctx, double* dsum, double* rho);
 
-/* Wall-node state (LBM_P_WALL_NODES = 1, else LBM_E_STATE): fw [2][5][nz][nx]
+/* Wall-node state (LBM_P_WALL_NODES = 1 or 2, else LBM_E_STATE): fw [2][5][nz][nx]
  * receives, as h = f - w, the populations each wall node sends into the fluid
  * at the next step (walls w = 0 bottom, 1 top; directions 3, 7, 11, 14, 17
  * at the bottom and their mirror images 4, 13, 18, 8, 12 at the top); rec

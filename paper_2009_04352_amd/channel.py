@@ -100,7 +100,7 @@ class Channel:
             self._set(L.LBM_P_BRICK, brick)
         set_collision(self._set, collision, mrt_rates, van_driest, van_driest_utau)
         if wall_nodes:
-            self._set(L.LBM_P_WALL_NODES, 1)
+            self._set(L.LBM_P_WALL_NODES, int(wall_nodes))   # True / 1: stress of the previous step; 2: same step
         nbytes = C.c_size_t(0)
         L.check(self.lib.lbm_required_bytes(self._h, C.byref(nbytes)), self._h)
         self.nbytes = nbytes.value

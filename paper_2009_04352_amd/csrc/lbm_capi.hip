@@ -673,7 +673,9 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
             case LBM_P_WALL_NODES:
                 if (c->initialized)
                     return fail(c, LBM_E_STATE, "the wall placement is fixed once the state is initialised");
-                if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "wall nodes is 0 (halfway walls) or 1");
+                if (v != 0.0 && v != 1.0 && v != 2.0)
+                    return fail(c, LBM_E_ARG, "wall nodes is 0 (halfway walls), 1 or 2 (wall nodes, stress of the "
+                                              "previous or of the same step)");
                 if (c->wall_nodes != (int)v && c->dwn) {
                     drop_graphs(c);
                     (void)hipFree(c->dwn);

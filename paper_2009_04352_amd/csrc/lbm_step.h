@@ -549,8 +549,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
         }
     }
 
+    // wall nodes: the collision of the populations that arrived there, with the
+    // stress from the first layer's record of the previous step (mode 1); in
+    // mode 2 it follows the record of this step, below
     if constexpr (NODE) {
-        if (L.active && (bot || top)) node_collide<S, V>(p, top, z, L.x0, prev, cur);
+        if (L.active && (bot || top) && p.wall_nodes != 2) node_collide<S, V>(p, top, z, L.x0, prev, cur);
     }
 
     double sm[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -622,6 +625,10 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(min_w
             node_record<V>(p, top, z, L.x0, nrho, nux, nuz, it, fl);
             iters = max(iters, it);
             newton_fail = newton_fail || fl;
+            // the record of a node's column is this thread's own, and the arrivals
+            // it collides came in the previous step (ring prev; this step's stores
+            // fill ring cur)
+            if (p.wall_nodes == 2) node_collide<S, V>(p, top, z, L.x0, prev, cur);
         }
     }
     if (L.active && (bad || newton_fail)) {

@@ -83,7 +83,8 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
     (keys s_e, s_eps, s_q, s_pi, s_m).  With mass_steps > 0, the Appendix B
     mass check runs over
     that many steps between the two phases.  wall_nodes: the wall grid as a
-    lattice node (LBM_P_WALL_NODES); the channel then has ny - 1 fluid layers
+    lattice node (LBM_P_WALL_NODES 1 or 2: the stress from the first layer's
+    velocity of the previous or of the same step); the channel then has ny - 1 fluid layers
     between wall nodes ny spacings apart, so that D = ny / 2 and the
     parameters are those of the halfway channel of ny layers.  Returns the
     metrics with the run's parameters and the sampled mean profile."""
@@ -137,7 +138,7 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
         m.update(mean_ux=stats[:, 0].tolist(), mean_uxuy=stats[:, 6].tolist(), mean_ux2=stats[:, 3].tolist())
     m.update(workload=workload, grid=[nx, ny, nz], store=store, bc=bc, collision=collision,
              van_driest_aplus=van_driest, re_tau=W.case(workload)["re_tau"], u_tau=p["u_tau"], tau0=p["tau0"],
-             fx=p["fx"], wall_nodes=bool(wall_nodes), develop_steps=develop, sample_steps=sample,
+             fx=p["fx"], wall_nodes=int(wall_nodes), develop_steps=develop, sample_steps=sample,
              stats_every=stats_every, develop_T=develop / T, sample_T=sample / T, sampled_steps=nsamp, status=0,
              seconds=time.time() - t0)
     if mass is not None:
@@ -164,7 +165,9 @@ def main():
     ap.add_argument("--report-every", type=int, default=50000)
     ap.add_argument("--mass-steps", type=int, default=0)
     ap.add_argument("--mrt-rates", default="", help="e.g. s_e=1.19,s_q=1.2 (MRT rates to override)")
-    ap.add_argument("--wall-nodes", action="store_true", help="the wall grid as a lattice node (LBM_P_WALL_NODES)")
+    ap.add_argument("--wall-nodes", type=int, nargs="?", const=1, default=0, choices=(0, 1, 2),
+                    help="the wall grid as a lattice node (LBM_P_WALL_NODES): 1 = stress of the previous step, "
+                         "2 = of the same step")
     ap.add_argument("--out", default="", help="also write the record to this JSON file")
     a = ap.parse_args()
     rates = {k: float(v) for k, v in (kv.split("=") for kv in a.mrt_rates.split(",") if kv)} or None

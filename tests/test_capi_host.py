@@ -183,7 +183,7 @@ def test_workload_parameters_match_oracle_mapping(orc):
 
 
 def test_wall_node_parameter(L):
-    """The wall placement key: 0 or 1, read back; state calls without storage
+    """The wall placement key: 0, 1 or 2, read back; state calls without storage
     are state errors; batches do not take it."""
     lib = L.lib()
     h = C.c_void_p()
@@ -192,7 +192,9 @@ def test_wall_node_parameter(L):
         v = C.c_double()
         assert lib.lbm_get_param(h, L.LBM_P_WALL_NODES, C.byref(v)) == 0 and v.value == 0.0
         assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 0.5) == L.LBM_E_ARG
-        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 2) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 3) == L.LBM_E_ARG
+        assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 2) == 0
+        assert lib.lbm_get_param(h, L.LBM_P_WALL_NODES, C.byref(v)) == 0 and v.value == 2.0
         assert lib.lbm_set_param(h, L.LBM_P_WALL_NODES, 1) == 0
         assert lib.lbm_get_param(h, L.LBM_P_WALL_NODES, C.byref(v)) == 0 and v.value == 1.0
         fw = np.zeros(10 * 8 * 4)

@@ -10,7 +10,9 @@ gpu_common (one ulp of the store at the result, the arithmetic bound and the
 oracle's own rounding), the first-layer records (density, velocity) within
 the observables' bound; the oracle continues from the GPU's rounded state,
 wall nodes included.  200 FP64 steps of the 32x16x16 channel from its
-Spalding state: max |du| / u_tau <= 1e-9.
+Spalding state: max |du| / u_tau <= 1e-9.  Mode 2 (the stress from the
+first layer's velocity of the same step) runs the same checks with WFB, the
+only boundary where the two modes differ.
 """
 import zlib
 
@@ -22,6 +24,8 @@ from gpu_common import MATH_EPS, STORES, one_step_tol, oracle_for, random_state,
 pytestmark = pytest.mark.gpu
 
 BCS = ("bb", "wfb", "freeslip")
+# (boundary, mode): the stress timing of mode 2 only matters for WFB
+BC_MODES = [("bb", 1), ("wfb", 1), ("freeslip", 1), ("wfb", 2)]
 GRIDS = [(4, 4, 4), (67, 5, 3), (64, 6, 3)]
 
 
@@ -34,10 +38,10 @@ def P():
     return P
 
 
-def _pair(P, orc, grid, store, bc, tau=0.52, cs=0.1, fx=2e-6, **kw):
+def _pair(P, orc, grid, store, bc, tau=0.52, cs=0.1, fx=2e-6, mode=1, **kw):
     nx, ny, nz = grid
-    ch = P.Channel(nx, ny, nz, tau, cs=cs, fx=fx, store=store, bc=bc, wall_nodes=True, **kw)
-    o = oracle_for(orc, grid, tau, cs, fx, bc, wall_nodes=True)
+    ch = P.Channel(nx, ny, nz, tau, cs=cs, fx=fx, store=store, bc=bc, wall_nodes=mode, **kw)
+    o = oracle_for(orc, grid, tau, cs, fx, bc, wall_nodes=mode)
     return ch, o
 
 
@@ -69,15 +73,15 @@ def _check(ch, o, orc, store, w, w_in):
 
 
 @pytest.mark.parametrize("grid", GRIDS)
-@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("bc,mode", BC_MODES)
 @pytest.mark.parametrize("store", STORES)
-def test_wall_nodes_one_and_two_steps(P, orc, store, bc, grid):
-    print("wall nodes: %s %s %s" % (store, bc, grid), flush=True)
-    rng = np.random.default_rng(zlib.crc32(repr(("nodes", store, bc, grid)).encode()))
+def test_wall_nodes_one_and_two_steps(P, orc, store, bc, mode, grid):
+    print("wall nodes: %s %s mode %d %s" % (store, bc, mode, grid), flush=True)
+    rng = np.random.default_rng(zlib.crc32(repr(("nodes", store, bc, grid) + ((mode,) if mode != 1 else ())).encode()))
     nx, ny, nz = grid
     h0 = random_state(orc, (nz, ny, nx), store, rng)
     w, w_in = weights(orc), _w_in(orc)
-    ch, o = _pair(P, orc, grid, store, bc)
+    ch, o = _pair(P, orc, grid, store, bc, mode=mode)
     ch.set_state(h0)
     o.set_state(h0 + w)
     _check(ch, o, orc, store, w, w_in)          # the wall nodes' start
@@ -88,15 +92,15 @@ def test_wall_nodes_one_and_two_steps(P, orc, store, bc, grid):
         _check(ch, o, orc, store, w, w_in)
 
 
-@pytest.mark.parametrize("bc", ("wfb", "bb"))
-def test_wall_nodes_fp64_200_steps(P, orc, bc):
+@pytest.mark.parametrize("bc,mode", (("wfb", 1), ("bb", 1), ("wfb", 2)))
+def test_wall_nodes_fp64_200_steps(P, orc, bc, mode):
     """The 32x15x16 channel (the wall nodes add a spacing: 2D = 16) from its
     Spalding state, 200 FP64 steps against the oracle."""
     from paper_2009_04352_amd import workloads as W
     p = W.params("c1")
     nx, _, nz = p["grid"]
     grid = (nx, 15, nz)
-    ch, o = _pair(P, orc, grid, "f64", bc, tau=p["tau0"], cs=p["cs"], fx=p["fx"])
+    ch, o = _pair(P, orc, grid, "f64", bc, tau=p["tau0"], cs=p["cs"], fx=p["fx"], mode=mode)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     o.init_spalding(p["u_tau"], p["noise"], p["seed"])
     ch.step(200)
@@ -111,8 +115,8 @@ def test_wall_nodes_fp64_200_steps(P, orc, bc):
     assert np.abs(fg - (fo - _w_in(orc))).max() <= 1e-12
 
 
-@pytest.mark.parametrize("store", ("f64", "f16"))
-def test_wall_nodes_graph_equals_eager(P, orc, store):
+@pytest.mark.parametrize("store,mode", (("f64", 1), ("f16", 1), ("f16", 2)))
+def test_wall_nodes_graph_equals_eager(P, orc, store, mode):
     """Captured graph chunks and eager launches give the same bits (the wall-node
     rings alternate with the kernel parity, not with the step count)."""
     from paper_2009_04352_amd import workloads as W
@@ -120,7 +124,7 @@ def test_wall_nodes_graph_equals_eager(P, orc, store):
     nx, ny, nz = 64, 15, 8
     outs = []
     for gs in (0, 16):
-        ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb", wall_nodes=True,
+        ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb", wall_nodes=mode,
                        graph_steps=gs)
         ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
         ch.step(37)
