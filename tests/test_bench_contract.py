@@ -22,8 +22,24 @@ def test_help_lists_the_options():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for opt in ("--steps", "--warmup", "--workload", "--stores", "--collision", "--van-driest"):
+    for opt in ("--steps", "--warmup", "--workload", "--stores", "--collision", "--van-driest", "--no-autotune",
+                "--tune-steps"):
         assert opt in r.stdout
+    for wl in ("c5", "c5s", "c3", "c2", "c4"):
+        assert wl in r.stdout
+
+
+def test_every_single_channel_workload_has_defaults_and_a_launch_table():
+    import bench
+    from paper_2009_04352_amd import workloads as W
+    for wl in ("c5", "c5s", "c3", "c2"):
+        store, steps, warmup = bench.DEFAULTS[wl]
+        assert store in W.WORKLOADS[wl]["stores"] or store == "f64"
+        assert steps >= 2 and warmup >= 0
+        for s in ("f64", "f32", "f16", "bf16"):
+            odd, even, v = W.launch_tiles(wl, s)
+            assert odd in (64, 128, 256, 512) and even in (64, 128, 256, 512) and v in (1, 2, 4)
+    assert bench.DEFAULTS["c5"][0] == "f64"          # the headline store
 
 
 def test_traffic_used_only_for_its_kernel_sources(tmp_path, monkeypatch):
