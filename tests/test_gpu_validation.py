@@ -4,8 +4,9 @@ on Table 1's A20 channel, run by validation.run on the GPU in FP64, against
 the oracle's run with the same parameters: 100 steps of development, then
 200 steps sampled every 20.  The sampled mean profile agrees to FP64
 round-off of 300 steps (|d<u_x>| <= 1e-9 u_tau), and so do the metrics
-computed from it.  Both wall pictures: halfway walls with WFB, and wall nodes
-with bounce-back (the paper's comparison path)."""
+computed from it.  Both wall pictures: halfway walls with WFB, wall nodes
+with bounce-back (the paper's comparison path), and wall nodes with WFB whose
+stress follows the first layer's velocity of the same step."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,7 @@ def P():
     return P
 
 
-@pytest.mark.parametrize("bc,wall_nodes", (("wfb", False), ("bb", True)))
+@pytest.mark.parametrize("bc,wall_nodes", (("wfb", 0), ("bb", 1), ("wfb", 2)))
 def test_a20_statistics_and_metrics_match_oracle(P, orc, bc, wall_nodes):
     from paper_2009_04352_amd import validation as V
     from paper_2009_04352_amd import workloads as W
