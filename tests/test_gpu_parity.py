@@ -15,6 +15,9 @@ pytestmark = pytest.mark.gpu
 
 BCS = ("bb", "wfb", "freeslip")
 GRIDS = [(4, 4, 4), (67, 5, 3)]
+# degenerate geometries: one cell per row (x-periodic onto itself), one
+# spanwise plane, and the thinnest channel (every row a wall row)
+DEGENERATE = [(1, 5, 3), (8, 4, 1), (67, 2, 3)]
 
 
 @pytest.fixture(scope="module")
@@ -35,13 +38,14 @@ def _pair(P, orc, grid, store, bc, tau=0.52, cs=0.1, fx=2e-6, tiles=None, graph_
     return ch, o
 
 
-@pytest.mark.parametrize("grid", GRIDS)
+@pytest.mark.parametrize("grid", GRIDS + DEGENERATE)
 @pytest.mark.parametrize("bc", BCS)
 @pytest.mark.parametrize("store", STORES)
 def test_one_and_two_steps(P, orc, store, bc, grid):
     """One step from a representable state: each h_a within one ulp of the store
     plus the arithmetic bound; the second step (even kernel) starts from the
     GPU's own state handed to the oracle."""
+    print("parity: %s %s %s" % (store, bc, grid), flush=True)
     rng = np.random.default_rng(zlib.crc32(repr((store, bc, grid)).encode()))
     nx, ny, nz = grid
     h0 = random_state(orc, (nz, ny, nx), store, rng)
