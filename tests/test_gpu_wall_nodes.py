@@ -27,6 +27,9 @@ BCS = ("bb", "wfb", "freeslip")
 # (boundary, mode): the stress timing of mode 2 only matters for WFB
 BC_MODES = [("bb", 1), ("wfb", 1), ("freeslip", 1), ("wfb", 2)]
 GRIDS = [(4, 4, 4), (67, 5, 3), (64, 6, 3)]
+# degenerate geometries: one cell per row with a single wall-adjacent row
+# pair, and one spanwise plane with every row next to a wall node
+DEGENERATE = [(1, 3, 2), (8, 2, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -72,7 +75,7 @@ def _check(ch, o, orc, store, w, w_in):
         np.testing.assert_allclose(a, b, rtol=0, atol=(1e-5 if store != "f64" else 1e-12) * scale)
 
 
-@pytest.mark.parametrize("grid", GRIDS)
+@pytest.mark.parametrize("grid", GRIDS + DEGENERATE)
 @pytest.mark.parametrize("bc,mode", BC_MODES)
 @pytest.mark.parametrize("store", STORES)
 def test_wall_nodes_one_and_two_steps(P, orc, store, bc, mode, grid):
