@@ -79,7 +79,8 @@ def _build(tmp, text):
 
 
 def _pins(so):
-    env = dict(os.environ, ORC_LIB_PATH=so, OMP_NUM_THREADS="4")
+    # four threads, or the share of the cores a pytest-xdist worker was given
+    env = dict(os.environ, ORC_LIB_PATH=so, OMP_NUM_THREADS=os.environ.get("OMP_NUM_THREADS", "4"))
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu", "-p", "no:cacheprovider"]
                           + PIN_TESTS, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
 
