@@ -37,11 +37,19 @@ def test_create_validates_arguments(L):
     bad = [((4, 1, 4), 0.6, 0.1, 0.41, 5.5, 0.0), ((0, 4, 4), 0.6, 0.1, 0.41, 5.5, 0.0),
            ((4, 4, 4), 0.5, 0.1, 0.41, 5.5, 0.0), ((4, 4, 4), float("nan"), 0.1, 0.41, 5.5, 0.0),
            ((4, 4, 4), 0.6, -0.1, 0.41, 5.5, 0.0), ((4, 4, 4), 0.6, 0.1, 0.0, 5.5, 0.0),
-           ((4, 4, 4), 0.6, 0.1, 0.41, 5.5, float("inf")), ((2048, 1024, 1024), 0.6, 0.1, 0.41, 5.5, 0.0)]
+           ((4, 4, 4), 0.6, 0.1, 0.41, 5.5, float("inf")), ((2048, 1024, 1024), 0.6, 0.1, 0.41, 5.5, 0.0),
+           ((1 << 15, 1 << 14, 1), 0.6, 0.1, 0.41, 5.5, 0.0)]   # a z-plane of 2^29 cells
     for g, *args in bad:
         assert lib.lbm_create(C.byref(L.Grid(*g)), *args, C.byref(h)) == L.LBM_E_ARG
         assert not h.value          # untouched on error
         assert lib.lbm_last_error(None)
+    # the largest sizes taken: just below 2^31 cells, and a z-plane just below 2^29
+    for g in ((2048, 1023, 1024), ((1 << 28) - 1, 2, 1)):
+        assert lib.lbm_create(C.byref(L.Grid(*g)), 0.6, 0.1, 0.41, 5.5, 0.0, C.byref(h)) == L.LBM_OK
+        nb = C.c_size_t(0)
+        assert lib.lbm_required_bytes(h, C.byref(nb)) == 0 and nb.value == 19 * int(np.prod(g)) * 8
+        lib.lbm_destroy(h)
+        h = C.c_void_p()
     assert lib.lbm_create(C.byref(L.Grid(4, 4, 4)), 0.6, 0.1, 0.41, 5.5, 1e-6, C.byref(h)) == L.LBM_OK
     try:
         nb = C.c_size_t(0)

@@ -20,9 +20,11 @@ def P():
     return P
 
 
-def _channel(P, store, named=False, workload="c3", collision="bgk", van_driest=0.0):
+def _channel(P, store, named=False, workload="c3", collision="bgk", van_driest=0.0, grid=None):
     from paper_2009_04352_amd import workloads as W
     p = W.params(workload, named_tau=named)
+    if grid is not None:
+        p = dict(p, grid=grid)
     ch = P.Channel(*p["grid"], p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
                    tiles=W.launch_tiles(workload, store, collision), collision=collision, van_driest=van_driest)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
@@ -64,10 +66,29 @@ def test_two_steps_sampled(P, orc, workload, store, collision, named):
     the GPU's own step-1 state of the cells around them, with the one-step
     tolerance (one ulp of the store at the result, the arithmetic bound and the
     oracle's own rounding)."""
+    _two_steps_sampled(P, orc, workload, store, collision, named)
+
+
+# The largest grid the library takes is just below 2^31 cells: 2048 x 1023 x
+# 1024 (99.9 % of the limit; the odd row count leaves a last brick of 7 rows)
+# in the large channel's parameters and launch shapes, in the formats whose
+# populations fit in one GPU's memory at that size (FP16 81.5 GB, FP32
+# 163 GB; FP64 would need 326 GB).
+LARGEST = (2048, 1023, 1024)
+
+
+@pytest.mark.parametrize("store", ("f16", "f32"))
+def test_largest_grid_two_steps_sampled(P, orc, store):
+    """The two sampled steps of the test above on the largest accepted grid."""
+    assert np.prod(LARGEST) < 2 ** 31 and np.prod(LARGEST) > 0.999 * 2 ** 31
+    _two_steps_sampled(P, orc, "c5", store, "bgk", False, grid=LARGEST)
+
+
+def _two_steps_sampled(P, orc, workload, store, collision, named, grid=None):
     from paper_2009_04352_amd import workloads as W
-    print("full-size sampled steps: %s %s %s named=%s" % (workload, store, collision, named), flush=True)
+    print("full-size sampled steps: %s %s %s named=%s grid=%s" % (workload, store, collision, named, grid), flush=True)
     vd = 26.0 if collision == "mrt" else 0.0
-    ch, p = _channel(P, store, named=named, workload=workload, collision=collision, van_driest=vd)
+    ch, p = _channel(P, store, named=named, workload=workload, collision=collision, van_driest=vd, grid=grid)
     cells = W.sample_cells(p["grid"], 3000, seed=1)
     nx, ny, nz = p["grid"]
     op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB,
