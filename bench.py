@@ -25,6 +25,10 @@ device) is compared with the FP64 run's.  Prints one JSON line.
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c5|c5s|c3|c2|c4]
                 [--stores f64,f32,f16,bf16] [--no-cpu-baseline]
                 [--collision bgk|mrt] [--van-driest A+]
+                [--no-autotune] [--tune-steps N]
+Before each store's run the library's autotuner picks the launch shapes
+(timed on the run's own allocation, N steps per candidate); --no-autotune
+keeps the fixed launch table of workloads.py.
 The headline line is the BGK step (the default); --collision mrt with
 --van-driest 26 measures the paper's LES collision on the same workload.
 """
@@ -349,7 +353,8 @@ def bench_ensemble(P, W, args, copy_gbs):
     store = W.ENSEMBLE["store"]
     n = sum(e["nx"] * e["ny"] * e["nz"] for e in ens)
     b = P.Batch(ens, store=store, graph_steps=0, **collision_kw(args))
-    tiles = b.autotune(steps=6)
+    tiles = None if args.no_autotune else b.autotune(steps=6)   # None: the library's default shapes
+    launch = list(tiles) if tiles else "library default"
     b.init_spalding([e["u_tau"] for e in ens], 0.05, seeds=[e["seed"] for e in ens])
     total_ms, odd_ms, even_ms, per = timed_steps(torch, b.step, b.stream, args.steps, args.warmup, 1)
     status, first, inst = b.sync()
@@ -371,10 +376,10 @@ def bench_ensemble(P, W, args, copy_gbs):
           % (r["mlups"], graph_mlups, odd_ms, even_ms, tiles), file=sys.stderr, flush=True)
     d = store_record(r, store, n, copy_gbs)
     d["graph_mlups"] = graph_mlups
-    d["launch"] = list(tiles)
+    d["launch"] = launch
     config = {"workload": "c4: %s; %d steps timed after %d warm-up steps" % (W.ENSEMBLE["desc"], args.steps,
                                                                               args.warmup),
-              "instances": len(ens), "cells": n, "store": store, "launch": list(tiles), "parallelism": "single GPU",
+              "instances": len(ens), "cells": n, "store": store, "launch": launch, "parallelism": "single GPU",
               "timed_steps": args.steps}
     b.close()
     b2.close()
