@@ -50,9 +50,11 @@ FULL = [("c5", "f64", "bgk", False), ("c5", "f32", "bgk", False), ("c5", "f16", 
 
 
 # the MRT line of the benchmark (--collision mrt --van-driest 26) on the
-# 512 x 128 x 256 channel
+# 512 x 128 x 256 channel, and on the 2048 x 512 x 1024 channel (where the
+# 2-byte odd step walks rows at 2 cells per thread)
 FULL_MRT = [("c3", "f64", "mrt", False), ("c3", "f32", "mrt", False), ("c3", "f16", "mrt", False),
-            ("c3", "bf16", "mrt", False)]
+            ("c3", "bf16", "mrt", False), ("c5", "f64", "mrt", False), ("c5", "f16", "mrt", False),
+            ("c5", "bf16", "mrt", False)]
 
 
 @pytest.mark.parametrize("workload,store,collision,named", FULL + FULL_MRT)
