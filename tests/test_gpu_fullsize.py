@@ -142,3 +142,49 @@ def test_c3_fp64_conservation(P):
     assert abs(m1 - m0) <= 1e-12 * m0
     assert ch.sync()[0] == 0
     _release(ch)
+
+
+@pytest.mark.parametrize("bc,mode", (("wfb", 1), ("wfb", 2), ("bb", 1)))
+def test_c3_fp64_wall_nodes_budget(P, orc, bc, mode):
+    """Wall nodes (Sec. 2.1-2.2) at full size in the benchmark's FP64 launch
+    shape: per step the x-momentum of fluid plus wall nodes changes by N Fx
+    plus the stress of the step's wall-node collisions (WFB: from the record
+    before the step, or with the same step's velocity from the one the step
+    computed; bounce-back: the momentum exchange of the populations waiting
+    at the nodes), and their mass is conserved."""
+    from paper_2009_04352_amd import workloads as W
+    print("full-size wall nodes: c3 f64 %s mode %d" % (bc, mode), flush=True)
+    p = W.params("c3")
+    nx, ny, nz = p["grid"]
+    ch = P.Channel(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], store="f64", bc=bc,
+                   tiles=W.launch_tiles("c3", "f64"), wall_nodes=mode)
+    ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
+    ex = orc.tables()[0][:, 0].astype(np.float64)
+    ex_in = np.array([[ex[a] for a in orc.IN_W[k]] for k in (0, 1)])
+
+    def totals():
+        # h = f - w: sum_a w_a and sum_a e_ax w_a are constants (zero for x-momentum)
+        h = ch.get_state().reshape(19, -1)
+        fw, _ = ch.wall_nodes()
+        fw = fw.reshape(2, 5, -1)
+        m = h.sum() + fw.sum()
+        px = float(ex @ h.sum(axis=1)) + float((ex_in * fw.sum(axis=2)).sum())
+        return m, px, np.abs(h).sum()
+
+    n = nx * ny * nz
+    m0, _, _ = totals()
+    for _ in range(2):
+        _, p0, habs = totals()
+        taux = ch.wall_shear()[0]
+        ch.step(1)
+        if mode == 2 and bc == "wfb":
+            taux = ch.wall_shear()[0]   # the stress of the step's own record
+        _, p1, _ = totals()
+        want = n * p["fx"] + taux.sum()
+        # pairwise sums over 3e8 terms: a few ulp of the summed magnitudes
+        assert abs((p1 - p0) - want) <= 1e-9 * abs(want) + 1e-14 * habs, ((p1 - p0), want)
+    ch.step(20)
+    m1, _, habs = totals()
+    assert abs(m1 - m0) <= 1e-14 * habs, (m1 - m0)
+    assert ch.sync()[0] == 0
+    _release(ch)
