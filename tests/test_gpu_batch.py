@@ -123,3 +123,32 @@ def test_batch_autotune_picks_valid_shapes(P):
         out.append([b.instance(i).get_state() for i in range(len(specs))])
     for a, c in zip(*out):
         np.testing.assert_array_equal(a, c)
+
+
+def test_ensemble_in_its_benchmark_shapes_matches_oracle(P, orc):
+    """The 64-channel ensemble in the launch shapes the benchmark's tuner picks
+    for it: an odd and an even step of four instances (WFB and bounce-back
+    channels of different sizes) against the oracle continued from the GPU's
+    state, to the one-step tolerance."""
+    from paper_2009_04352_amd import workloads as W
+    ens = W.ensemble()
+    b = P.Batch(ens, store="f32", graph_steps=0)
+    tiles = b.autotune(steps=6)
+    print("ensemble in tuned shapes", tiles, flush=True)
+    b.init_spalding([e["u_tau"] for e in ens], 0.05, seeds=[e["seed"] for e in ens])
+    b.step(1)
+    w = weights(orc)
+    sel = (0, 17, 42, 63)
+    for _ in range(2):
+        prev = {i: b.instance(i).get_state() for i in sel}
+        b.step(1)
+        for i in sel:
+            e = ens[i]
+            o = oracle_for(orc, (e["nx"], e["ny"], e["nz"]), e["tau"], e["cs"], e["fx"], e["bc"])
+            o.set_state(prev[i] + w)
+            assert o.step(1) == 0
+            want = o.state() - w
+            got = b.instance(i).get_state()
+            assert np.all(np.abs(got - want) <= one_step_tol("f32", want, w)), (i, np.abs(got - want).max())
+    assert b.sync()[0] == 0
+    b.close()
