@@ -20,13 +20,15 @@ def P():
     return P
 
 
-def _channel(P, store, named=False, workload="c3", collision="bgk", van_driest=0.0, grid=None):
+def _channel(P, store, named=False, workload="c3", collision="bgk", van_driest=0.0, grid=None, tune=False):
     from paper_2009_04352_amd import workloads as W
     p = W.params(workload, named_tau=named)
     if grid is not None:
         p = dict(p, grid=grid)
     ch = P.Channel(*p["grid"], p["tau0"], cs=p["cs"], fx=p["fx"], store=store, bc="wfb",
                    tiles=W.launch_tiles(workload, store, collision), collision=collision, van_driest=van_driest)
+    if tune:   # as the benchmark does: the tuner searches from the table before the state is set
+        print("tuned launch:", ch.autotune(steps=4), flush=True)
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])
     return ch, p
 
@@ -71,6 +73,14 @@ def test_two_steps_sampled(P, orc, workload, store, collision, named):
     _two_steps_sampled(P, orc, workload, store, collision, named)
 
 
+@pytest.mark.parametrize("store", ("f64", "f32", "f16", "bf16"))
+def test_two_steps_sampled_in_tuned_shapes(P, orc, store):
+    """The two sampled steps on the 2048 x 512 x 1024 channel in the shapes the
+    benchmark's autotuner picks on this device (block sizes, cells per thread,
+    rows per brick, launch order, odd-step mode)."""
+    _two_steps_sampled(P, orc, "c5", store, "bgk", False, tune=True)
+
+
 # The largest grid the library takes is just below 2^31 cells: 2048 x 1023 x
 # 1024 (99.9 % of the limit; the odd row count leaves a last brick of 7 rows)
 # in the large channel's parameters and launch shapes, in the formats whose
@@ -86,11 +96,13 @@ def test_largest_grid_two_steps_sampled(P, orc, store):
     _two_steps_sampled(P, orc, "c5", store, "bgk", False, grid=LARGEST)
 
 
-def _two_steps_sampled(P, orc, workload, store, collision, named, grid=None):
+def _two_steps_sampled(P, orc, workload, store, collision, named, grid=None, tune=False):
     from paper_2009_04352_amd import workloads as W
-    print("full-size sampled steps: %s %s %s named=%s grid=%s" % (workload, store, collision, named, grid), flush=True)
+    print("full-size sampled steps: %s %s %s named=%s grid=%s tuned=%s" % (workload, store, collision, named, grid,
+                                                                         tune), flush=True)
     vd = 26.0 if collision == "mrt" else 0.0
-    ch, p = _channel(P, store, named=named, workload=workload, collision=collision, van_driest=vd, grid=grid)
+    ch, p = _channel(P, store, named=named, workload=workload, collision=collision, van_driest=vd, grid=grid,
+                     tune=tune)
     cells = W.sample_cells(p["grid"], 3000, seed=1)
     nx, ny, nz = p["grid"]
     op = orc.make_params(nx, ny, nz, p["tau0"], cs=p["cs"], fx=p["fx"], bc=orc.WFB,
