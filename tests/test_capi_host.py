@@ -244,3 +244,23 @@ def test_yplus_pdf_noalloc_argument_checks(L):
     finally:
         lib.lbm_destroy(big)
         lib.lbm_destroy(small)
+
+
+def test_empty_inputs_are_no_ops_or_refused(L):
+    """Zero-sized calls that need no device return at once (no device call is
+    made, so they run without a GPU); an empty batch is refused."""
+    lib = L.lib()
+    assert lib.lbm_device_wall_utau(0, None, 1.0, 1e-3, 0.41, 5.5, 1e-14, 50, None, None) == L.LBM_OK
+    assert lib.lbm_device_wall_utau(-1, None, 1.0, 1e-3, 0.41, 5.5, 1e-14, 50, None, None) == L.LBM_E_ARG
+    assert lib.lbm_codec_roundtrip(2, 0, None, None) == L.LBM_OK
+    assert lib.lbm_codec_roundtrip(2, -1, None, None) == L.LBM_E_ARG
+    dummy = C.c_void_p(16)   # never dereferenced: zero bytes
+    assert lib.lbm_copy_probe(dummy, dummy, 0, None) == L.LBM_OK
+    assert lib.lbm_copy_probe(dummy, dummy, 8, None) == L.LBM_E_ARG
+    assert lib.lbm_copy_probe(None, dummy, 0, None) == L.LBM_E_ARG
+    b = C.c_void_p()
+    g = L.Grid(8, 4, 2)
+    one = (C.c_double * 1)(0.6)
+    bc = (C.c_int32 * 1)(1)
+    assert lib.lbm_batch_create(0, C.byref(g), one, one, one, bc, 0.41, 5.5, C.byref(b)) == L.LBM_E_ARG
+    assert not b.value

@@ -305,3 +305,29 @@ def test_batch_odd_step_by_rows(P):
         ch.init_spalding([1e-2, 2e-2][i], 0.05, 3 + i)
         ch.step(5)
         assert np.array_equal(b.instance(i).get_state(), ch.get_state()), i
+
+
+@pytest.mark.parametrize("graph_steps", (0, 8))
+def test_empty_calls_leave_the_state_alone(P, orc, graph_steps):
+    """Zero steps (single channel and batch, eager and in graphs) and an empty
+    cell list are no-ops: the state, the step count and the status stay as
+    they were."""
+    grid = (64, 6, 3)
+    h0 = _state(orc, grid, "f32", 7)
+    ch = P.Channel(*grid, 0.52, cs=0.1, fx=1e-6, store="f32", bc="wfb", graph_steps=graph_steps)
+    ch.set_state(h0)
+    ch.step(0)
+    assert ch.steps == 0 and ch.sync()[0] == 0
+    np.testing.assert_array_equal(ch.get_state(), h0)
+    assert ch.get_state_cells(np.zeros(0, dtype=np.int64)).shape == (0, 19)
+    ch.step(3)
+    h3 = ch.get_state()
+    ch.step(0)
+    assert ch.steps == 3
+    np.testing.assert_array_equal(ch.get_state(), h3)
+    b = P.Batch([dict(nx=32, ny=5, nz=3, tau=0.51, cs=0.1, fx=1e-6, bc="wfb")], store="f32", graph_steps=graph_steps)
+    b.init_spalding([0.02], 0.05, seeds=[1])
+    s0 = b.instance(0).get_state()
+    b.step(0)
+    np.testing.assert_array_equal(b.instance(0).get_state(), s0)
+    assert b.sync()[0] == 0
