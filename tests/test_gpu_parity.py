@@ -279,3 +279,31 @@ def test_boundary_switch_after_odd_step(P, orc):
         ch.step(2)
         o.step(2)
         np.testing.assert_allclose(ch.get_state(), o.state() - w, rtol=0, atol=2e-15)
+
+
+# (boundary, wall placement): halfway walls, wall nodes, and wall nodes with
+# the same step's stress (which only differs from the previous step's with WFB)
+REST_CASES = [(bc, m) for bc in BCS for m in (0, 1)] + [("wfb", 2)]
+
+
+@pytest.mark.parametrize("bc,wall_nodes", REST_CASES)
+@pytest.mark.parametrize("store", STORES)
+def test_fluid_at_rest_stays_at_rest(P, store, bc, wall_nodes):
+    """The degenerate flow: no force and f = f_eq(1, 0) everywhere.  Every
+    population stays exactly at its weight (h = 0 in every format), the wall
+    function sees U = 0 and returns u_tau = 0 without a Newton step, and every
+    wall stress is exactly zero, for each boundary and wall placement."""
+    from paper_2009_04352_amd import _lib as L
+    nx, ny, nz = 24, 5, 3
+    ch = P.Channel(nx, ny, nz, 0.52, cs=0.1, fx=0.0, store=store, bc=bc, wall_nodes=wall_nodes)
+    # a cap of one iteration: any solve that needed a step would be reported
+    ch.set_param(L.LBM_P_NEWTON_MAXIT, 1)
+    ch.init_moments(np.ones((nz, ny, nx)), np.zeros((3, nz, ny, nx)))
+    ch.step(7)
+    assert ch.sync()[0] == 0
+    assert not np.any(ch.get_state())
+    for a in ch.wall_shear()[:3]:
+        assert not np.any(a)
+    if wall_nodes:
+        fw, rec = ch.wall_nodes()
+        assert not np.any(fw) and not np.any(rec[..., 1:])
