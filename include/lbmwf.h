@@ -73,7 +73,7 @@ extern "C" {
 #define LBM_P_TAU0 10         /* read-only: molecular relaxation time */
 #define LBM_P_FX 11           /* body force density along x; settable at any time */
 #define LBM_P_CS 12           /* Smagorinsky constant; settable at any time */
-#define LBM_P_VECTOR 13       /* cells per thread: 0 = auto (groups of 8 bytes), or 1, 2, 4 (group <= 8 bytes, divides nx) */
+#define LBM_P_VECTOR 13       /* cells per thread: 0 = auto (FP32: 1; otherwise groups of 8 bytes), or 1, 2, 4 (group <= 8 bytes, divides nx) */
 #define LBM_P_BRICK 14        /* rows per brick of the device layout: 0 = auto (8; capped at ny).  Used only
                                * when every block of both step kernels holds a single row, otherwise the
                                * plain order (brick = ny).  Fixed once the state is initialised; reading it
@@ -350,7 +350,7 @@ int lbm_batch_create(int32_t n, const lbm_grid* grids, const double* tau, const 
                      const int32_t* bc, double kappa, double B, lbm_batch** out);
 void lbm_batch_destroy(lbm_batch* batch);
 /* Keys LBM_P_STORE (before binding), LBM_P_TILE_ODD, LBM_P_TILE_EVEN,
- * LBM_P_VECTOR (0 = the widest group every instance allows), LBM_P_XCD_REMAP,
+ * LBM_P_VECTOR (0 = automatic: FP32 one cell per thread, otherwise the widest group every instance allows), LBM_P_XCD_REMAP,
  * LBM_P_GRAPH_STEPS, LBM_P_SPREAD, LBM_P_ODD_ROWS (walks rows only if every instance's rows
  * qualify), and LBM_P_Y1 / LBM_P_NEWTON_TOL / LBM_P_NEWTON_MAXIT /
  * LBM_P_BRICK (before initialisation) applied to every instance.  Block
