@@ -153,17 +153,20 @@ def run(workload="c3", store="f16", bc="wfb", collision="mrt", van_driest=26.0, 
 
 
 def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="c3")
-    ap.add_argument("--store", default="f16")
-    ap.add_argument("--bc", default="wfb")
-    ap.add_argument("--collision", default="mrt")
-    ap.add_argument("--van-driest", type=float, default=26.0)
-    ap.add_argument("--develop", type=int, default=400000)
-    ap.add_argument("--sample", type=int, default=400000)
-    ap.add_argument("--stats-every", type=int, default=20)
-    ap.add_argument("--report-every", type=int, default=50000)
-    ap.add_argument("--mass-steps", type=int, default=0)
+    ap = argparse.ArgumentParser(description="Wall-law validation run: develop the channel, sample plane "
+                                 "statistics, report the Eq. 19 errors against Spalding's law and the Eq. 20 "
+                                 "intercept as one JSON record.")
+    ap.add_argument("--workload", default="c3", help="a Table 1 case (A20, A40, B40, B80) or a benchmark workload")
+    ap.add_argument("--store", default="f16", help="population store: f64, f32, f16 or bf16")
+    ap.add_argument("--bc", default="wfb", help="wall boundary: wfb, bb or freeslip")
+    ap.add_argument("--collision", default="mrt", help="bgk or mrt")
+    ap.add_argument("--van-driest", type=float, default=26.0, help="van Driest A+ (0: no damping)")
+    ap.add_argument("--develop", type=int, default=400000, help="steps of development before sampling")
+    ap.add_argument("--sample", type=int, default=400000, help="steps over which statistics are sampled")
+    ap.add_argument("--stats-every", type=int, default=20, help="sample the plane statistics every k steps")
+    ap.add_argument("--report-every", type=int, default=50000, help="progress line every k steps")
+    ap.add_argument("--mass-steps", type=int, default=0, help="also run the Appendix B mass check over this many "
+                                                              "steps (0: off)")
     ap.add_argument("--mrt-rates", default="", help="e.g. s_e=1.19,s_q=1.2 (MRT rates to override)")
     ap.add_argument("--wall-nodes", type=int, nargs="?", const=1, default=0, choices=(0, 1, 2),
                     help="the wall grid as a lattice node (LBM_P_WALL_NODES): 1 = stress of the previous step, "
