@@ -257,6 +257,20 @@ void drop_graphs(lbm_ctx* c)
     c->graphs.clear();
 }
 
+// Creates the tuners' three timing events; on a failure destroys those made.
+bool create_events(hipEvent_t (&ev)[3])
+{
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return false;
+        }
+    }
+    return true;
+}
+
 // Whether the odd step walks rows (one wavefront per row) for these shapes.
 // Automatic (mode 1): for 2-byte stores whose rows are longer than an odd-step
 // block, where it beat row segments exchanging through LDS (5 % on the
@@ -1530,7 +1544,7 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
         const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
         int state_brick = -1;
         hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        for (auto& e : ev) LBM_HIP(c, hipEventCreate(&e));
+        if (!create_events(ev)) return fail(c, LBM_E_DEVICE, "autotune: event creation failed");
         const Shapes start = shapes_of(c);
         int st = LBM_OK;
         hipError_t err = hipSuccess;
@@ -2201,8 +2215,8 @@ int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
         for (lbm_ctx* c : b->inst) c->initialized = false;  // timing states: layouts follow the candidates
         const int tcand[4] = {64, 128, 256, 512};
         const int vcand[3] = {1, 2, 4};
-        hipEvent_t ev[3];
-        for (auto& e : ev) LBM_BHIP(b, hipEventCreate(&e));
+        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+        if (!create_events(ev)) return bfail(b, LBM_E_DEVICE, "autotune: event creation failed");
         hipError_t err = hipSuccess;
         // mean odd and even step times (ms) of the current settings: one warm-up
         // pair, then steps / 2 timed pairs
