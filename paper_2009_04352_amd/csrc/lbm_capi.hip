@@ -257,19 +257,25 @@ void drop_graphs(lbm_ctx* c)
     c->graphs.clear();
 }
 
-// Creates the tuners' three timing events; on a failure destroys those made.
-bool create_events(hipEvent_t (&ev)[3])
-{
-    for (auto& e : ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            e = nullptr;
-            for (auto& f : ev)
-                if (f) (void)hipEventDestroy(f);
-            return false;
-        }
+// The tuners' three timing events, destroyed on every way out of the tuner
+// (error returns and host exceptions included).
+struct TimingEvents {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool create()
+    {
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+                return false;
+            }
+        return true;
     }
-    return true;
-}
+    ~TimingEvents()
+    {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
 
 // Whether the odd step walks rows (one wavefront per row) for these shapes.
 // Automatic (mode 1): for 2-byte stores whose rows are longer than an odd-step
@@ -874,9 +880,9 @@ int lbm_init_moments(lbm_ctx* c, const double* rho, const double* u)
         }
         DeviceGuard dg(c->dev);
         const long long chunk = std::min<long long>(c->n, 1ll << 24);
+        std::vector<double> stage((size_t)chunk * 4);   // host staging first: a throw leaks no device memory
         double* tmp = nullptr;
         LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 4 * sizeof(double)));
-        std::vector<double> stage((size_t)chunk * 4);
         c->initialized = false;  // the layout is chosen afresh
         c->brick = brick_for_tiles(c);
         int st = LBM_OK;
@@ -915,9 +921,9 @@ int lbm_set_state(lbm_ctx* c, const double* in, int64_t steps)
         if (steps < 0) return fail(c, LBM_E_ARG, "steps must be >= 0");
         DeviceGuard dg(c->dev);
         const long long chunk = std::min<long long>(c->n, 1ll << 24);
+        std::vector<double> stage((size_t)chunk * 19);  // host staging first: a throw leaks no device memory
         double* tmp = nullptr;
         LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
-        std::vector<double> stage((size_t)chunk * 19);
         c->initialized = false;  // the layout is chosen afresh
         c->brick = brick_for_tiles(c);
         int st = LBM_OK;
@@ -957,6 +963,8 @@ static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, dou
         for (long long i = 0; i < count; ++i)
             if (cells[i] < 0 || cells[i] >= c->n) return fail(c, LBM_E_ARG, "cell index out of range");
     const long long chunk = std::min<long long>(std::max<long long>(count, 1), 1ll << 24);
+    std::vector<double> stage((size_t)chunk * 19);  // host buffers first: a throw leaks no device memory
+    std::vector<double> result((size_t)count * 19);
     double* tmp = nullptr;
     long long* dcells = nullptr;
     LBM_HIP(c, hipMalloc((void**)&tmp, (size_t)chunk * 19 * sizeof(double)));
@@ -964,8 +972,6 @@ static int get_state_impl(lbm_ctx* c, long long count, const int64_t* cells, dou
         (void)hipFree(tmp);
         return fail(c, LBM_E_DEVICE, "get_state: allocation failed");
     }
-    std::vector<double> stage((size_t)chunk * 19);
-    std::vector<double> result((size_t)count * 19);
     for (long long first = 0; first < count && st == LBM_OK; first += chunk) {
         const long long cnt = std::min(chunk, count - first);
         hipError_t e = hipSuccess;
@@ -1125,6 +1131,9 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
         for (long long i = 0; i < count; ++i)
             if (cells[i] < 0 || cells[i] >= c->n) return fail(c, LBM_E_ARG, "cell index out of range");
     const long long chunk = std::min<long long>(std::max<long long>(count, 1), 1ll << 24);
+    std::vector<double> result((size_t)count * 4);  // host buffers first: a throw leaks no device memory
+    std::vector<int> itres(iters ? (size_t)count : 0);
+    std::vector<double> dmres(dmass ? (size_t)count * 2 : 0);
     double* tmp = nullptr;
     long long* dcells = nullptr;
     int* dit = nullptr;
@@ -1134,9 +1143,6 @@ static int observe_impl(lbm_ctx* c, int mode, long long count, const int64_t* ce
     if (e == hipSuccess && iters) e = hipMalloc((void**)&dit, (size_t)chunk * sizeof(int));
     double* ddm = nullptr;
     if (e == hipSuccess && dmass) e = hipMalloc((void**)&ddm, (size_t)chunk * 2 * sizeof(double));
-    std::vector<double> result((size_t)count * 4);
-    std::vector<int> itres(iters ? (size_t)count : 0);
-    std::vector<double> dmres(dmass ? (size_t)count * 2 : 0);
     for (long long first = 0; first < count && e == hipSuccess; first += chunk) {
         const long long cnt = std::min(chunk, count - first);
         ObsArgs a = obs_args(c);
@@ -1304,13 +1310,13 @@ int lbm_wall_yplus_pdf(lbm_ctx* c, int32_t nbins, double lo, double hi, int64_t*
         if ((st = fix_layout(c)) != LBM_OK) return st;
         if ((st = sync_check(c)) != LBM_OK) return st;
         const long long m = 2ll * c->nx * c->nz;
+        std::vector<unsigned long long> hc((size_t)nbins + 2);  // host buffer first: a throw leaks no device memory
         double* ut = nullptr;
         double* ms = nullptr;
         unsigned long long* dcnt = nullptr;
         hipError_t e = hipMalloc((void**)&ut, (size_t)m * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void**)&ms, 2 * sizeof(double));
         if (e == hipSuccess) e = hipMalloc((void**)&dcnt, (size_t)(nbins + 2) * sizeof(unsigned long long));
-        std::vector<unsigned long long> hc((size_t)nbins + 2);
         double hms[2] = {0.0, 0.0};
         if (e == hipSuccess) e = enqueue_yplus_pdf(c, nbins, lo, hi, ut, ms, dcnt);
         if (e == hipSuccess) e = hipMemcpyAsync(hms, ms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
@@ -1543,8 +1549,9 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
         // written again whenever a candidate's rows per brick change the layout
         const double ut = std::sqrt(std::fabs(c->fx) * c->ny * 0.5);
         int state_brick = -1;
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (!create_events(ev)) return fail(c, LBM_E_DEVICE, "autotune: event creation failed");
+        TimingEvents tev;
+        if (!tev.create()) return fail(c, LBM_E_DEVICE, "autotune: event creation failed");
+        hipEvent_t* ev = tev.ev;
         const Shapes start = shapes_of(c);
         int st = LBM_OK;
         hipError_t err = hipSuccess;
@@ -1645,7 +1652,6 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
             }
             if (!changed) break;
         }
-        for (auto& e : ev) (void)hipEventDestroy(e);
         apply_shapes(c, ok ? best : start);
         c->initialized = false;
         drop_graphs(c);
@@ -2215,8 +2221,9 @@ int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
         for (lbm_ctx* c : b->inst) c->initialized = false;  // timing states: layouts follow the candidates
         const int tcand[4] = {64, 128, 256, 512};
         const int vcand[3] = {1, 2, 4};
-        hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-        if (!create_events(ev)) return bfail(b, LBM_E_DEVICE, "autotune: event creation failed");
+        TimingEvents tev;
+        if (!tev.create()) return bfail(b, LBM_E_DEVICE, "autotune: event creation failed");
+        hipEvent_t* ev = tev.ev;
         hipError_t err = hipSuccess;
         // mean odd and even step times (ms) of the current settings: one warm-up
         // pair, then steps / 2 timed pairs
@@ -2285,7 +2292,6 @@ int lbm_batch_autotune(lbm_batch* b, int steps, int32_t* tiles)
                 }
             }
         }
-        for (auto& e : ev) (void)hipEventDestroy(e);
         b->vw_req = ok ? bv : save_req;
         b->odd_rows = ok ? brows : save_rows;
         b->tile_odd = bo;
