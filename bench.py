@@ -141,7 +141,7 @@ def run_store(P, W, name, store, bc, steps, warmup, coll, acc_steps, ref, tune_s
         launch = dict(tile_odd=int(ch.get_param(L.LBM_P_TILE_ODD)), tile_even=int(ch.get_param(L.LBM_P_TILE_EVEN)),
                       vector=int(ch.get_param(L.LBM_P_VECTOR)), brick=int(ch.get_param(L.LBM_P_BRICK)),
                       spread=int(ch.get_param(L.LBM_P_SPREAD)), odd_rows=int(ch.get_param(L.LBM_P_ODD_BY_ROWS)),
-                      cached=0)
+                      cached=0, xcd_chunk=int(ch.get_param(L.LBM_P_XCD_CHUNK)))
     launch.update(source="autotuned from the measured table" if tune_steps > 0 else "measured table",
                   table=list(table), tune_seconds=round(tune_s, 2))
     ch.init_spalding(p["u_tau"], p["noise"], p["seed"])

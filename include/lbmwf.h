@@ -124,6 +124,9 @@ extern "C" {
                                * layer's density and velocity of the same step (the moments of what it gathers
                                * in that step), the wall records then those of the latest wall-node collision.
                                * Not for batches. */
+#define LBM_P_XCD_CHUNK 27    /* with LBM_P_XCD_REMAP = 1: each of the 8 XCDs takes chunks of 2^c consecutive
+                               * tiles in turn, c in [0, 12] (default 5; 0 = plain round robin).  Results do
+                               * not depend on it.  Not for batches (their chunk is 2^5). */
 
 typedef struct lbm_ctx lbm_ctx;
 
@@ -292,8 +295,9 @@ int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
  * storage: the block sizes of the odd and even kernels (64, 128, 256, 512),
  * the cells per thread (1, 2, 4 where the store and nx allow), the rows per
  * brick of the layout (4, 8, 16, 32), the launch order (LBM_P_SPREAD: memory
- * order or chunks of 2^5, 2^7, 2^9 tiles) and whether the odd step walks
- * rows (LBM_P_ODD_ROWS).  Coordinate descent from the context's current
+ * order or chunks of 2^5, 2^7, 2^9 tiles), whether the odd step walks
+ * rows (LBM_P_ODD_ROWS) and the XCD chunk (LBM_P_XCD_CHUNK: 2^5, 2^7, 2^9
+ * tiles).  Coordinate descent from the context's current
  * shapes, one setting at a time, each candidate timed over `steps` steps
  * (>= 2) after one warm-up pair; a change is kept only when it is more than
  * 1 % faster (the odd-step settings decided by the odd kernel's time, the even
@@ -303,10 +307,10 @@ int lbm_stats_get(lbm_ctx* ctx, double* out, int64_t* nsamples);
  * None of these settings changes a result bit.  Valid only before the state
  * is initialised (it writes the initial profile the body force implies);
  * afterwards the state is undefined until lbm_init_* / lbm_set_state.
- * Synchronises.  choice (may be NULL) receives seven values: the odd and even
+ * Synchronises.  choice (may be NULL) receives eight values: the odd and even
  * block sizes, the cells per thread, the rows per brick in use, the launch
- * order's chunk log2 (0: memory order), 1 if the odd step walks rows, and 1
- * if the result came from the cache. */
+ * order's chunk log2 (0: memory order), 1 if the odd step walks rows, 1 if
+ * the result came from the cache, and the XCD chunk log2. */
 int lbm_autotune(lbm_ctx* ctx, int steps, int32_t* choice);
 
 /* Spalding's law inverted on the host (Eq. 16): u+ for a given y+ >= 0. */

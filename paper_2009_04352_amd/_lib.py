@@ -17,7 +17,7 @@ LBM_STORE_F64, LBM_STORE_F32, LBM_STORE_F16, LBM_STORE_BF16 = 0, 1, 2, 3
  LBM_P_TILE_EVEN, LBM_P_XCD_REMAP, LBM_P_GRAPH_STEPS, LBM_P_BC, LBM_P_TAU0, LBM_P_FX, LBM_P_CS,
  LBM_P_VECTOR, LBM_P_BRICK, LBM_P_ODD_ROWS, LBM_P_SPREAD, LBM_P_ODD_BY_ROWS, LBM_P_COLLISION,
  LBM_P_MRT_S_E, LBM_P_MRT_S_EPS, LBM_P_MRT_S_Q, LBM_P_MRT_S_PI, LBM_P_MRT_S_M, LBM_P_VD_APLUS,
- LBM_P_VD_UTAU, LBM_P_WALL_NODES) = range(27)
+ LBM_P_VD_UTAU, LBM_P_WALL_NODES, LBM_P_XCD_CHUNK) = range(28)
 LBM_BGK, LBM_MRT = 0, 1
 
 # every symbol the header declares, with (restype, argtypes)

@@ -156,10 +156,11 @@ class Channel:
         a dict: tile_odd, tile_even, vector (cells per thread), brick (rows per
         brick in use), spread (launch-order chunk log2, 0 = memory order),
         odd_rows (1 if the odd step walks rows), cached (1 if taken from the
-        process's cache of earlier results for this grid, store and boundary)."""
-        t = (C.c_int32 * 7)()
+        process's cache of earlier results for this grid, store and boundary),
+        xcd_chunk (log2 of the consecutive tiles each XCD takes in turn)."""
+        t = (C.c_int32 * 8)()
         self._chk(self.lib.lbm_autotune(self._h, int(steps), t))
-        keys = ("tile_odd", "tile_even", "vector", "brick", "spread", "odd_rows", "cached")
+        keys = ("tile_odd", "tile_even", "vector", "brick", "spread", "odd_rows", "cached", "xcd_chunk")
         self.tiles = (t[0], t[1], t[2])
         return dict(zip(keys, list(t)))
 

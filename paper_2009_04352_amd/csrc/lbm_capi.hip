@@ -92,6 +92,7 @@ struct lbm_ctx {
     int bc = kWFB;
     int stats_every = 0;
     int tile_odd = 256, tile_even = 256, xcd_remap = 1, graph_steps = 32;
+    int xcd_chunk = kXcdChunkLog2;   // log2 of the consecutive tiles each XCD takes in turn (LBM_P_XCD_CHUNK)
     int vw_req = 0;              // cells per thread requested; 0 = automatic (auto_vector_width)
     int brick_req = 0;           // rows per brick of the population layout requested; 0 = automatic
     int brick = 0;               // rows per brick in use; fixed while the state is initialised
@@ -315,7 +316,7 @@ StepArgs step_args(const lbm_ctx* c, bool odd, int rows_mode)
         step_geometry(c->nx, c->ny, c->nz, odd ? c->tile_odd : c->tile_even, vector_width(c), brick_rows(c), a);
     a.tile_begin = 0;
     a.bc = c->bc;
-    a.xcd_remap = c->xcd_remap ? kXcdChunkLog2 + 1 : 0;
+    a.xcd_remap = c->xcd_remap ? c->xcd_chunk + 1 : 0;
     set_spread(a, spread_log2(c));
     a.newton_maxit = c->newton_maxit;
     a.tau0 = c->tau0;
@@ -643,6 +644,10 @@ int lbm_set_param(lbm_ctx* c, int key, double v)
                 if (v != 0.0 && v != 1.0) return fail(c, LBM_E_ARG, "XCD remap is 0 or 1");
                 c->xcd_remap = (int)v;
                 break;
+            case LBM_P_XCD_CHUNK:
+                if (!integral || v < 0 || v > 12) return fail(c, LBM_E_ARG, "XCD chunk is a tile-count log2 in [0, 12]");
+                c->xcd_chunk = (int)v;
+                break;
             case LBM_P_VECTOR: {
                 if (!integral || (v != 0.0 && !step_vector_width_ok(c->store, c->nx, (int)v)))
                     return fail(c, LBM_E_ARG, "cells per thread must be 0 (auto) or 1, 2, 4 with groups of at most 8 bytes dividing nx");
@@ -737,6 +742,7 @@ int lbm_get_param(const lbm_ctx* c, int key, double* v)
             case LBM_P_TILE_ODD: *v = c->tile_odd; break;
             case LBM_P_TILE_EVEN: *v = c->tile_even; break;
             case LBM_P_XCD_REMAP: *v = c->xcd_remap; break;
+            case LBM_P_XCD_CHUNK: *v = c->xcd_chunk; break;
             case LBM_P_VECTOR: *v = vector_width(c); break;
             case LBM_P_BRICK: *v = brick_rows(c); break;
             case LBM_P_ODD_ROWS: *v = c->odd_rows; break;
@@ -1451,13 +1457,14 @@ namespace {
 
 // Launch shapes of a single channel: block sizes of the odd and even kernels,
 // cells per thread, rows per brick requested (0 = automatic), launch order
-// (LBM_P_SPREAD) and the odd-step mode (LBM_P_ODD_ROWS).
+// (LBM_P_SPREAD), the odd-step mode (LBM_P_ODD_ROWS) and the XCD chunk
+// (LBM_P_XCD_CHUNK).
 struct Shapes {
-    int tile_odd, tile_even, vw, brick, spread, odd_rows;
+    int tile_odd, tile_even, vw, brick, spread, odd_rows, xcd;
     bool operator==(const Shapes& o) const
     {
-        return std::tie(tile_odd, tile_even, vw, brick, spread, odd_rows) ==
-               std::tie(o.tile_odd, o.tile_even, o.vw, o.brick, o.spread, o.odd_rows);
+        return std::tie(tile_odd, tile_even, vw, brick, spread, odd_rows, xcd) ==
+               std::tie(o.tile_odd, o.tile_even, o.vw, o.brick, o.spread, o.odd_rows, o.xcd);
     }
 };
 
@@ -1476,7 +1483,7 @@ std::map<TuneKey, Shapes> g_tune_cache;
 
 Shapes shapes_of(const lbm_ctx* c)
 {
-    return Shapes{c->tile_odd, c->tile_even, vector_width(c), c->brick_req, spread_log2(c), c->odd_rows};
+    return Shapes{c->tile_odd, c->tile_even, vector_width(c), c->brick_req, spread_log2(c), c->odd_rows, c->xcd_chunk};
 }
 
 void apply_shapes(lbm_ctx* c, const Shapes& v)
@@ -1487,6 +1494,7 @@ void apply_shapes(lbm_ctx* c, const Shapes& v)
     c->brick_req = v.brick;
     c->spread = v.spread;
     c->odd_rows = v.odd_rows;
+    c->xcd_chunk = v.xcd;
 }
 
 // What the odd and even launches of shapes v look like (geometry, order and
@@ -1500,7 +1508,7 @@ std::vector<long long> launch_signature(lbm_ctx* c, const Shapes& v)
         const StepArgs a = step_args(c, odd, c->odd_rows);
         for (long long x : {(long long)a.brick, (long long)a.spread, (long long)a.spread_rot, (long long)a.nseg,
                             (long long)a.tile_x, (long long)a.vw, (long long)a.ntx, (long long)a.rpb,
-                            (long long)a.nyt, (long long)a.ntiles})
+                            (long long)a.nyt, (long long)a.ntiles, (long long)a.xcd_remap})
             sig.push_back(x);
     }
     apply_shapes(c, keep);
@@ -1533,6 +1541,7 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
                 out[4] = v.spread;
                 out[5] = odd_by_rows(c, v.odd_rows) ? 1 : 0;
                 out[6] = cached ? 1 : 0;
+                out[7] = v.xcd;
             }
         };
         {
@@ -1596,6 +1605,7 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
         const int widths[3] = {1, 2, 4};
         const int bricks[4] = {4, 8, 16, 32};
         const int spreads[4] = {0, 5, 7, 9};
+        const int xcd_chunks[3] = {5, 7, 9};
         enum Criterion { kPair, kOdd, kEven };
         auto consider = [&](Shapes v, Criterion j) -> bool {
             if (!ok || same_launch(c, v, best)) return false;
@@ -1648,6 +1658,11 @@ int lbm_autotune(lbm_ctx* c, int steps, int32_t* out)
             for (int sp : spreads) {
                 Shapes v = best;
                 v.spread = sp;
+                changed |= consider(v, kPair);
+            }
+            for (int xc : xcd_chunks) {
+                Shapes v = best;
+                v.xcd = xc;
                 changed |= consider(v, kPair);
             }
             if (!changed) break;

@@ -264,3 +264,40 @@ def test_empty_inputs_are_no_ops_or_refused(L):
     bc = (C.c_int32 * 1)(1)
     assert lib.lbm_batch_create(0, C.byref(g), one, one, one, bc, 0.41, 5.5, C.byref(b)) == L.LBM_E_ARG
     assert not b.value
+
+
+def test_binding_constants_match_the_header(L):
+    """Every status code, store, boundary and parameter key of the header has
+    the same value in the Python binding."""
+    text = open(os.path.join(ROOT, "include", "lbmwf.h")).read()
+    defs = re.findall(r"^#define (LBM_(?:P|E|STORE|BB|WFB|FREESLIP|BGK|MRT|OK)\w*)\s+\(?(-?\d+)\)?", text, re.M)
+    assert len(defs) > 30
+    for name, value in defs:
+        assert getattr(L, name) == int(value), name
+
+
+def test_xcd_chunk_parameter(L):
+    """The XCD chunk (log2 of the consecutive tiles each XCD takes in turn) is
+    an integer in [0, 12], default 5; batches keep theirs."""
+    lib = L.lib()
+    h = C.c_void_p()
+    assert lib.lbm_create(C.byref(L.Grid(64, 6, 4)), 0.6, 0.1, 0.41, 5.5, 0.0, C.byref(h)) == 0
+    try:
+        v = C.c_double()
+        assert lib.lbm_get_param(h, L.LBM_P_XCD_CHUNK, C.byref(v)) == 0 and v.value == 5.0
+        for ok in (0, 7, 12):
+            assert lib.lbm_set_param(h, L.LBM_P_XCD_CHUNK, ok) == 0
+            assert lib.lbm_get_param(h, L.LBM_P_XCD_CHUNK, C.byref(v)) == 0 and v.value == ok
+        for bad in (-1, 13, 2.5):
+            assert lib.lbm_set_param(h, L.LBM_P_XCD_CHUNK, bad) == L.LBM_E_ARG
+    finally:
+        lib.lbm_destroy(h)
+    b = C.c_void_p()
+    g = (L.Grid * 1)(L.Grid(8, 4, 2))
+    one = (C.c_double * 1)(0.6)
+    bc = (C.c_int32 * 1)(1)
+    assert lib.lbm_batch_create(1, g, one, one, one, bc, 0.41, 5.5, C.byref(b)) == 0
+    try:
+        assert lib.lbm_batch_set_param(b, L.LBM_P_XCD_CHUNK, 7) == L.LBM_E_ARG
+    finally:
+        lib.lbm_batch_destroy(b)

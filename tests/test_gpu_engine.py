@@ -43,16 +43,18 @@ def test_block_size_and_remap_invariance(P, orc, store):
     grid = (200, 7, 6)
     h0 = _state(orc, grid, store, 2)
     ref = None
+    from paper_2009_04352_amd import _lib as L
     for tiles in ((64, 64), (128, 256), (256, 512), (512, 128)):
-        for remap in (0, 1):
+        for remap, chunk in ((0, 5), (1, 5), (1, 0), (1, 2), (1, 9)):
             ch = P.Channel(*grid, 0.505, cs=0.1, fx=1e-6, store=store, bc="wfb", tiles=tiles)
-            ch.set_param(7, remap)
+            ch.set_param(L.LBM_P_XCD_REMAP, remap)
+            ch.set_param(L.LBM_P_XCD_CHUNK, chunk)
             ch.set_state(h0)
             ch.step(9)
             s = ch.get_state()
             if ref is None:
                 ref = s
-            assert np.array_equal(s, ref), (tiles, remap)
+            assert np.array_equal(s, ref), (tiles, remap, chunk)
 
 
 def test_autotune_picks_valid_shapes_and_caches_them(P):
@@ -66,9 +68,10 @@ def test_autotune_picks_valid_shapes_and_caches_them(P):
     assert t["cached"] == 0
     assert t["tile_odd"] in (64, 128, 256, 512) and t["tile_even"] in (64, 128, 256, 512)
     assert t["vector"] in (1, 2) and t["spread"] in (0, 5, 7, 9) and t["odd_rows"] in (0, 1)
-    assert 1 <= t["brick"] <= grid[1]
+    assert 1 <= t["brick"] <= grid[1] and t["xcd_chunk"] in (5, 7, 9)
     for key, name in ((L.LBM_P_TILE_ODD, "tile_odd"), (L.LBM_P_TILE_EVEN, "tile_even"), (L.LBM_P_VECTOR, "vector"),
-                      (L.LBM_P_BRICK, "brick"), (L.LBM_P_SPREAD, "spread"), (L.LBM_P_ODD_BY_ROWS, "odd_rows")):
+                      (L.LBM_P_BRICK, "brick"), (L.LBM_P_SPREAD, "spread"), (L.LBM_P_ODD_BY_ROWS, "odd_rows"),
+                      (L.LBM_P_XCD_CHUNK, "xcd_chunk")):
         assert ch.get_param(key) == t[name], name
     again = P.Channel(*grid, 0.51, fx=1e-6, store="f32", bc="wfb")
     t2 = again.autotune(steps=4)
