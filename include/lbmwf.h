@@ -67,7 +67,8 @@ extern "C" {
 #define LBM_P_STORE 4         /* LBM_STORE_*; settable only before lbm_bind_storage (default F64) */
 #define LBM_P_TILE_ODD 5      /* threads per block of the odd-step kernel: 64, 128, 256 or 512 */
 #define LBM_P_TILE_EVEN 6     /* threads per block of the even-step kernel */
-#define LBM_P_XCD_REMAP 7     /* 1: the 8 XCDs take chunks of 32 consecutive tiles in turn (default), 0: identity */
+#define LBM_P_XCD_REMAP 7     /* 1: the 8 XCDs take chunks of consecutive tiles in turn (default; the chunk is
+                               * LBM_P_XCD_CHUNK, 32 tiles by default), 0: identity */
 #define LBM_P_GRAPH_STEPS 8   /* steps per captured HIP graph chunk; 0 = launch eagerly (default 32) */
 #define LBM_P_BC 9            /* read-only here: the current boundary */
 #define LBM_P_TAU0 10         /* read-only: molecular relaxation time */
