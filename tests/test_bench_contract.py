@@ -58,3 +58,25 @@ def test_traffic_used_only_for_its_kernel_sources(tmp_path, monkeypatch):
     # a summary taken on other sources is ignored
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
     assert bench.measured_traffic("c3", "f16", "odd") is None
+
+
+def test_roofline_is_algorithmic_bytes_over_the_dominant_kernel_time():
+    """The line's roofline object: the dominant (slower) kernel's algorithmic
+    bytes (38 x cells x store bytes) over its measured time, against the
+    8 TB/s HBM peak; traffic only from the BGK counter records."""
+    import bench
+    n = 2048 * 512 * 1024
+    r = dict(mlups=20000.0, ms_per_step=52.0, odd_kernel_ms=52.5, even_kernel_ms=51.0, status=0)
+    d = bench.store_record(r, "f64", n, 6500.0)
+    assert d["dominant_kernel"] == "odd" and d["bytes_per_cell"] == 38 * 8
+    roof = bench.roofline(d, "f64", n, "c5")
+    want = 38 * 8 * n / 52.5e-3 / 1e9
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+    assert abs(roof["achieved"] - want) <= 1e-9 * want and abs(roof["frac"] - want / 8000.0) <= 1e-12
+    assert roof["algorithmic_bytes_per_launch"] == 38 * 8 * n and roof["kernel_ms"] == 52.5
+    assert abs(d["copy_frac"] - want / 6500.0) <= 1e-12
+    # the even kernel dominates when it is the slower one; MRT runs report no traffic
+    r2 = dict(r, odd_kernel_ms=50.0)
+    d2 = bench.store_record(r2, "f16", n, None)
+    assert d2["dominant_kernel"] == "even" and "copy_frac" not in d2
+    assert bench.roofline(d2, "f16", n, "c5", collision="mrt")["traffic"] is None
