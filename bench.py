@@ -64,9 +64,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, store, kernel):
+def measured_traffic(workload, store, kernel, name=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on the current kernel source and (name given) for the same
+    kernel ("k_step" or "k_odd_rows"); else None."""
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
@@ -75,7 +76,9 @@ def measured_traffic(workload, store, kernel):
     if t.get("kernel_source") != kernel_source_hash():
         return None
     rec = t.get("stores", {}).get(store, {}).get(kernel)
-    return rec.get("bytes_per_launch") if rec else None
+    if not rec or (name is not None and rec.get("kernel") != name):
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def timed_steps(torch, stepper, stream, steps, warmup, first_step):
@@ -270,7 +273,8 @@ def cpu_baseline(W, name, coll, budget_s=20.0, budget_1core_s=8.0):
 def roofline(per, kernel_key, n_cells, workload, collision="bgk"):
     kern = per["dominant_kernel"]
     # the committed counter summaries were taken with the BGK kernels
-    traffic = measured_traffic(workload, kernel_key, kern) if collision == "bgk" else None
+    name = "k_odd_rows" if (kern == "odd" and per.get("odd_by_rows")) else "k_step"
+    traffic = measured_traffic(workload, kernel_key, kern, name) if collision == "bgk" else None
     r = dict(bound="hbm", achieved=per["kernel_gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
              frac=per["kernel_gbs"] / HBM_PEAK_GBS, traffic=traffic,
              kernel=(("k_odd_rows odd (one wavefront per row; pull/push with wall reflections)"

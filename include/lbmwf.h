@@ -81,7 +81,7 @@ extern "C" {
                                * gives the height in use.  Results do not depend on it. */
 #define LBM_P_ODD_ROWS 15     /* odd-step kernel: 0 = blocks of rows or row segments exchanging through LDS;
                                * 1 = (default) one wavefront per row walking it in 64-lane segments, for FP16/BF16
-                               * stores whose rows are longer than an odd-step block; 2 = walk rows whenever nx is a
+                               * and FP64 stores whose rows are longer than an odd-step block; 2 = walk rows whenever nx is a
                                * multiple of 64 cells
                                * per thread.  Results do not depend on it (statistics sums up to summation order). */
 #define LBM_P_SPREAD 16       /* launch order: c in [5, 16] = chunks of 2^c tiles cycle through the bricks of the

@@ -279,15 +279,18 @@ struct TimingEvents {
 };
 
 // Whether the odd step walks rows (one wavefront per row) for these shapes.
-// Automatic (mode 1): for 2-byte stores whose rows are longer than an odd-step
-// block, where it beat row segments exchanging through LDS (5 % on the
-// 2048 x 512 x 1024 channel in FP16); for FP32/FP64 and short rows the block
-// kernel was as fast or faster.
+// Automatic (mode 1): for 2-byte and 8-byte stores whose rows are longer than
+// an odd-step block.  On the 2048 x 512 x 1024 channel the walk beat row
+// segments exchanging through LDS by 5 % in FP16; in FP64 it runs as fast as
+// the blocks' direct shifted loads (52.3 against 52.4 ms) and writes every
+// 128-byte line once, where the blocks' shifted segment-edge stores wrote
+// 0.6 % more.  FP32 and short rows keep the blocks (as fast or faster).
 bool odd_by_rows(const lbm_ctx* c, int mode)
 {
     const int vw = vector_width(c);
     if (mode == 0 || c->wall_nodes || !rows_ok(c->nx, vw)) return false;
-    return mode == 2 || (store_bytes(c->store) == 2 && c->nx / vw > c->tile_odd);
+    const int bytes = store_bytes(c->store);
+    return mode == 2 || ((bytes == 2 || bytes == 8) && c->nx / vw > c->tile_odd);
 }
 
 // Chunk size of the brick-spreading launch order (LBM_P_SPREAD = -1): the

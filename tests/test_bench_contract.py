@@ -53,6 +53,10 @@ def test_traffic_used_only_for_its_kernel_sources(tmp_path, monkeypatch):
         if t["kernel_source"] == h:
             rec = t["stores"]["f16"]["odd"]
             assert bench.measured_traffic(wl, "f16", "odd") == rec["bytes_per_launch"]
+            assert bench.measured_traffic(wl, "f16", "odd", rec["kernel"]) == rec["bytes_per_launch"]
+            # a record of the other odd kernel is not used for this one
+            other = "k_step" if rec["kernel"] == "k_odd_rows" else "k_odd_rows"
+            assert bench.measured_traffic(wl, "f16", "odd", other) is None
             # a traffic figure within 3 % of the algorithmic bytes: no re-reads
             assert abs(rec["bytes_per_launch"] / rec["algorithmic"] - 1.0) <= 0.03
     # a summary taken on other sources is ignored

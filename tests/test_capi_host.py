@@ -118,12 +118,13 @@ def test_spread_parameter(L):
 
 def test_odd_kernel_choice_reads_back(L):
     """LBM_P_ODD_BY_ROWS reports the odd kernel the settings select: rows are
-    walked for 2-byte stores whose rows are longer than an odd-step block
-    (mode 1), always where nx allows (mode 2), never in mode 0; read only."""
+    walked for 2-byte and 8-byte stores whose rows are longer than an odd-step
+    block (mode 1), always where nx allows (mode 2), never in mode 0; read only."""
     lib = L.lib()
     v = C.c_double()
     cases = [  # nx, store, odd block, mode, walks rows
-        (2048, L.LBM_STORE_F16, 128, 1, 1), (512, L.LBM_STORE_F16, 128, 1, 0), (2048, L.LBM_STORE_F64, 256, 1, 0),
+        (2048, L.LBM_STORE_F16, 128, 1, 1), (512, L.LBM_STORE_F16, 128, 1, 0), (2048, L.LBM_STORE_F64, 256, 1, 1),
+        (512, L.LBM_STORE_F64, 512, 1, 0), (2048, L.LBM_STORE_F32, 256, 1, 0), (2048, L.LBM_STORE_F32, 256, 2, 1),
         (2048, L.LBM_STORE_F64, 256, 2, 1), (2048, L.LBM_STORE_F16, 128, 0, 0), (96, L.LBM_STORE_F16, 64, 2, 0)]
     for nx, store, tile, mode, want in cases:
         h = C.c_void_p()
